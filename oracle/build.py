@@ -1,0 +1,26 @@
+"""Build step for the CPU oracle (test infrastructure, not part of the product).
+
+Compiles oracle_gemm.c with gcc into liboracle.so beside this file.  The flags
+keep every multiply and add separately rounded (-ffp-contract=off) so the
+library computes exactly the expressions written in the C source.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle_gemm.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", LIB + ".tmp", SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,219 @@
+/*
+ * CPU oracle for C := alpha*A*B + beta*C — TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load this file's library.  The product path (the HIP library) never links,
+ * calls or shares code with it.
+ *
+ * All matrices are column-major: element (i,j) of X is X[i + j*ldX].
+ * Built with -O2 -fopenmp -ffp-contract=off so that every multiply and every
+ * add is rounded separately, exactly as written below.
+ *
+ *   oracle_dgemm     — the definition of Sec. 2.1 ("Computing C = alpha A B + C"),
+ *                      with the BLAS beta of Sec. 2.2: each c_ij is alpha times the
+ *                      sum over p of a_ip*b_pj, summed in increasing p, plus beta*c_ij.
+ *   oracle_strassen  — classic recursive Strassen (Sec. 3.2), each level being the
+ *                      seven operations of Fig. "All operations for one-level
+ *                      Strassen" (Sec. 3.1) written out with explicit temporaries.
+ *                      Odd dimensions are zero-padded to even at every level, the
+ *                      traditional treatment of fringes that Sec. 3.3 mentions.
+ *                      The base case is oracle_dgemm's summation.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* S := X*Y (overwrite), the plain definition; loops ordered j, p, i so that the
+ * sum for each (i,j) is still accumulated in increasing p. */
+static void plain_product(int64_t m, int64_t n, int64_t k,
+                          const double *X, int64_t ldx,
+                          const double *Y, int64_t ldy,
+                          double *S, int64_t lds)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        double *s = S + j * lds;
+        for (int64_t i = 0; i < m; ++i) s[i] = 0.0;
+        for (int64_t p = 0; p < k; ++p) {
+            const double y = Y[p + j * ldy];
+            const double *x = X + p * ldx;
+            for (int64_t i = 0; i < m; ++i) s[i] = s[i] + x[i] * y;
+        }
+    }
+}
+
+/* C := alpha*S + beta*C; beta == 0 means C is not read (BLAS convention). */
+static void scale_add(int64_t m, int64_t n, double alpha, const double *S, int64_t lds,
+                      double beta, double *C, int64_t ldc)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            const double t = alpha * S[i + j * lds];
+            C[i + j * ldc] = (beta == 0.0) ? t : t + beta * C[i + j * ldc];
+        }
+}
+
+int oracle_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double beta, double *C, int64_t ldc)
+{
+    if (m <= 0 || n <= 0) return 0;
+    double *S = (double *)calloc((size_t)m * (size_t)n, sizeof(double));
+    if (!S) return 1;
+    /* BLAS: with alpha == 0 or k == 0, A and B are not referenced. */
+    if (k > 0 && alpha != 0.0) plain_product(m, n, k, A, lda, B, ldb, S, m);
+    scale_add(m, n, alpha, S, m, beta, C, ldc);
+    free(S);
+    return 0;
+}
+
+/* ---- recursive Strassen ------------------------------------------------ */
+
+/* Copy quadrant (bi,bj) of the rows x cols matrix X into the h x w buffer Q,
+ * filling positions that fall outside X with zeros. */
+static void get_quadrant(const double *X, int64_t ldx, int64_t rows, int64_t cols,
+                         int bi, int bj, int64_t h, int64_t w, double *Q)
+{
+    for (int64_t j = 0; j < w; ++j)
+        for (int64_t i = 0; i < h; ++i) {
+            const int64_t r = bi * h + i, c = bj * w + j;
+            Q[i + j * h] = (r < rows && c < cols) ? X[r + c * ldx] : 0.0;
+        }
+}
+
+static void add_into(int64_t len, const double *X, double sx, const double *Y, double sy, double *Z)
+{
+    for (int64_t e = 0; e < len; ++e) Z[e] = sx * X[e] + sy * Y[e];
+}
+
+static void accumulate(int64_t len, double *Z, double s, const double *M)
+{
+    for (int64_t e = 0; e < len; ++e) Z[e] = Z[e] + s * M[e];
+}
+
+/* P := X*Y (overwrite) for X m x k, Y k x n, P m x n (ld = m), using `levels`
+ * levels of Strassen and the plain product below them. */
+static int strassen_product(int64_t m, int64_t n, int64_t k,
+                            const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                            double *P, int levels)
+{
+    if (levels == 0) { plain_product(m, n, k, X, ldx, Y, ldy, P, m); return 0; }
+    /* one level: h = ceil(m/2), w = ceil(n/2), d = ceil(k/2) */
+    const int64_t h = (m + 1) / 2, w = (n + 1) / 2, d = (k + 1) / 2;
+    const int64_t sa = h * d, sb = d * w, sc = h * w;
+    double *buf = (double *)calloc((size_t)(4 * sa + 4 * sb + 2 * sa + 2 * sb + 5 * sc), sizeof(double));
+    if (!buf) return 1;
+    double *A00 = buf, *A01 = A00 + sa, *A10 = A01 + sa, *A11 = A10 + sa;
+    double *B00 = A11 + sa, *B01 = B00 + sb, *B10 = B01 + sb, *B11 = B10 + sb;
+    double *TA = B11 + sb, *TA2 = TA + sa, *TB = TA2 + sa, *TB2 = TB + sb;
+    double *M = TB2 + sb, *C00 = M + sc, *C01 = C00 + sc, *C10 = C01 + sc, *C11 = C10 + sc;
+    (void)TA2; (void)TB2;
+    get_quadrant(X, ldx, m, k, 0, 0, h, d, A00);
+    get_quadrant(X, ldx, m, k, 0, 1, h, d, A01);
+    get_quadrant(X, ldx, m, k, 1, 0, h, d, A10);
+    get_quadrant(X, ldx, m, k, 1, 1, h, d, A11);
+    get_quadrant(Y, ldy, k, n, 0, 0, d, w, B00);
+    get_quadrant(Y, ldy, k, n, 0, 1, d, w, B01);
+    get_quadrant(Y, ldy, k, n, 1, 0, d, w, B10);
+    get_quadrant(Y, ldy, k, n, 1, 1, d, w, B11);
+    int rc = 0;
+    /* M0 = (A00 + A11)(B00 + B11);  C00 += M0; C11 += M0 */
+    add_into(sa, A00, 1, A11, 1, TA); add_into(sb, B00, 1, B11, 1, TB);
+    rc |= strassen_product(h, w, d, TA, h, TB, d, M, levels - 1);
+    accumulate(sc, C00, 1, M); accumulate(sc, C11, 1, M);
+    /* M1 = (A10 + A11) B00;  C10 += M1; C11 -= M1 */
+    add_into(sa, A10, 1, A11, 1, TA);
+    rc |= strassen_product(h, w, d, TA, h, B00, d, M, levels - 1);
+    accumulate(sc, C10, 1, M); accumulate(sc, C11, -1, M);
+    /* M2 = A00 (B01 - B11);  C01 += M2; C11 += M2 */
+    add_into(sb, B01, 1, B11, -1, TB);
+    rc |= strassen_product(h, w, d, A00, h, TB, d, M, levels - 1);
+    accumulate(sc, C01, 1, M); accumulate(sc, C11, 1, M);
+    /* M3 = A11 (B10 - B00);  C00 += M3; C10 += M3 */
+    add_into(sb, B10, 1, B00, -1, TB);
+    rc |= strassen_product(h, w, d, A11, h, TB, d, M, levels - 1);
+    accumulate(sc, C00, 1, M); accumulate(sc, C10, 1, M);
+    /* M4 = (A00 + A01) B11;  C01 += M4; C00 -= M4 */
+    add_into(sa, A00, 1, A01, 1, TA);
+    rc |= strassen_product(h, w, d, TA, h, B11, d, M, levels - 1);
+    accumulate(sc, C01, 1, M); accumulate(sc, C00, -1, M);
+    /* M5 = (A10 - A00)(B00 + B01);  C11 += M5 */
+    add_into(sa, A10, 1, A00, -1, TA); add_into(sb, B00, 1, B01, 1, TB);
+    rc |= strassen_product(h, w, d, TA, h, TB, d, M, levels - 1);
+    accumulate(sc, C11, 1, M);
+    /* M6 = (A01 - A11)(B10 + B11);  C00 += M6 */
+    add_into(sa, A01, 1, A11, -1, TA); add_into(sb, B10, 1, B11, 1, TB);
+    rc |= strassen_product(h, w, d, TA, h, TB, d, M, levels - 1);
+    accumulate(sc, C00, 1, M);
+    /* P = [C00 C01; C10 C11], dropping the zero padding */
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            const double *Q = (i < h) ? (j < w ? C00 : C01) : (j < w ? C10 : C11);
+            P[i + j * m] = Q[(i % h) + (j % w) * h];
+        }
+    free(buf);
+    return rc;
+}
+
+int oracle_strassen(int64_t m, int64_t n, int64_t k, double alpha,
+                    const double *A, int64_t lda, const double *B, int64_t ldb,
+                    double beta, double *C, int64_t ldc, int levels)
+{
+    if (m <= 0 || n <= 0) return 0;
+    if (levels < 0) return -12;
+    double *P = (double *)calloc((size_t)m * (size_t)n, sizeof(double));
+    if (!P) return 1;
+    int rc = 0;
+    if (k > 0 && alpha != 0.0) rc = strassen_product(m, n, k, A, lda, B, ldb, P, levels);
+    scale_add(m, n, alpha, P, m, beta, C, ldc);
+    free(P);
+    return rc;
+}
+
+/* Compensated dot products (Ogita, Rump and Oishi's Dot2: TwoProduct by
+ * Dekker splitting, TwoSum by Knuth), used only to measure how far a result
+ * lies from the exact product at small sizes.  C := alpha*A*B + beta*C with
+ * the sum over p carried in twice the working precision. */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    const double x = a + b, z = x - a;
+    *s = x;
+    *e = (a - (x - z)) + (b - z);
+}
+static void split(double a, double *hi, double *lo)
+{
+    const double c = 134217729.0 * a; /* 2^27 + 1 */
+    const double h = c - (c - a);
+    *hi = h;
+    *lo = a - h;
+}
+static void two_prod(double a, double b, double *p, double *e)
+{
+    double ah, al, bh, bl;
+    const double x = a * b;
+    split(a, &ah, &al);
+    split(b, &bh, &bl);
+    *p = x;
+    *e = al * bl - (((x - ah * bh) - al * bh) - ah * bl);
+}
+
+int oracle_dgemm_dot2(int64_t m, int64_t n, int64_t k, double alpha,
+                      const double *A, int64_t lda, const double *B, int64_t ldb,
+                      double beta, double *C, int64_t ldc)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            double s = 0.0, c = 0.0;
+            for (int64_t p = 0; p < k; ++p) {
+                double h, r, q;
+                two_prod(A[i + p * lda], B[p + j * ldb], &h, &r);
+                two_sum(s, h, &s, &q);
+                c = c + (q + r);
+            }
+            const double t = alpha * (s + c);
+            C[i + j * ldc] = (beta == 0.0) ? t : t + beta * C[i + j * ldc];
+        }
+    return 0;
+}
