@@ -1,0 +1,158 @@
+/*
+ * strassen.h — one- and two-level Strassen matrix multiplication on AMD MI355X (gfx950).
+ *
+ * Implements the family of practical Strassen implementations of Huang, Smith, Henry and
+ * van de Geijn, "Implementing Strassen's Algorithm with BLIS" (arXiv 1605.01078):
+ *
+ *   C := alpha * A * B + beta * C                                 (Sec. 2.1, Sec. 2.2)
+ *
+ * computed with `levels` levels of Strassen, each product being the general operation
+ *
+ *   M = (sum_s delta_s X_s)(sum_t eps_t V_t);   C_r += alpha * gamma_r * M    (eq. e:straprim4)
+ *
+ * over the sub-blocks of the 2^L x 2^L partition of A, B and C given by the one-level table
+ * (Fig. "All operations for one-level Strassen") and the two-level table (Fig. "Computations
+ * for two-level Strassen", built as the Kronecker composition of the one-level table, Sec. 3.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Column-major storage: element (i,j) of X is X[i + j*ldX].  A is m x k (lda >= max(1,m)),
+ *    B is k x n (ldb >= max(1,k)), C is m x n (ldc >= max(1,m)).  No transposes.
+ *  - A, B, C are DEVICE pointers owned by the caller.  The library never frees or retains
+ *    them.  A and B are only read.  C must not overlap A or B.
+ *  - Dimensions that are not multiples of 2^L are handled inside the kernels: every sub-block
+ *    has ceil(m/2^L) x ceil(k/2^L) (etc.) elements, positions past the matrix read as zero
+ *    and are never written (Sec. 3.3, "Practical considerations", fringes).
+ *  - beta is applied once to every element of C, at the first update that touches it; with
+ *    beta == 0 C is write-only (NaN/Inf already in C do not propagate), as in BLAS.
+ *  - alpha == 0 or k == 0: A and B are not read; C := beta*C (nothing at all when beta == 1).
+ *    m == 0 or n == 0: nothing is done.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work and return;
+ *    errors that can be detected on the host are reported on return, kernel faults surface
+ *    at the next synchronisation.  Calls on one stream execute in order.
+ *  - Return value: 0 on success; -i when the i-th argument (1-based) is invalid (nothing is
+ *    enqueued and C is untouched); a positive STRASSEN_ERR_* code for runtime failures.
+ *    strassen_last_error() gives a message for the calling thread's last failure.
+ *  - Results are deterministic: the same call on the same data gives bitwise identical C.
+ *    For a given number of levels the three variants give bitwise identical C.
+ */
+#ifndef STRASSEN_MI355X_H
+#define STRASSEN_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Variants of Sec. 4.1 ("Variations on a theme"). */
+enum strassen_variant {
+    STRASSEN_ABC = 0,   /* sums formed in the operand load, products added to every C
+                           destination in the kernel epilogue; no workspace            */
+    STRASSEN_AB = 1,    /* sums formed in the operand load, products stored to explicit
+                           temporaries M_r, C assembled from them by a second kernel    */
+    STRASSEN_NAIVE = 2  /* explicit operand-sum temporaries, plain GEMM on them, then
+                           the same C assembly as AB                                    */
+};
+
+/* Runtime error codes (positive). */
+enum strassen_error {
+    STRASSEN_OK = 0,
+    STRASSEN_ERR_HIP = 1,        /* a HIP runtime call failed (message has the HIP error)  */
+    STRASSEN_ERR_ALLOC = 2,      /* workspace allocation failed / caller workspace too small */
+    STRASSEN_ERR_UNSUPPORTED = 3,/* valid arguments the library cannot run (e.g. sizes past
+                                    the 32-bit tile grid)                                    */
+    STRASSEN_ERR_NO_DEVICE = 4   /* no gfx950 device is visible                            */
+};
+
+/* Precisions of the reduced-precision mode (strassen_gemm_ex). */
+enum strassen_compute {
+    STRASSEN_COMPUTE_F64 = 0,    /* FP64 products on FP64 MFMA (same as strassen_dgemm)     */
+    STRASSEN_COMPUTE_BF16 = 1,   /* operand sums rounded to bf16, FP32-accumulated MFMA     */
+    STRASSEN_COMPUTE_BF16X3 = 2  /* sums split x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
+                                    product hi*hi + hi*lo + lo*hi, FP32 accumulation        */
+};
+enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
+
+/*
+ * strassen_dgemm — C := alpha*A*B + beta*C with `levels` levels of Strassen.
+ *   levels : 0 (classical GEMM on FP64 MFMA, the effective-GFLOPS yardstick), 1 or 2.
+ *   variant: STRASSEN_ABC, STRASSEN_AB or STRASSEN_NAIVE (ignored when levels == 0).
+ * The general operation is eq. (e:straprim1) at one level and eq. (e:straprim3) at two.
+ * AB and NAIVE use a library-owned workspace (grown on demand, kept until
+ * strassen_release_workspace or process exit) unless strassen_set_workspace gave one;
+ * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 3.3).
+ * Argument positions for -i: m=1 n=2 k=3 alpha=4 A=5 lda=6 B=7 ldb=8 beta=9 C=10 ldc=11
+ * levels=12 variant=13.
+ */
+int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
+                   const double *A, int64_t lda, const double *B, int64_t ldb,
+                   double beta, double *C, int64_t ldc,
+                   int levels, int variant, void *stream);
+
+/*
+ * strassen_workspace_size — bytes of device workspace strassen_dgemm needs for these sizes
+ * (0 for ABC and for levels 0).  AB: one M_r temporary per product (7^L of
+ * ceil(m/2^L) x ceil(n/2^L) doubles); NAIVE adds the operand-sum temporaries.
+ * Returns 0 or -i as strassen_dgemm does for the same argument (m=1 n=2 k=3 levels=4
+ * variant=5 bytes=6).
+ */
+int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int variant,
+                            size_t *bytes);
+
+/*
+ * strassen_set_workspace — use caller-owned device memory [ptr, ptr+bytes) as workspace
+ * instead of the library's own (ptr must stay valid while calls that use it are in
+ * flight; 256-byte alignment required).  ptr == NULL returns to library-owned workspace.
+ * A call needing more than `bytes` fails with STRASSEN_ERR_ALLOC without touching C.
+ * Returns 0, -1 (misaligned ptr) or -2 (ptr != NULL with bytes == 0).
+ */
+int strassen_set_workspace(void *ptr, size_t bytes);
+
+/* strassen_release_workspace — synchronise the device and free the library-owned workspace. */
+int strassen_release_workspace(void);
+
+/*
+ * strassen_gemm_ex — the reduced-precision mode.  C (FP64) := alpha*A*B + beta*C where each
+ * product M_r runs on BF16 MFMA with FP32 accumulation (compute = STRASSEN_COMPUTE_BF16 or
+ * _BF16X3; _F64 forwards to strassen_dgemm).  A, B, C are FP64 as in strassen_dgemm.
+ *   sum_prec: precision in which the quadrant sums sum_s delta_s X_s are formed before the
+ *             rounding to bf16 (F32: every term is first rounded to FP32; F64: the sum is
+ *             formed in FP64 and rounded once to FP32).  Rounding is to nearest-even.
+ *   c_prec  : precision of the C update  c := c + alpha*gamma*M  (F32: c is rounded to FP32
+ *             before the first update of the call and each update is an FP32 operation;
+ *             F64: FP64 operations).  C is stored as FP64 either way.
+ * Only STRASSEN_ABC is offered (variant must be 0).  Argument positions as strassen_dgemm,
+ * then compute=14, sum_prec=15, c_prec=16.
+ */
+int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
+                     const double *A, int64_t lda, const double *B, int64_t ldb,
+                     double beta, double *C, int64_t ldc,
+                     int levels, int variant, int compute, int sum_prec, int c_prec,
+                     void *stream);
+
+/*
+ * Table introspection (host only, no device needed): the operation table the kernels execute.
+ * strassen_table_size returns the number of products for `levels` (1, 7, 49) or -1.
+ * strassen_table_get fills, for product r, the operand and destination terms as
+ * codes  sign * (1 + row_block + 2^L * col_block)  (sign = -1 for a subtraction) in
+ * a_terms[0..*na), b_terms[0..*nb), c_terms[0..*nc) (arrays of at least 8 entries).
+ * Returns 0, or -1 for levels out of range, -2 for r out of range.
+ */
+int strassen_table_size(int levels);
+int strassen_table_get(int levels, int r, int *na, int *a_terms, int *nb, int *b_terms,
+                       int *nc, int *c_terms);
+
+/* strassen_last_error — message describing the calling thread's most recent failure
+ * ("" if none).  The pointer stays valid until the next library call on this thread. */
+const char *strassen_last_error(void);
+
+/* strassen_version — library version string. */
+const char *strassen_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STRASSEN_MI355X_H */

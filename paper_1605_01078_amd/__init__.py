@@ -1,0 +1,246 @@
+"""Python binding of libstrassen.so: one- and two-level Strassen GEMM on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the library's HIP kernels.
+The library must have been built (``python -m paper_1605_01078_amd.build``); importing the
+functions below fails loudly if it is missing.  PyTorch supplies device memory and streams.
+
+Matrices are column-major.  A column-major m x k matrix with leading dimension ld is a torch
+tensor of shape (m, k) with strides (1, ld), e.g. ``torch.empty(k, ld).t()[:m]``;
+:func:`colmajor` and :func:`to_device` build such tensors.
+"""
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstrassen.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "strassen.h")
+
+ABC, AB, NAIVE = 0, 1, 2
+VARIANTS = {"abc": ABC, "ab": AB, "naive": NAIVE}
+COMPUTE = {"f64": 0, "bf16": 1, "bf16x3": 2}
+PREC = {"f32": 0, "f64": 1}
+
+_lib = None
+
+
+class StrassenError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"strassen error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """The loaded library (ctypes.CDLL); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1605_01078_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, dbl, vp, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+        gemm = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, ci, ci]
+        L.strassen_dgemm.argtypes = gemm + [vp]
+        L.strassen_dgemm.restype = ci
+        L.strassen_gemm_ex.argtypes = gemm + [ci, ci, ci, vp]
+        L.strassen_gemm_ex.restype = ci
+        L.strassen_workspace_size.argtypes = [i64, i64, i64, ci, ci, ctypes.POINTER(ctypes.c_size_t)]
+        L.strassen_workspace_size.restype = ci
+        L.strassen_set_workspace.argtypes = [vp, ctypes.c_size_t]
+        L.strassen_set_workspace.restype = ci
+        L.strassen_release_workspace.argtypes = []
+        L.strassen_release_workspace.restype = ci
+        L.strassen_table_size.argtypes = [ci]
+        L.strassen_table_size.restype = ci
+        ip = ctypes.POINTER(ci)
+        L.strassen_table_get.argtypes = [ci, ci, ip, ip, ip, ip, ip, ip]
+        L.strassen_table_get.restype = ci
+        L.strassen_last_error.argtypes = []
+        L.strassen_last_error.restype = ctypes.c_char_p
+        L.strassen_version.argtypes = []
+        L.strassen_version.restype = ctypes.c_char_p
+        _optional(L)
+        _lib = L
+    return _lib
+
+
+def _optional(L):
+    """Signatures of the batched-mode and selector entry points (present in full builds)."""
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp, ci, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    specs = {
+        "strassen_batched_plan": ([ci, i64p, i64p, i64p, ctypes.POINTER(ci), ctypes.POINTER(ci),
+                                   ctypes.POINTER(vp)], ci),
+        "strassen_batched_run": ([vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p,
+                                  ctypes.POINTER(vp), i64p, dbl, dbl, vp], ci),
+        "strassen_batched_capture": ([vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p,
+                                      ctypes.POINTER(vp), i64p, dbl, dbl, vp], ci),
+        "strassen_batched_replay": ([vp, vp], ci),
+        "strassen_batched_destroy": ([vp], ci),
+    }
+    for name, (args, res) in specs.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+
+
+def last_error():
+    return lib().strassen_last_error().decode()
+
+
+def version():
+    return lib().strassen_version().decode()
+
+
+def check(rc):
+    if rc != 0:
+        raise StrassenError(rc, last_error())
+    return rc
+
+
+def header_functions():
+    """Names of the functions include/strassen.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(strassen_[a-z0-9_]+)\s*\(", text)))
+
+
+# ---------------------------------------------------------------------------------------------
+# torch helpers
+# ---------------------------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(rows, cols, ld=None, device="cuda", dtype=None, fill=None):
+    """Empty (or filled) column-major rows x cols tensor with leading dimension ld."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    ld = rows if ld is None else ld
+    buf = torch.empty((cols, max(ld, 1)), dtype=dtype, device=device)
+    if fill is not None:
+        buf.fill_(fill)
+    return buf.t()[:rows, :]
+
+
+def to_device(X, ld=None, device="cuda", offset=0):
+    """Copy a 2-D numpy array into a column-major device tensor.  `offset` shifts the first
+    element by that many doubles inside the allocation (to test unaligned operands)."""
+    import numpy as np
+    torch = _torch()
+    X = np.asarray(X, dtype=np.float64)
+    rows, cols = X.shape
+    ld = rows if ld is None else ld
+    flat = torch.zeros(offset + max(ld, 1) * cols, dtype=torch.float64, device=device)
+    buf = flat[offset:].view(cols, max(ld, 1))
+    buf[:, :rows] = torch.from_numpy(np.ascontiguousarray(X.T)).to(device)
+    return buf.t()[:rows, :]
+
+
+def to_host(T):
+    """Column-major device tensor -> Fortran-order numpy array."""
+    return T.t().contiguous().cpu().numpy().T
+
+
+def _mat(T, name):
+    torch = _torch()
+    if T.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {T.dtype}")
+    if T.dim() != 2:
+        raise ValueError(f"{name}: expected a matrix")
+    rows, cols = T.shape
+    if rows > 1 and T.stride(0) != 1:
+        raise ValueError(f"{name}: rows must be contiguous (column-major); got strides {T.stride()}")
+    ld = T.stride(1)
+    if cols <= 1:
+        ld = max(ld, rows, 1)
+    return T.data_ptr() if T.numel() > 0 else None, rows, cols, ld
+
+
+def _stream(stream):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _variant(v):
+    return VARIANTS[v] if isinstance(v, str) else int(v)
+
+
+def dgemm(A, B, C, alpha=1.0, beta=1.0, levels=1, variant="abc", stream=None):
+    """C := alpha*A*B + beta*C in place with `levels` levels of Strassen (0 = classical).
+    A (m x k), B (k x n), C (m x n): float64 column-major device tensors."""
+    pa, m, k, lda = _mat(A, "A")
+    pb, k2, n, ldb = _mat(B, "B")
+    pc, m2, n2, ldc = _mat(C, "C")
+    if k2 != k or m2 != m or n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    check(lib().strassen_dgemm(m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc, int(levels),
+                               _variant(variant), _stream(stream)))
+    return C
+
+
+def gemm_ex(A, B, C, alpha=1.0, beta=1.0, levels=1, compute="bf16", sum_prec="f64",
+            c_prec="f64", variant="abc", stream=None):
+    """Reduced-precision mode: products on BF16 MFMA (compute 'bf16' or 'bf16x3') with FP32
+    accumulation, operand sums in `sum_prec`, C update in `c_prec`; A, B, C are FP64."""
+    pa, m, k, lda = _mat(A, "A")
+    pb, k2, n, ldb = _mat(B, "B")
+    pc, m2, n2, ldc = _mat(C, "C")
+    if k2 != k or m2 != m or n2 != n:
+        raise ValueError("shape mismatch")
+    check(lib().strassen_gemm_ex(m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc, int(levels),
+                                 _variant(variant), COMPUTE[compute], PREC[sum_prec], PREC[c_prec],
+                                 _stream(stream)))
+    return C
+
+
+def raw_dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, stream=None):
+    """Direct call with integer pointers; returns the library's status code (no raise)."""
+    return lib().strassen_dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant,
+                                stream)
+
+
+def workspace_size(m, n, k, levels, variant):
+    out = ctypes.c_size_t(0)
+    check(lib().strassen_workspace_size(m, n, k, levels, _variant(variant), ctypes.byref(out)))
+    return out.value
+
+
+def set_workspace(tensor_or_none):
+    """Use a caller-owned device buffer (a torch tensor, kept alive by the caller) as workspace;
+    None returns to the library's own."""
+    if tensor_or_none is None:
+        check(lib().strassen_set_workspace(None, 0))
+    else:
+        t = tensor_or_none
+        check(lib().strassen_set_workspace(t.data_ptr(), t.numel() * t.element_size()))
+
+
+def release_workspace():
+    check(lib().strassen_release_workspace())
+
+
+def table(levels):
+    """The operation table the kernels execute: list of (A terms, B terms, C terms), each term
+    ((row_block, col_block), sign)."""
+    L = lib()
+    nprod = L.strassen_table_size(levels)
+    if nprod < 0:
+        raise ValueError("levels out of range")
+    q = 2 ** levels
+    out = []
+    for r in range(nprod):
+        na, nb, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        a, b, c = (ctypes.c_int * 8)(), (ctypes.c_int * 8)(), (ctypes.c_int * 8)()
+        check(L.strassen_table_get(levels, r, ctypes.byref(na), a, ctypes.byref(nb), b,
+                                   ctypes.byref(nc), c))
+
+        def dec(v):
+            s = 1 if v > 0 else -1
+            v = abs(v) - 1
+            return ((v % q, v // q), s)
+        out.append(([dec(a[i]) for i in range(na.value)], [dec(b[i]) for i in range(nb.value)],
+                    [dec(c[i]) for i in range(nc.value)]))
+    return out

@@ -1,0 +1,477 @@
+// C-ABI of the Strassen library: argument checking, planning, workspace, launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/strassen.h"
+#include "launch.h"
+#include "plan.h"
+
+namespace smx {
+
+// ---------------------------------------------------------------------------------------------
+// Errors.
+// ---------------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return fail(STRASSEN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SMX_HIP(call)                                    \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return smx::hip_fail(e_, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Tables.
+// ---------------------------------------------------------------------------------------------
+static TableDev make_table_dev(int levels, bool naive) {
+  TableDev td;
+  std::memset(&td, 0, sizeof td);
+  const std::vector<Product> tab = build_table(levels);
+  const int q = 1 << levels;
+  td.nprod = (int32_t)tab.size();
+  td.q = q;
+  bool touched[16] = {false};
+  for (size_t r = 0; r < tab.size(); ++r) {
+    const Product& p = tab[r];
+    ProdDesc& d = td.prod[r];
+    d.na = (uint8_t)p.a.size();
+    d.nb = (uint8_t)p.b.size();
+    d.nc = (uint8_t)p.c.size();
+    for (size_t s = 0; s < p.a.size(); ++s) d.a[s] = term_code(p.a[s].row, p.a[s].col, p.a[s].sign);
+    for (size_t s = 0; s < p.b.size(); ++s) d.b[s] = term_code(p.b[s].row, p.b[s].col, p.b[s].sign);
+    for (size_t s = 0; s < p.c.size(); ++s) {
+      d.c[s] = term_code(p.c[s].row, p.c[s].col, p.c[s].sign);
+      const int blk = p.c[s].row * q + p.c[s].col;
+      if (!touched[blk]) {
+        d.first |= (uint8_t)(1u << s);
+        touched[blk] = true;
+      }
+      uint8_t& cnt = td.asm_cnt[blk];
+      td.asm_list[blk][cnt++] = (uint8_t)(r | (p.c[s].sign < 0 ? 0x80 : 0));
+    }
+    if (naive) {
+      if (p.a.size() > 1 || p.a[0].sign < 0) {
+        d.flags |= 1;
+        d.tslot_a = (uint8_t)td.nslot_a;
+        td.slot_prod_a[td.nslot_a++] = (uint8_t)r;
+      }
+      if (p.b.size() > 1 || p.b[0].sign < 0) {
+        d.flags |= 2;
+        d.tslot_b = (uint8_t)td.nslot_b;
+        td.slot_prod_b[td.nslot_b++] = (uint8_t)r;
+      }
+    }
+  }
+  return td;
+}
+
+static const TableDev* host_tables() {
+  static TableDev tabs[kNumTables];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    tabs[0] = make_table_dev(0, false);
+    tabs[1] = make_table_dev(1, false);
+    tabs[2] = make_table_dev(2, false);
+    tabs[3] = make_table_dev(1, true);
+    tabs[4] = make_table_dev(2, true);
+  });
+  return tabs;
+}
+
+static int table_maxt(const TableDev& td) {
+  int mx = 1;
+  for (int r = 0; r < td.nprod; ++r) {
+    const ProdDesc& d = td.prod[r];
+    const int na = (d.flags & 1) ? 1 : d.na, nb = (d.flags & 2) ? 1 : d.nb;
+    mx = std::max(mx, std::max(na, nb));
+  }
+  return mx <= 1 ? 1 : (mx <= 2 ? 2 : 4);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-device state: architecture check, constant tables, library-owned workspace.
+// ---------------------------------------------------------------------------------------------
+struct DeviceState {
+  bool ready = false;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+static std::mutex g_mu;
+static std::vector<DeviceState> g_dev;
+static void* g_user_ws = nullptr;
+static size_t g_user_ws_bytes = 0;
+
+static int device_ready(int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(STRASSEN_ERR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+  if (!g_dev[dev].ready) {
+    hipDeviceProp_t prop;
+    SMX_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(STRASSEN_ERR_NO_DEVICE, "device %d is %s, the library is built for gfx950", dev,
+                  prop.gcnArchName);
+    SMX_HIP(upload_tables(host_tables()));
+    SMX_HIP(hipDeviceSynchronize());
+    g_dev[dev].ready = true;
+  }
+  *dev_out = dev;
+  return 0;
+}
+
+// Device workspace of at least `bytes`: caller-provided if set, else the library's own.
+static int get_workspace(int dev, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_user_ws) {
+    if (bytes > g_user_ws_bytes)
+      return fail(STRASSEN_ERR_ALLOC, "caller workspace has %zu bytes, %zu needed",
+                  g_user_ws_bytes, bytes);
+    *out = g_user_ws;
+    return 0;
+  }
+  DeviceState& d = g_dev[dev];
+  if (d.ws_bytes < bytes) {
+    if (d.ws) {
+      SMX_HIP(hipDeviceSynchronize());  // earlier calls may still use the old buffer
+      SMX_HIP(hipFree(d.ws));
+      d.ws = nullptr;
+      d.ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&d.ws, bytes);
+    if (e != hipSuccess) {
+      d.ws = nullptr;
+      return fail(STRASSEN_ERR_ALLOC, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    d.ws_bytes = bytes;
+  }
+  *out = d.ws;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Planning.
+// ---------------------------------------------------------------------------------------------
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+struct Plan {
+  int levels, variant, q;
+  int64_t mq, nq, kq;
+  const TableDev* td;
+  int tab;
+  // workspace layout (doubles)
+  int64_t ldm, m_stride, ta_stride, tb_stride;
+  int64_t off_m, off_ta, off_tb, total;
+};
+
+static Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int variant) {
+  Plan p;
+  p.levels = levels;
+  p.variant = levels == 0 ? STRASSEN_ABC : variant;
+  p.q = 1 << levels;
+  p.mq = cdiv(m, p.q);
+  p.nq = cdiv(n, p.q);
+  p.kq = cdiv(k, p.q);
+  p.tab = table_id(levels, p.variant == STRASSEN_NAIVE);
+  p.td = &host_tables()[p.tab];
+  p.ldm = round_up(p.mq, 8);
+  p.m_stride = round_up(p.ldm * p.nq, 32);
+  p.ta_stride = round_up(p.mq * p.kq, 32);
+  p.tb_stride = round_up(p.kq * p.nq, 32);
+  p.off_m = p.off_ta = p.off_tb = p.total = 0;
+  if (p.variant != STRASSEN_ABC) {
+    p.off_m = 0;
+    p.total = p.m_stride * p.td->nprod;
+    if (p.variant == STRASSEN_NAIVE) {
+      p.off_ta = p.total;
+      p.total += p.ta_stride * p.td->nslot_a;
+      p.off_tb = p.total;
+      p.total += p.tb_stride * p.td->nslot_b;
+    }
+  }
+  return p;
+}
+
+static int pick_cfg(const Plan& p, int64_t products_per_launch) {
+  const int64_t t128 = cdiv(p.mq, 128) * cdiv(p.nq, 128) * products_per_launch;
+  return t128 >= 512 ? kCfg128 : kCfg64;
+}
+
+static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15) == 0; }
+
+static int validate(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double* C, int64_t ldc, int levels,
+                    int variant) {
+  if (m < 0) return fail(-1, "m = %lld < 0", (long long)m);
+  if (n < 0) return fail(-2, "n = %lld < 0", (long long)n);
+  if (k < 0) return fail(-3, "k = %lld < 0", (long long)k);
+  const bool reads_ab = m > 0 && n > 0 && k > 0 && alpha != 0.0;
+  if (reads_ab && A == nullptr) return fail(-5, "A is NULL");
+  if (lda < std::max<int64_t>(1, m)) return fail(-6, "lda = %lld < max(1, m)", (long long)lda);
+  if (reads_ab && B == nullptr) return fail(-7, "B is NULL");
+  if (ldb < std::max<int64_t>(1, k)) return fail(-8, "ldb = %lld < max(1, k)", (long long)ldb);
+  if (m > 0 && n > 0 && C == nullptr) return fail(-10, "C is NULL");
+  if (ldc < std::max<int64_t>(1, m)) return fail(-11, "ldc = %lld < max(1, m)", (long long)ldc);
+  if (levels < 0 || levels > kMaxLevels) return fail(-12, "levels = %d not in 0..%d", levels, kMaxLevels);
+  if (variant < 0 || variant > 2) return fail(-13, "variant = %d not in 0..2", variant);
+  return 0;
+}
+
+static int run_scale(double* C, int64_t ldc, int64_t m, int64_t n, double beta, hipStream_t s) {
+  ScaleArgs a;
+  a.C = C;
+  a.ldc = ldc;
+  a.m = m;
+  a.n = n;
+  a.beta = beta;
+  SMX_HIP(launch_scale(a, s));
+  return 0;
+}
+
+int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+          const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
+          int variant, hipStream_t stream) {
+  g_last_error.clear();
+  if (int rc = validate(m, n, k, alpha, A, lda, B, ldb, C, ldc, levels, variant)) return rc;
+  if (m == 0 || n == 0) return 0;
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
+  if (alpha == 0.0 || k == 0) {
+    if (beta == 1.0) return 0;
+    return run_scale(C, ldc, m, n, beta, stream);
+  }
+  const Plan p = make_plan(m, n, k, levels, variant);
+  const int64_t tiles_limit = 1ll << 30;
+
+  GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.mq = p.mq;
+  g.nq = p.nq;
+  g.kq = p.kq;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.tab = p.tab;
+  const int maxt = table_maxt(*p.td);
+  bool vec = aligned16(A) && aligned16(B) && lda % 2 == 0 && ldb % 2 == 0 && m % 2 == 0 &&
+             k % 2 == 0 && p.mq % 2 == 0 && p.kq % 2 == 0;
+
+  if (p.variant == STRASSEN_ABC) {
+    const int cfg = pick_cfg(p, 1);
+    g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
+    g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
+    const int64_t grid = (int64_t)g.tiles_m * g.tiles_n;
+    if (grid >= tiles_limit) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+    g.mode = kModeABC;
+    SMX_HIP(launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+    return 0;
+  }
+
+  void* ws = nullptr;
+  if (int rc = get_workspace(dev, (size_t)p.total * sizeof(double), &ws)) return rc;
+  double* wsd = static_cast<double*>(ws);
+  g.M = wsd + p.off_m;
+  g.ldm = p.ldm;
+  g.m_stride = p.m_stride;
+
+  if (p.variant == STRASSEN_NAIVE) {
+    double* TA = wsd + p.off_ta;
+    double* TB = wsd + p.off_tb;
+    if (p.td->nslot_a > 0) {
+      SumArgs sa;
+      std::memset(&sa, 0, sizeof sa);
+      sa.src = A;
+      sa.dst = TA;
+      sa.ld = lda;
+      sa.rows = m;
+      sa.cols = k;
+      sa.rows_q = p.mq;
+      sa.cols_q = p.kq;
+      sa.dst_stride = p.ta_stride;
+      sa.tab = p.tab;
+      sa.side = 0;
+      sa.chunks_r = (int32_t)cdiv(p.mq, 256);
+      SMX_HIP(launch_sums(sa, p.td->nslot_a, stream));
+    }
+    if (p.td->nslot_b > 0) {
+      SumArgs sb;
+      std::memset(&sb, 0, sizeof sb);
+      sb.src = B;
+      sb.dst = TB;
+      sb.ld = ldb;
+      sb.rows = k;
+      sb.cols = n;
+      sb.rows_q = p.kq;
+      sb.cols_q = p.nq;
+      sb.dst_stride = p.tb_stride;
+      sb.tab = p.tab;
+      sb.side = 1;
+      sb.chunks_r = (int32_t)cdiv(p.kq, 256);
+      SMX_HIP(launch_sums(sb, p.td->nslot_b, stream));
+    }
+    g.TA = TA;
+    g.TB = TB;
+    g.ta_stride = p.ta_stride;
+    g.tb_stride = p.tb_stride;
+  }
+
+  const int cfg = pick_cfg(p, p.td->nprod);
+  g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
+  g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
+  g.mode = kModeStoreM;
+  g.prod_begin = 0;
+  const int64_t grid = (int64_t)g.tiles_m * g.tiles_n * p.td->nprod;
+  if (grid >= tiles_limit) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+  SMX_HIP(launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+
+  AssembleArgs asmb;
+  std::memset(&asmb, 0, sizeof asmb);
+  asmb.M = g.M;
+  asmb.C = C;
+  asmb.ldm = p.ldm;
+  asmb.m_stride = p.m_stride;
+  asmb.ldc = ldc;
+  asmb.m = m;
+  asmb.n = n;
+  asmb.mq = p.mq;
+  asmb.nq = p.nq;
+  asmb.alpha = alpha;
+  asmb.beta = beta;
+  asmb.tab = p.tab;
+  asmb.chunks_m = (int32_t)cdiv(p.mq, 256);
+  if ((int64_t)asmb.chunks_m * p.nq * p.q * p.q >= tiles_limit)
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many assembly workgroups");
+  SMX_HIP(launch_assemble(asmb, p.q * p.q, stream));
+  return 0;
+}
+
+}  // namespace smx
+
+// ---------------------------------------------------------------------------------------------
+// extern "C" entry points.
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
+                   int variant, void* stream) {
+  return smx::dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant,
+                    static_cast<hipStream_t>(stream));
+}
+
+int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int variant,
+                            size_t* bytes) {
+  smx::g_last_error.clear();
+  if (m < 0) return smx::fail(-1, "m < 0");
+  if (n < 0) return smx::fail(-2, "n < 0");
+  if (k < 0) return smx::fail(-3, "k < 0");
+  if (levels < 0 || levels > smx::kMaxLevels) return smx::fail(-4, "levels out of range");
+  if (variant < 0 || variant > 2) return smx::fail(-5, "variant out of range");
+  if (!bytes) return smx::fail(-6, "bytes is NULL");
+  if (m == 0 || n == 0 || k == 0) {
+    *bytes = 0;
+    return 0;
+  }
+  const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
+  *bytes = (size_t)p.total * sizeof(double);
+  return 0;
+}
+
+int strassen_set_workspace(void* ptr, size_t bytes) {
+  smx::g_last_error.clear();
+  if (ptr && ((uintptr_t)ptr & 255) != 0) return smx::fail(-1, "workspace not 256-byte aligned");
+  if (ptr && bytes == 0) return smx::fail(-2, "workspace of 0 bytes");
+  std::lock_guard<std::mutex> lk(smx::g_mu);
+  smx::g_user_ws = ptr;
+  smx::g_user_ws_bytes = ptr ? bytes : 0;
+  return 0;
+}
+
+int strassen_release_workspace(void) {
+  smx::g_last_error.clear();
+  std::lock_guard<std::mutex> lk(smx::g_mu);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return 0;
+  for (size_t d = 0; d < smx::g_dev.size(); ++d) {
+    if (!smx::g_dev[d].ws) continue;
+    SMX_HIP(hipSetDevice((int)d));
+    SMX_HIP(hipDeviceSynchronize());
+    SMX_HIP(hipFree(smx::g_dev[d].ws));
+    smx::g_dev[d].ws = nullptr;
+    smx::g_dev[d].ws_bytes = 0;
+  }
+  SMX_HIP(hipSetDevice(cur));
+  return 0;
+}
+
+int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
+                     int variant, int compute, int sum_prec, int c_prec, void* stream) {
+  smx::g_last_error.clear();
+  if (compute < 0 || compute > 2) return smx::fail(-14, "compute out of range");
+  if (sum_prec < 0 || sum_prec > 1) return smx::fail(-15, "sum_prec out of range");
+  if (c_prec < 0 || c_prec > 1) return smx::fail(-16, "c_prec out of range");
+  if (compute == STRASSEN_COMPUTE_F64)
+    return strassen_dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, stream);
+  return smx::fail(STRASSEN_ERR_UNSUPPORTED, "reduced-precision mode not built yet");
+}
+
+int strassen_table_size(int levels) {
+  if (levels < 0 || levels > smx::kMaxLevels) return -1;
+  return smx::host_tables()[smx::table_id(levels, false)].nprod;
+}
+
+int strassen_table_get(int levels, int r, int* na, int* a_terms, int* nb, int* b_terms, int* nc,
+                       int* c_terms) {
+  if (levels < 0 || levels > smx::kMaxLevels) return -1;
+  const smx::TableDev& td = smx::host_tables()[smx::table_id(levels, false)];
+  if (r < 0 || r >= td.nprod) return -2;
+  const smx::ProdDesc& d = td.prod[r];
+  const int q = td.q;
+  auto dec = [q](uint8_t c) {
+    const int v = 1 + (c & 7) + q * ((c >> 3) & 7);
+    return (c & 0x80) ? -v : v;
+  };
+  *na = d.na;
+  *nb = d.nb;
+  *nc = d.nc;
+  for (int s = 0; s < d.na; ++s) a_terms[s] = dec(d.a[s]);
+  for (int s = 0; s < d.nb; ++s) b_terms[s] = dec(d.b[s]);
+  for (int s = 0; s < d.nc; ++s) c_terms[s] = dec(d.c[s]);
+  return 0;
+}
+
+const char* strassen_last_error(void) { return smx::g_last_error.c_str(); }
+
+const char* strassen_version(void) { return "strassen-mi355x 0.1 (gfx950, FP64 MFMA)"; }
+
+}  // extern "C"

@@ -1,0 +1,30 @@
+// Host-side launchers of the HIP kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace smx {
+
+// Tile configurations of the FP64 tile kernel: workgroup tile BM x BN, k step BK, 256 threads.
+enum TileCfg : int {
+  kCfg128 = 0,     // 128 x 128, BK 16
+  kCfg64 = 1,      // 64 x 64, BK 16
+  kNumCfgs = 2
+};
+inline int cfg_bm(int cfg) { return cfg == kCfg128 ? 128 : 64; }
+inline int cfg_bn(int cfg) { return cfg == kCfg128 ? 128 : 64; }
+
+// Copies the kNumTables table descriptors into the current device's constant memory.
+hipError_t upload_tables(const TableDev* tabs);
+
+// FP64 tile kernel.  maxt: largest operand term count in the table (1, 2 or 4);
+// vec: operands are 16-byte aligned with even leading dimensions and even extents, so
+// pairs of doubles can be loaded together.  grid = number of workgroups.
+hipError_t launch_fp64_tile(const GemmArgs& a, int cfg, int maxt, bool vec, int grid,
+                            hipStream_t s);
+hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
+hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
+hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
+
+}  // namespace smx

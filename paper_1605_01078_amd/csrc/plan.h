@@ -1,0 +1,103 @@
+// Internal structures shared by the host planner and the HIP kernels.
+//
+// A Strassen "table" lists, for every product M_r, the general operation of eq. (e:straprim4):
+//   M_r = (sum_s delta_s X_s)(sum_t eps_t V_t);  C_d += alpha * gamma_d * M_r for each destination d,
+// with X_s sub-blocks of A, V_t sub-blocks of B and C_d sub-blocks of C in the 2^L x 2^L partition.
+#pragma once
+#include <stdint.h>
+#include <vector>
+
+namespace smx {
+
+constexpr int kMaxLevels = 2;
+constexpr int kMaxProducts = 49;   // 7^kMaxLevels
+constexpr int kMaxTerms = 4;       // 2^kMaxLevels operand terms / destinations per product
+
+// Term code: bits 0-2 row block, bits 3-5 column block, bit 7 set for a minus sign.
+inline constexpr uint8_t term_code(int row, int col, int sign) {
+  return (uint8_t)((row & 7) | ((col & 7) << 3) | (sign < 0 ? 0x80 : 0));
+}
+
+struct ProdDesc {
+  uint8_t na, nb, nc;   // number of A terms, B terms, C destinations
+  uint8_t first;        // bit d: destination d is the first update of its C sub-block (apply beta)
+  uint8_t flags;        // bit 0: A operand is Naive temporary slot `tslot_a`; bit 1: same for B
+  uint8_t tslot_a, tslot_b, pad0;
+  uint8_t a[kMaxTerms], b[kMaxTerms], c[kMaxTerms];
+  uint8_t pad1[4];
+};
+static_assert(sizeof(ProdDesc) == 24, "ProdDesc layout");
+
+enum : int32_t { kModeABC = 0, kModeStoreM = 1 };
+
+// Everything the kernels need to know about one table, kept in __constant__ memory
+// (uploaded once per device).  Table ids: see table_id().
+struct TableDev {
+  int32_t nprod;
+  int32_t q;                                  // 2^levels
+  int32_t nslot_a, nslot_b;                   // Naive operand-sum temporaries
+  ProdDesc prod[kMaxProducts];
+  uint8_t asm_cnt[16];                        // products feeding C sub-block s = ci*q + cj
+  uint8_t asm_list[16][16];                   // their indices (| 0x80 for a minus sign), increasing
+  uint8_t slot_prod_a[kMaxProducts];          // product whose A sum fills Naive slot s
+  uint8_t slot_prod_b[kMaxProducts];
+};
+constexpr int kNumTables = 5;
+// 0: classical; 1, 2: one / two levels (ABC, AB); 3, 4: one / two levels, Naive slots
+inline int table_id(int levels, bool naive) { return levels == 0 ? 0 : (naive ? 2 + levels : levels); }
+
+// Arguments of the FP64 tile kernel.
+struct GemmArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  double* M;            // StoreM mode: M_r at M + r * m_stride, leading dimension ldm
+  const double* TA;     // Naive: A-sum slot s at TA + s * ta_stride (leading dimension mq)
+  const double* TB;     // Naive: B-sum slot s at TB + s * tb_stride (leading dimension kq)
+  int64_t lda, ldb, ldc, ldm, m_stride, ta_stride, tb_stride;
+  int64_t m, n, k;      // full problem
+  int64_t mq, nq, kq;   // sub-block extents ceil(m/q), ceil(n/q), ceil(k/q)
+  double alpha, beta;
+  int32_t tab;          // table id
+  int32_t tiles_m, tiles_n;
+  int32_t mode;         // kModeABC: a workgroup owns one tile position in every C sub-block and
+                        //           runs every product; kModeStoreM: one (product, tile) each
+  int32_t prod_begin;   // StoreM: first product of this launch
+};
+
+// C assembly for AB / Naive: C_s := beta*C_s at the first update, then C_s += alpha*gamma*M_r
+// for the products r feeding sub-block s, in increasing r.
+struct AssembleArgs {
+  const double* M;
+  double* C;
+  int64_t ldm, m_stride, ldc;
+  int64_t m, n, mq, nq;
+  double alpha, beta;
+  int32_t tab;
+  int32_t chunks_m;     // ceil(mq / rows per workgroup)
+};
+
+// Naive operand sums: slot s := sum_t delta_t X_t over the zero-padded sub-block extent.
+struct SumArgs {
+  const double* src;
+  double* dst;          // slot s at dst + s * dst_stride, leading dimension rows_q
+  int64_t ld, rows, cols, rows_q, cols_q, dst_stride;
+  int32_t tab;
+  int32_t side;         // 0: A operand (rows = m, cols = k); 1: B operand (rows = k, cols = n)
+  int32_t chunks_r;
+};
+
+// C := beta*C (alpha == 0 or k == 0).
+struct ScaleArgs {
+  double* C;
+  int64_t ldc, m, n;
+  double beta;
+};
+
+struct Term { int row, col, sign; };
+struct Product { std::vector<Term> a, b, c; };
+
+// Product-side table construction (one-level figure + Kronecker composition, Sec. 3.5).
+std::vector<Product> build_table(int levels);
+
+}  // namespace smx

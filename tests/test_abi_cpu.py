@@ -1,0 +1,124 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls).
+
+The library must load, export every function include/strassen.h declares, reject invalid
+arguments with the documented -i codes before touching any device, report workspace sizes
+that follow from the sub-block shapes, and carry the same operation tables as the oracle.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1605_01078_amd as sx
+from oracle import tables as otab
+
+
+def test_library_loads_and_exports_header_functions():
+    L = sx.lib()
+    names = sx.header_functions()
+    assert "strassen_dgemm" in names and "strassen_gemm_ex" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert "gfx950" in sx.version()
+
+
+BAD = [
+    # (m, n, k, lda, ldb, ldc, levels, variant, A, B, C) -> expected code
+    ((-1, 4, 4, 4, 4, 4, 1, 0, 1, 1, 1), -1),
+    ((4, -1, 4, 4, 4, 4, 1, 0, 1, 1, 1), -2),
+    ((4, 4, -1, 4, 4, 4, 1, 0, 1, 1, 1), -3),
+    ((4, 4, 4, 4, 4, 4, 1, 0, 0, 1, 1), -5),
+    ((4, 4, 4, 3, 4, 4, 1, 0, 1, 1, 1), -6),
+    ((4, 4, 4, 4, 4, 4, 1, 0, 1, 0, 1), -7),
+    ((4, 4, 5, 4, 4, 4, 1, 0, 1, 1, 1), -8),
+    ((4, 4, 4, 4, 4, 4, 1, 0, 1, 1, 0), -10),
+    ((4, 4, 4, 4, 4, 3, 1, 0, 1, 1, 1), -11),
+    ((4, 4, 4, 4, 4, 4, 3, 0, 1, 1, 1), -12),
+    ((4, 4, 4, 4, 4, 4, -1, 0, 1, 1, 1), -12),
+    ((4, 4, 4, 4, 4, 4, 1, 3, 1, 1, 1), -13),
+    ((0, 4, 4, 0, 4, 0, 1, 0, 1, 1, 1), -6),     # lda >= max(1, m) even when m == 0
+]
+
+
+@pytest.mark.parametrize("args,code", BAD)
+def test_invalid_arguments(args, code):
+    m, n, k, lda, ldb, ldc, lev, var, pa, pb, pc = args
+    fake = 1 << 20   # never dereferenced: validation fails first
+    rc = sx.raw_dgemm(m, n, k, 1.0, fake * pa or None, lda, fake * pb or None, ldb, 1.0,
+                      fake * pc or None, ldc, lev, var, None)
+    assert rc == code
+    assert sx.last_error() != ""
+
+
+def test_quick_return_without_device():
+    # m == 0 or n == 0: nothing to do, success, no device touched (none exists here)
+    assert sx.raw_dgemm(0, 5, 5, 1.0, None, 1, None, 5, 1.0, None, 1, 1, 0, None) == 0
+    assert sx.raw_dgemm(5, 0, 5, 1.0, None, 5, None, 5, 1.0, None, 5, 2, 1, None) == 0
+
+
+def test_null_operands_allowed_when_not_read():
+    # alpha == 0: A and B are not referenced (BLAS); with m == 0 nothing at all is done
+    assert sx.raw_dgemm(0, 3, 3, 0.0, None, 1, None, 3, 1.0, None, 1, 1, 0, None) == 0
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_tables_match_oracle(levels):
+    lib_tab = sx.table(levels)
+    ora = otab.table(levels)
+    assert len(lib_tab) == len(ora)
+    for r, (la, lb, lc) in enumerate(lib_tab):
+        oa, ob, oc = ora[r]
+        assert la == [tuple(t) for t in oa], r
+        assert lb == [tuple(t) for t in ob], r
+        assert sorted(lc) == sorted(tuple(t) for t in oc), r
+
+
+def test_tables_satisfy_identity():
+    for levels in (1, 2):
+        tab = sx.table(levels)
+        assert np.array_equal(otab.tensor_of(tab, levels), otab.matmul_tensor(levels))
+
+
+def _cdiv(a, b):
+    return -(-a // b)
+
+
+@pytest.mark.parametrize("m,n,k", [(512, 512, 512), (1000, 777, 333), (16384, 16384, 16384)])
+def test_workspace_sizes(m, n, k):
+    assert sx.workspace_size(m, n, k, 0, "ab") == 0
+    for levels in (1, 2):
+        q = 2 ** levels
+        mq, nq, kq = _cdiv(m, q), _cdiv(n, q), _cdiv(k, q)
+        assert sx.workspace_size(m, n, k, levels, "abc") == 0
+        ab = sx.workspace_size(m, n, k, levels, "ab")
+        nprod = 7 ** levels
+        # one M_r per product, leading dimension rounded to 8 doubles, slot to 32
+        per = _cdiv(_cdiv(mq, 8) * 8 * nq, 32) * 32
+        assert ab == 8 * nprod * per
+        nv = sx.workspace_size(m, n, k, levels, "naive")
+        tab = otab.table(levels)
+        na = sum(1 for a, _, _ in tab if len(a) > 1 or a[0][1] < 0)
+        nb = sum(1 for _, b, _ in tab if len(b) > 1 or b[0][1] < 0)
+        assert (na, nb) == ((5, 5) if levels == 1 else (45, 45))
+        assert nv == ab + 8 * (na * _cdiv(mq * kq, 32) * 32 + nb * _cdiv(kq * nq, 32) * 32)
+
+
+def test_workspace_size_errors():
+    out = ctypes.c_size_t()
+    L = sx.lib()
+    assert L.strassen_workspace_size(-1, 1, 1, 1, 0, ctypes.byref(out)) == -1
+    assert L.strassen_workspace_size(1, 1, 1, 5, 0, ctypes.byref(out)) == -4
+    assert L.strassen_workspace_size(1, 1, 1, 1, 9, ctypes.byref(out)) == -5
+    assert L.strassen_set_workspace(ctypes.c_void_p(8), 64) == -1
+    assert L.strassen_set_workspace(ctypes.c_void_p(256), 0) == -2
+    assert L.strassen_set_workspace(None, 0) == 0
+
+
+def test_gemm_ex_argument_checks():
+    L = sx.lib()
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, None, 4, 1.0, None, 4, 1, 0, 7, 0, 0, None)
+    assert rc == -14
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, None, 4, 1.0, None, 4, 1, 0, 1, 2, 0, None)
+    assert rc == -15
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, None, 4, 1.0, None, 4, 1, 0, 1, 0, 5, None)
+    assert rc == -16

@@ -1,0 +1,180 @@
+"""Parity of the HIP path with the CPU oracle (needs an MI355X).
+
+Every call goes through the C-ABI (via the ctypes binding).  Tolerances:
+  * small integer inputs: bit-exact (every intermediate of one- and two-level Strassen is an
+    integer below 2^53, so any order of exact operations gives the same value);
+  * real inputs, Strassen: relative Frobenius error <= 1e-12 (one level), 1e-11 (two levels)
+    against the plain-definition oracle;
+  * real inputs, classical: elementwise |C - C_ref| <= 2 gamma_{k+2} (|alpha||A||B| + |beta||C|),
+    the rounding-error bound of any summation order (Higham, Sec. 3.1).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle_dgemm, oracle_strassen, rel_fro
+
+torch = pytest.importorskip("torch")
+sx = pytest.importorskip("paper_1605_01078_amd")
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+TOL = {1: 1e-12, 2: 1e-11}
+VARIANTS = ["abc", "ab", "naive"]
+
+
+def run(A, B, C, alpha, beta, levels, variant, lda=None, ldb=None, ldc=None, offset=0):
+    dA = sx.to_device(A, ld=lda, offset=offset)
+    dB = sx.to_device(B, ld=ldb, offset=offset)
+    dC = sx.to_device(C, ld=ldc, offset=offset)
+    sx.dgemm(dA, dB, dC, alpha, beta, levels, variant)
+    torch.cuda.synchronize()
+    return sx.to_host(dC)
+
+
+def classical_bound(A, B, C, alpha, beta):
+    k = A.shape[1]
+    g = (k + 2) * U / (1 - (k + 2) * U)
+    return 2 * g * (abs(alpha) * (np.abs(A) @ np.abs(B)) + abs(beta) * np.abs(C))
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_c1_uniform_512(levels, variant):
+    if levels == 0 and variant != "abc":
+        pytest.skip("classical has one variant")
+    print(f"case c1 uniform L={levels} {variant}", flush=True)
+    A, B, C = W.problem(0, 512, 512, 512, "uniform")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    got = run(A, B, C, 1.0, 1.0, levels, variant)
+    if levels == 0:
+        assert np.all(np.abs(got - ref) <= classical_bound(A, B, C, 1.0, 1.0))
+    else:
+        assert rel_fro(got, ref) <= TOL[levels]
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_c1_integer_bit_exact(levels, variant):
+    print(f"case c1 integer L={levels} {variant}", flush=True)
+    A, B, C = W.problem(0, 512, 512, 512, "integer", c_zero=True)
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    if levels > 0:
+        ref2 = oracle_strassen(A, B, C.copy(order="F"), 1.0, 1.0, levels)
+        assert np.array_equal(ref, ref2)
+    got = run(A, B, C, 1.0, 1.0, levels, variant)
+    assert np.array_equal(got, ref)
+
+
+RAGGED = [(1, 1, 1), (3, 5, 7), (17, 33, 9), (255, 257, 130), (513, 511, 515), (1000, 1000, 1000),
+          (64, 1030, 31), (700, 90, 1290), (129, 2, 260)]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_ragged_integer_all_variants(shape, levels):
+    m, n, k = shape
+    print(f"case ragged integer {shape} L={levels}", flush=True)
+    A, B, C = W.problem(1, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 2.0, -1.0)
+    outs = []
+    for variant in (VARIANTS if levels else ["abc"]):
+        got = run(A, B, C, 2.0, -1.0, levels, variant)
+        assert np.array_equal(got, ref), variant
+        outs.append(got)
+
+
+@pytest.mark.parametrize("shape", [(255, 257, 130), (513, 511, 515), (1000, 777, 333)])
+@pytest.mark.parametrize("levels", [1, 2])
+def test_ragged_uniform_tolerance_and_variants_bitwise(shape, levels):
+    m, n, k = shape
+    print(f"case ragged uniform {shape} L={levels}", flush=True)
+    A, B, C = W.problem(2, m, n, k, "uniform")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 0.75, 0.5)
+    outs = [run(A, B, C, 0.75, 0.5, levels, v) for v in VARIANTS]
+    for got in outs:
+        assert rel_fro(got, ref) <= TOL[levels]
+    # same table, same product order, same update arithmetic: variants agree bit for bit
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_leading_dimensions_and_unaligned(levels):
+    m, n, k = 300, 260, 270
+    print(f"case ld/unaligned L={levels}", flush=True)
+    A, B, C = W.problem(3, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    for lda, ldb, ldc, off in [(m + 3, k + 5, m + 1, 0), (m + 8, k + 8, m + 8, 1), (m, k, m, 1)]:
+        got = run(A, B, C, 1.0, 1.0, levels, "abc", lda, ldb, ldc, off)
+        assert np.array_equal(got, ref), (lda, ldb, ldc, off)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_beta_zero_ignores_nan_in_c(levels, variant):
+    A, B, _ = W.problem(4, 130, 140, 150, "integer")
+    C = np.full((130, 140), np.nan, order="F")
+    got = run(A, B, C, 1.0, 0.0, levels, variant)
+    ref = oracle_dgemm(A, B, np.zeros((130, 140), order="F"), 1.0, 0.0)
+    assert np.array_equal(got, ref)
+
+
+def test_alpha_zero_and_k_zero_scale_c_only():
+    g = np.random.default_rng(5)
+    C = W.integers(g, 70, 90)
+    A = np.full((70, 40), np.nan, order="F")
+    B = np.full((40, 90), np.nan, order="F")
+    for levels in (0, 1, 2):
+        got = run(A, B, C, 0.0, 3.0, levels, "abc")
+        assert np.array_equal(got, 3.0 * C)
+        got = run(A, B, C, 0.0, 0.0, levels, "ab")
+        assert np.all(got == 0.0)
+    dA = sx.colmajor(70, 0)
+    dB = sx.colmajor(0, 90)
+    dC = sx.to_device(C)
+    sx.dgemm(dA, dB, dC, 1.0, -2.0, 1, "abc")
+    torch.cuda.synchronize()
+    assert np.array_equal(sx.to_host(dC), -2.0 * C)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_determinism_and_power_of_two_scaling(levels):
+    A, B, C = W.problem(6, 600, 520, 700, "uniform")
+    a1 = run(A, B, C, 1.0, 0.0, levels, "abc")
+    a2 = run(A, B, C, 1.0, 0.0, levels, "abc")
+    assert np.array_equal(a1, a2)
+    a3 = run(2.0 * A, B, C, 1.0, 0.0, levels, "abc")
+    assert np.array_equal(a3, 2.0 * a1)
+    a4 = run(A, B, C, 0.5, 0.0, levels, "abc")
+    assert np.array_equal(a4, 0.5 * a1)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_strassen_error_comparable_to_oracle_strassen(levels):
+    A, B, C = W.problem(7, 512, 512, 512, "uniform")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    o2 = oracle_strassen(A, B, C.copy(order="F"), 1.0, 1.0, levels)
+    got = run(A, B, C, 1.0, 1.0, levels, "abc")
+    e_gpu, e_o2 = rel_fro(got, ref), rel_fro(o2, ref)
+    print(f"L={levels}: gpu {e_gpu:.3e} oracle-strassen {e_o2:.3e}")
+    assert e_gpu <= 10 * e_o2 + 1e-16
+
+
+def test_caller_workspace():
+    A, B, C = W.problem(8, 400, 300, 200, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    need = sx.workspace_size(400, 300, 200, 2, "naive")
+    ws = torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    sx.set_workspace(ws)
+    try:
+        assert np.array_equal(run(A, B, C, 1.0, 1.0, 2, "naive"), ref)
+        small = torch.empty(64, dtype=torch.float64, device="cuda")
+        sx.set_workspace(small)
+        dA, dB, dC = sx.to_device(A), sx.to_device(B), sx.to_device(C)
+        with pytest.raises(sx.StrassenError) as ei:
+            sx.dgemm(dA, dB, dC, 1.0, 1.0, 2, "ab")
+        assert ei.value.code == 2
+        torch.cuda.synchronize()
+        assert np.array_equal(sx.to_host(dC), C)   # untouched
+    finally:
+        sx.set_workspace(None)

@@ -96,3 +96,15 @@ def selector_shapes(seed=0, count=20000, lo=256, hi=20000):
     x = np.exp(g.uniform(np.log(lo), np.log(hi), size=(count, 3)))
     x = np.clip(np.rint(x), lo, hi).astype(np.int64)
     return [tuple(int(v) for v in row) for row in x]
+
+
+def device_uniform(seed, rows, cols, ld=None, device="cuda", lo=-1.0, hi=1.0):
+    """rows x cols column-major float64 torch tensor, i.i.d. uniform on [lo, hi), drawn on the
+    device from a seeded torch generator (for sizes too large to draw on the host quickly)."""
+    import torch
+    ld = rows if ld is None else int(ld)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    buf = torch.empty((cols, max(ld, 1)), dtype=torch.float64, device=device)
+    buf.uniform_(lo, hi, generator=g)
+    return buf.t()[:rows, :]
