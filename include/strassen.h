@@ -133,6 +133,16 @@ int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                      void *stream);
 
 /*
+ * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the
+ * tile configuration per call; 0..3 forces one for every later call in the process:
+ *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;
+ *   2: 128 x 128, k step 8, two workgroups per CU;        3: 128 x 128, k step 16, one per CU.
+ * Results do not depend on the configuration (bitwise).  The environment variable
+ * STRASSEN_TILE_CFG sets the initial value.  Returns 0 or -1 (cfg out of range).
+ */
+int strassen_set_tile_config(int cfg);
+
+/*
  * Table introspection (host only, no device needed): the operation table the kernels execute.
  * strassen_table_size returns the number of products for `levels` (1, 7, 49) or -1.
  * strassen_table_get fills, for product r, the operand and destination terms as

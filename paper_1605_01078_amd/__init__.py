@@ -56,6 +56,8 @@ def lib():
         L.strassen_table_get.restype = ci
         L.strassen_last_error.argtypes = []
         L.strassen_last_error.restype = ctypes.c_char_p
+        L.strassen_set_tile_config.argtypes = [ci]
+        L.strassen_set_tile_config.restype = ci
         L.strassen_version.argtypes = []
         L.strassen_version.restype = ctypes.c_char_p
         _optional(L)
@@ -216,6 +218,11 @@ def set_workspace(tensor_or_none):
     else:
         t = tensor_or_none
         check(lib().strassen_set_workspace(t.data_ptr(), t.numel() * t.element_size()))
+
+
+def set_tile_config(cfg):
+    """Force a tile configuration (0..3) for later calls, or -1 for the automatic choice."""
+    check(lib().strassen_set_tile_config(int(cfg)))
 
 
 def release_workspace():

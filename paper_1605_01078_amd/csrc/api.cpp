@@ -1,8 +1,10 @@
 // C-ABI of the Strassen library: argument checking, planning, workspace, launches.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -213,9 +215,21 @@ static Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int variant) 
   return p;
 }
 
-static int pick_cfg(const Plan& p, int64_t products_per_launch) {
+// Tile configuration: 128 x 128 when there are enough tiles to fill the 256 CUs twice over,
+// else 64 x 64.  Four-term tables (two levels) use the BK = 8 variant, whose staging registers
+// for four quadrant tiles fit beside the 128 x 128 accumulator at two workgroups per CU.
+// STRASSEN_TILE_CFG=<0..3> forces one configuration (used by the tuning sweeps).
+static std::atomic<int> g_forced_cfg{[] {
+  const char* e = std::getenv("STRASSEN_TILE_CFG");
+  return e ? std::atoi(e) : -1;
+}()};
+
+static int pick_cfg(const Plan& p, int64_t products_per_launch, int maxt) {
+  const int forced = g_forced_cfg.load(std::memory_order_relaxed);
+  if (forced >= 0 && forced < kNumCfgs) return forced;
   const int64_t t128 = cdiv(p.mq, 128) * cdiv(p.nq, 128) * products_per_launch;
-  return t128 >= 512 ? kCfg128 : kCfg64;
+  if (t128 < 512) return kCfg64;
+  return maxt >= 4 ? kCfg128k8 : kCfg128;
 }
 
 static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15) == 0; }
@@ -286,7 +300,7 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
              k % 2 == 0 && p.mq % 2 == 0 && p.kq % 2 == 0;
 
   if (p.variant == STRASSEN_ABC) {
-    const int cfg = pick_cfg(p, 1);
+    const int cfg = pick_cfg(p, 1, maxt);
     g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
     g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
     const int64_t grid = (int64_t)g.tiles_m * g.tiles_n;
@@ -344,7 +358,7 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     g.tb_stride = p.tb_stride;
   }
 
-  const int cfg = pick_cfg(p, p.td->nprod);
+  const int cfg = pick_cfg(p, p.td->nprod, maxt);
   g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
   g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
   g.mode = kModeStoreM;
@@ -443,6 +457,13 @@ int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double
   if (compute == STRASSEN_COMPUTE_F64)
     return strassen_dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, stream);
   return smx::fail(STRASSEN_ERR_UNSUPPORTED, "reduced-precision mode not built yet");
+}
+
+int strassen_set_tile_config(int cfg) {
+  smx::g_last_error.clear();
+  if (cfg < -1 || cfg >= smx::kNumCfgs) return smx::fail(-1, "tile configuration %d out of range", cfg);
+  smx::g_forced_cfg.store(cfg);
+  return 0;
 }
 
 int strassen_table_size(int levels) {

@@ -8,12 +8,14 @@ namespace smx {
 
 // Tile configurations of the FP64 tile kernel: workgroup tile BM x BN, k step BK, 256 threads.
 enum TileCfg : int {
-  kCfg128 = 0,     // 128 x 128, BK 16
+  kCfg128 = 0,     // 128 x 128, BK 16, two workgroups per CU
   kCfg64 = 1,      // 64 x 64, BK 16
-  kNumCfgs = 2
+  kCfg128k8 = 2,   // 128 x 128, BK 8, two workgroups per CU
+  kCfg128w1 = 3,   // 128 x 128, BK 16, one workgroup per CU (512 registers per lane)
+  kNumCfgs = 4
 };
-inline int cfg_bm(int cfg) { return cfg == kCfg128 ? 128 : 64; }
-inline int cfg_bn(int cfg) { return cfg == kCfg128 ? 128 : 64; }
+inline int cfg_bm(int cfg) { return cfg == kCfg64 ? 64 : 128; }
+inline int cfg_bn(int cfg) { return cfg == kCfg64 ? 64 : 128; }
 
 // Copies the kNumTables table descriptors into the current device's constant memory.
 hipError_t upload_tables(const TableDev* tabs);

@@ -1,0 +1,401 @@
+// FP64 Strassen tile: the quadrant-summing operand load and the FP64 MFMA main loop for one
+// product M_r on one BM x BN tile (the GPU form of the paper's modified packing routines and
+// micro-kernel, Sec. 4.1).  Included by the translation units that launch it.
+//
+// Layout
+//   256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a (BM/2) x (BN/2) block as
+//   (BM/32) x (BN/32) 16x16 MFMA accumulators (v_mfma_f64_16x16x4_f64).
+//   LDS holds two stages of As[BK][BM] and Bs[BK][BN + 1] (both k-major; B is transposed on its
+//   way in, the +1 padding keeps that store free of bank conflicts).
+//   The MFMA takes B as its first operand and A as its second, so it produces the transposed
+//   16x16 block: lane l, element e holds C(row l % 16, column l / 16 + 4e).  Sixteen lanes thus
+//   cover 16 consecutive rows of one column, which keeps column-major C and M traffic coalesced.
+//
+// Operand load
+//   Every term X_s of the product has a wave-uniform base pointer (scalar registers) and all
+//   terms share the per-thread 32-bit offsets, so summing 2 or 4 quadrant tiles costs no extra
+//   vector address registers.  Tiles strictly inside every term's valid extent take an
+//   unmasked path; fringe tiles and the last partial k step take a masked path in which
+//   out-of-range positions read a safe address and are replaced by zero (the paper's internal
+//   zero padding, Sec. 3.3).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace smx {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int code_row(uint8_t c) { return c & 7; }
+__device__ __forceinline__ int code_col(uint8_t c) { return (c >> 3) & 7; }
+__device__ __forceinline__ bool code_neg(uint8_t c) { return (c & 0x80) != 0; }
+
+// One C update.  Every variant goes through this function in the same product order, so
+// ABC, AB and Naive give bitwise identical results for the same table.
+__device__ __forceinline__ double c_update(double c, double mv, double ag, double beta,
+                                           bool first) {
+  if (!first) return __builtin_fma(ag, mv, c);
+  if (beta == 0.0) return ag * mv;
+  return __builtin_fma(ag, mv, beta * c);
+}
+
+// Signed operand sum, term by term in table order: v = +-x0, then v = v +- x_s.
+__device__ __forceinline__ double sum_first(double x, bool neg) { return neg ? -x : x; }
+__device__ __forceinline__ double sum_next(double v, double x, bool neg) {
+  return neg ? v - x : v + x;
+}
+
+// Raw buffer access (gfx9 buffer resource: stride 0, 2 GiB range).  A load whose offset lies
+// past the range returns zero without touching memory; kOOB is such an offset.
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
+constexpr uint32_t kOOB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, 0x7fffffff,
+                                           0x00020000);
+}
+__device__ __forceinline__ d2_t load2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ double load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// Store operand for the 64-bit buffer store.  Goes through uint64_t: a direct bit_cast of an
+// element of a double vector to the 2 x u32 vector is lowered to the wrong register by this
+// compiler (every element of the vector is stored as element 0).
+__device__ __forceinline__ u2_t as_u2(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  return (u2_t){(unsigned)b, (unsigned)(b >> 32)};
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8).
+// Give each XCD a contiguous range of logical ids so neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nwg) {
+  const int per = nwg >> 3, rem = nwg & 7, x = b & 7, idx = b >> 3;
+  return x * per + min(x, rem) + idx;
+}
+
+// Logical tile id -> (ti, tj), walking groups of 8 tile rows column by column so that the
+// workgroups resident at one time cover a compact block of C (operand panels reused in L2).
+__device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int& ti, int& tj) {
+  constexpr int G = 8;
+  const int per_group = G * tiles_n;
+  const int group = t / per_group;
+  const int first = group * G;
+  const int gsize = min(tiles_m - first, G);
+  const int w = t - group * per_group;
+  ti = first + w % gsize;
+  tj = w / gsize;
+}
+
+template <int BM, int BN, int BK, int MAXT, bool VEC>
+struct Fp64Tile {
+  static constexpr int NT = 256;
+  static constexpr int A_TPC = BM / 2;       // threads per A tile column (2 rows each)
+  static constexpr int A_CPP = NT / A_TPC;   // A tile columns per load pass
+  static constexpr int A_PASSES = BK / A_CPP;
+  static constexpr int B_TPC = BK / 2;       // threads per B tile column (2 k each)
+  static constexpr int B_CPP = NT / B_TPC;
+  static constexpr int B_PASSES = BN / B_CPP;
+  static constexpr int LDA_S = BM;
+  static constexpr int LDB_S = BN + 1;
+  static constexpr int WM = BM / 2, WN = BN / 2;
+  static constexpr int FM = WM / 16, FN = WN / 16;
+  static constexpr int A_STAGE = BK * LDA_S, B_STAGE = BK * LDB_S;
+  static constexpr int LDS_DOUBLES = 2 * (A_STAGE + B_STAGE);
+  static_assert(A_PASSES >= 1 && B_PASSES >= 1 && BK % 4 == 0 && A_CPP * A_PASSES == BK &&
+                    B_CPP * B_PASSES == BN,
+                "tile shape");
+
+  typedef d4_t Acc[FM][FN];
+
+  // Computes M = (sum_s delta_s X_s)(sum_t eps_t V_t) for the tile at (row0, col0) of the
+  // sub-block grid into acc.  lds: LDS_DOUBLES doubles.  Ends with a barrier, so the caller may
+  // reuse the LDS right away.
+  __device__ static void product(const GemmArgs& args, const ProdDesc& pd, int64_t row0,
+                                 int64_t col0, double* lds, Acc& acc) {
+    double* As = lds;
+    double* Bs = lds + 2 * A_STAGE;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int a_row = 2 * (tid % A_TPC), a_col = tid / A_TPC;
+    const int b_k = 2 * (tid % B_TPC), b_col = tid / B_TPC;
+    const int na = pd.na, nb = pd.nb;
+
+    // ---- per-term (wave-uniform) setup ----
+    const double* a_base[MAXT];
+    const double* b_base[MAXT];
+    int64_t a_rlim[MAXT], a_klim[MAXT], b_klim[MAXT], b_clim[MAXT];
+    bool a_neg[MAXT], b_neg[MAXT];
+    int64_t lda_e, ldb_e;
+    const double* a_safe;
+    const double* b_safe;
+    if (pd.flags & 1) {
+      lda_e = args.mq;
+      a_safe = args.TA;
+    } else {
+      lda_e = args.lda;
+      a_safe = args.A;
+    }
+    if (pd.flags & 2) {
+      ldb_e = args.kq;
+      b_safe = args.TB;
+    } else {
+      ldb_e = args.ldb;
+      b_safe = args.B;
+    }
+    int64_t kmin = args.kq;
+    bool rows_full = true, cols_full = true;   // (kept for the masked-path statistics below)
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      const uint8_t ca = s < na ? pd.a[s] : pd.a[0];
+      if (pd.flags & 1) {
+        a_base[s] = args.TA + (int64_t)pd.tslot_a * args.ta_stride;
+        a_rlim[s] = args.mq;
+        a_klim[s] = args.kq;
+        a_neg[s] = false;
+      } else {
+        const int64_t bi = code_row(ca), bp = code_col(ca);
+        a_base[s] = args.A + bi * args.mq + bp * args.kq * args.lda;
+        a_rlim[s] = min64(args.mq, args.m - bi * args.mq);
+        a_klim[s] = min64(args.kq, args.k - bp * args.kq);
+        a_neg[s] = code_neg(ca);
+      }
+      const uint8_t cb = s < nb ? pd.b[s] : pd.b[0];
+      if (pd.flags & 2) {
+        b_base[s] = args.TB + (int64_t)pd.tslot_b * args.tb_stride;
+        b_klim[s] = args.kq;
+        b_clim[s] = args.nq;
+        b_neg[s] = false;
+      } else {
+        const int64_t bp = code_row(cb), bj = code_col(cb);
+        b_base[s] = args.B + bp * args.kq + bj * args.nq * args.ldb;
+        b_klim[s] = min64(args.kq, args.k - bp * args.kq);
+        b_clim[s] = min64(args.nq, args.n - bj * args.nq);
+        b_neg[s] = code_neg(cb);
+      }
+      if (s < na) {
+        rows_full = rows_full && row0 + BM <= a_rlim[s];
+        kmin = min64(kmin, a_klim[s]);
+      }
+      if (s < nb) {
+        cols_full = cols_full && col0 + BN <= b_clim[s];
+        kmin = min64(kmin, b_klim[s]);
+      }
+    }
+    const bool tile_full = rows_full && cols_full;
+    const int nk = (int)((args.kq + BK - 1) / BK);
+
+    // ---- tile bases (uniform) and per-thread byte offsets shared by all terms ----
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      a_base[s] += row0;
+      b_base[s] += col0 * ldb_e;
+    }
+    uint32_t oa[A_PASSES], ob[B_PASSES];
+#pragma unroll
+    for (int p = 0; p < A_PASSES; ++p)
+      oa[p] = (uint32_t)(8 * (a_row + (int64_t)(a_col + p * A_CPP) * lda_e));
+#pragma unroll
+    for (int p = 0; p < B_PASSES; ++p)
+      ob[p] = (uint32_t)(8 * (b_k + (int64_t)(b_col + p * B_CPP) * ldb_e));
+    // valid rows of each A term and valid columns of each B term inside this tile
+    int a_rv[MAXT], b_cv[MAXT];
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      a_rv[s] = (int)min64(BM, a_rlim[s] - row0);
+      b_cv[s] = (int)min64(BN, b_clim[s] - col0);
+    }
+    (void)a_safe;
+    (void)b_safe;
+    (void)kmin;
+    (void)tile_full;
+
+    d2_t ra[MAXT][A_PASSES], rb[MAXT][B_PASSES];
+
+    // Global loads of k step kt for every term.  Buffer loads: an out-of-range position gets
+    // an offset past the buffer's range and the hardware returns zero, so there is no branch
+    // and every load stays in flight across the MFMA stage.
+    auto load_stage = [&](int kt) {
+      const int64_t kb = (int64_t)kt * BK;
+#pragma unroll
+      for (int s = 0; s < MAXT; ++s) {
+        if (s < na) {
+          const __amdgpu_buffer_rsrc_t rs = make_rsrc(a_base[s] + kb * lda_e);
+          const int kv = (int)min64(BK, a_klim[s] - kb);
+          const bool r0 = a_row < a_rv[s], r1 = a_row + 1 < a_rv[s];
+#pragma unroll
+          for (int p = 0; p < A_PASSES; ++p) {
+            const bool kok = a_col + p * A_CPP < kv;
+            if (VEC) {
+              ra[s][p] = load2(rs, (kok && r0) ? oa[p] : kOOB);
+            } else {
+              ra[s][p] = (d2_t){load1(rs, (kok && r0) ? oa[p] : kOOB),
+                                load1(rs, (kok && r1) ? oa[p] + 8 : kOOB)};
+            }
+          }
+        }
+        if (s < nb) {
+          const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb);
+          const int kv = (int)min64(BK, b_klim[s] - kb);
+          const bool k0 = b_k < kv, k1 = b_k + 1 < kv;
+#pragma unroll
+          for (int p = 0; p < B_PASSES; ++p) {
+            const bool cok = b_col + p * B_CPP < b_cv[s];
+            if (VEC) {
+              rb[s][p] = load2(rs, (cok && k0) ? ob[p] : kOOB);
+            } else {
+              rb[s][p] = (d2_t){load1(rs, (cok && k0) ? ob[p] : kOOB),
+                                load1(rs, (cok && k1) ? ob[p] + 8 : kOOB)};
+            }
+          }
+        }
+      }
+    };
+
+    // Signed sums in registers, then into LDS stage `buf`.
+    auto store_stage = [&](int buf) {
+#pragma unroll
+      for (int p = 0; p < A_PASSES; ++p) {
+        double v0 = sum_first(ra[0][p].x, a_neg[0]);
+        double v1 = sum_first(ra[0][p].y, a_neg[0]);
+#pragma unroll
+        for (int s = 1; s < MAXT; ++s)
+          if (s < na) {
+            v0 = sum_next(v0, ra[s][p].x, a_neg[s]);
+            v1 = sum_next(v1, ra[s][p].y, a_neg[s]);
+          }
+        *reinterpret_cast<d2_t*>(&As[buf * A_STAGE + (a_col + p * A_CPP) * LDA_S + a_row]) =
+            (d2_t){v0, v1};
+      }
+#pragma unroll
+      for (int p = 0; p < B_PASSES; ++p) {
+        double v0 = sum_first(rb[0][p].x, b_neg[0]);
+        double v1 = sum_first(rb[0][p].y, b_neg[0]);
+#pragma unroll
+        for (int s = 1; s < MAXT; ++s)
+          if (s < nb) {
+            v0 = sum_next(v0, rb[s][p].x, b_neg[s]);
+            v1 = sum_next(v1, rb[s][p].y, b_neg[s]);
+          }
+        const int j = b_col + p * B_CPP;
+        Bs[buf * B_STAGE + b_k * LDB_S + j] = v0;
+        Bs[buf * B_STAGE + (b_k + 1) * LDB_S + j] = v1;
+      }
+    };
+
+    auto mfma_stage = [&](int buf) {
+      const double* as = As + buf * A_STAGE + wm * WM + (lane & 15);
+      const double* bs = Bs + buf * B_STAGE + wn * WN + (lane & 15);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double af[FM], bf[FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) af[fm] = as[kr * LDA_S + fm * 16];
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) bf[fn] = bs[kr * LDB_S + fn * 16];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < FN; ++fn)
+            acc[fm][fn] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(bf[fn], af[fm], acc[fm][fn], 0, 0, 0);
+      }
+    };
+
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = (d4_t){0.0, 0.0, 0.0, 0.0};
+
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) load_stage(kt + 1);
+      mfma_stage(cur);
+      if (kt + 1 < nk) store_stage(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // Accumulator element (fm, fn, e) of this lane sits at tile row  wm*WM + fm*16 + lane%16  and
+  // tile column  wn*WN + fn*16 + lane/16 + 4e.  The epilogues address it as a per-lane byte
+  // offset (voffset, range-checked: kOOB drops the access) plus a wave-uniform byte offset
+  // (soffset) of fm*16 + (fn*16 + 4e)*ld elements.
+
+  // ABC epilogue: C_d[tile] := c_update(C_d[tile], M, alpha*gamma_d) for every destination.
+  __device__ static void update_c(const GemmArgs& args, const ProdDesc& pd, int64_t row0,
+                                  int64_t col0, const Acc& acc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = (wave & 1) * WM + (lane & 15);        // tile row of fm = 0
+    const int lc = (wave >> 1) * WN + (lane >> 4);       // tile column of fn = 0, e = 0
+    const int64_t ldc = args.ldc;
+    const uint32_t voff = (uint32_t)(8 * (lr + (int64_t)lc * ldc));
+    for (int d = 0; d < pd.nc; ++d) {
+      const uint8_t cc = pd.c[d];
+      const int64_t ci = code_row(cc), cj = code_col(cc);
+      const double ag = code_neg(cc) ? -args.alpha : args.alpha;
+      const bool first = (pd.first >> d) & 1;
+      const bool read_c = !(first && args.beta == 0.0);
+      const int rlim = (int)min64(BM, min64(args.mq, args.m - ci * args.mq) - row0);
+      const int clim = (int)min64(BN, min64(args.nq, args.n - cj * args.nq) - col0);
+      const __amdgpu_buffer_rsrc_t rs =
+          make_rsrc(args.C + (ci * args.mq + row0) + (cj * args.nq + col0) * ldc);
+#pragma unroll
+      for (int fm = 0; fm < FM; ++fm) {
+        const bool rok = lr + fm * 16 < rlim;
+        double cv[FN][4];
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = rok && lc + fn * 16 + 4 * e < clim && read_c;
+            const uint32_t so = (uint32_t)(8 * (fm * 16 + (int64_t)(fn * 16 + 4 * e) * ldc));
+            cv[fn][e] = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(rs, ok ? voff : kOOB, so, 0));
+          }
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = rok && lc + fn * 16 + 4 * e < clim;
+            const uint32_t so = (uint32_t)(8 * (fm * 16 + (int64_t)(fn * 16 + 4 * e) * ldc));
+            const double v = c_update(cv[fn][e], acc[fm][fn][e], ag, args.beta, first);
+            __builtin_amdgcn_raw_buffer_store_b64(as_u2(v), rs, ok ? voff : kOOB, so, 0);
+          }
+      }
+    }
+  }
+
+  // AB / Naive epilogue: store M_r (unscaled) to its temporary.
+  __device__ static void store_m(const GemmArgs& args, int r, int64_t row0, int64_t col0,
+                                 const Acc& acc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = (wave & 1) * WM + (lane & 15);
+    const int lc = (wave >> 1) * WN + (lane >> 4);
+    const int64_t ldm = args.ldm;
+    const uint32_t voff = (uint32_t)(8 * (lr + (int64_t)lc * ldm));
+    const int rlim = (int)min64(BM, args.mq - row0), clim = (int)min64(BN, args.nq - col0);
+    const __amdgpu_buffer_rsrc_t rs =
+        make_rsrc(args.M + (int64_t)r * args.m_stride + row0 + col0 * ldm);
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = lr + fm * 16 < rlim && lc + fn * 16 + 4 * e < clim;
+          const uint32_t so = (uint32_t)(8 * (fm * 16 + (int64_t)(fn * 16 + 4 * e) * ldm));
+          __builtin_amdgcn_raw_buffer_store_b64(as_u2(acc[fm][fn][e]), rs, ok ? voff : kOOB,
+                                                so, 0);
+        }
+  }
+};
+
+}  // namespace smx

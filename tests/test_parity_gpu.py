@@ -178,3 +178,24 @@ def test_caller_workspace():
         assert np.array_equal(sx.to_host(dC), C)   # untouched
     finally:
         sx.set_workspace(None)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_every_tile_config_bitwise_and_exact(cfg, levels):
+    """Every tile configuration gives the oracle's exact integer result and, on reals, the
+    same bits as the automatic choice (per-element arithmetic does not depend on the tile)."""
+    m, n, k = 1100, 1030, 1210
+    print(f"case tile cfg {cfg} L={levels}", flush=True)
+    A, B, C = W.problem(9, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    Ar, Br, Cr = W.problem(10, m, n, k, "uniform")
+    try:
+        sx.set_tile_config(-1)
+        auto = [run(Ar, Br, Cr, 1.0, 1.0, levels, v) for v in (VARIANTS if levels else ["abc"])]
+        sx.set_tile_config(cfg)
+        for i, v in enumerate(VARIANTS if levels else ["abc"]):
+            assert np.array_equal(run(A, B, C, 1.0, 1.0, levels, v), ref), v
+            assert np.array_equal(run(Ar, Br, Cr, 1.0, 1.0, levels, v), auto[i]), v
+    finally:
+        sx.set_tile_config(-1)
