@@ -221,36 +221,40 @@ struct Fp64Tile {
     // and every load stays in flight across the MFMA stage.
     auto load_stage = [&](int kt) {
       const int64_t kb = (int64_t)kt * BK;
+      // Every term slot is loaded unconditionally (a slot past the product's term count gets
+      // the out-of-range offset): a branch around the loads would make the compiler wait for
+      // the loads already in flight before issuing the next ones.
 #pragma unroll
       for (int s = 0; s < MAXT; ++s) {
-        if (s < na) {
-          const __amdgpu_buffer_rsrc_t rs = make_rsrc(a_base[s] + kb * lda_e);
-          const int kv = (int)min64(BK, a_klim[s] - kb);
-          const bool r0 = a_row < a_rv[s], r1 = a_row + 1 < a_rv[s];
+        const bool live = s < na;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(a_base[s] + kb * lda_e);
+        const int kv = live ? (int)min64(BK, a_klim[s] - kb) : 0;
+        const bool r0 = a_row < a_rv[s], r1 = a_row + 1 < a_rv[s];
 #pragma unroll
-          for (int p = 0; p < A_PASSES; ++p) {
-            const bool kok = a_col + p * A_CPP < kv;
-            if (VEC) {
-              ra[s][p] = load2(rs, (kok && r0) ? oa[p] : kOOB);
-            } else {
-              ra[s][p] = (d2_t){load1(rs, (kok && r0) ? oa[p] : kOOB),
-                                load1(rs, (kok && r1) ? oa[p] + 8 : kOOB)};
-            }
+        for (int p = 0; p < A_PASSES; ++p) {
+          const bool kok = a_col + p * A_CPP < kv;
+          if (VEC) {
+            ra[s][p] = load2(rs, (kok && r0) ? oa[p] : kOOB);
+          } else {
+            ra[s][p] = (d2_t){load1(rs, (kok && r0) ? oa[p] : kOOB),
+                              load1(rs, (kok && r1) ? oa[p] + 8 : kOOB)};
           }
         }
-        if (s < nb) {
-          const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb);
-          const int kv = (int)min64(BK, b_klim[s] - kb);
-          const bool k0 = b_k < kv, k1 = b_k + 1 < kv;
+      }
 #pragma unroll
-          for (int p = 0; p < B_PASSES; ++p) {
-            const bool cok = b_col + p * B_CPP < b_cv[s];
-            if (VEC) {
-              rb[s][p] = load2(rs, (cok && k0) ? ob[p] : kOOB);
-            } else {
-              rb[s][p] = (d2_t){load1(rs, (cok && k0) ? ob[p] : kOOB),
-                                load1(rs, (cok && k1) ? ob[p] + 8 : kOOB)};
-            }
+      for (int s = 0; s < MAXT; ++s) {
+        const bool live = s < nb;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb);
+        const int kv = live ? (int)min64(BK, b_klim[s] - kb) : 0;
+        const bool k0 = b_k < kv, k1 = b_k + 1 < kv;
+#pragma unroll
+        for (int p = 0; p < B_PASSES; ++p) {
+          const bool cok = b_col + p * B_CPP < b_cv[s];
+          if (VEC) {
+            rb[s][p] = load2(rs, (cok && k0) ? ob[p] : kOOB);
+          } else {
+            rb[s][p] = (d2_t){load1(rs, (cok && k0) ? ob[p] : kOOB),
+                              load1(rs, (cok && k1) ? ob[p] + 8 : kOOB)};
           }
         }
       }
@@ -263,11 +267,10 @@ struct Fp64Tile {
         double v0 = sum_first(ra[0][p].x, a_neg[0]);
         double v1 = sum_first(ra[0][p].y, a_neg[0]);
 #pragma unroll
-        for (int s = 1; s < MAXT; ++s)
-          if (s < na) {
-            v0 = sum_next(v0, ra[s][p].x, a_neg[s]);
-            v1 = sum_next(v1, ra[s][p].y, a_neg[s]);
-          }
+        for (int s = 1; s < MAXT; ++s) {
+          v0 = s < na ? sum_next(v0, ra[s][p].x, a_neg[s]) : v0;
+          v1 = s < na ? sum_next(v1, ra[s][p].y, a_neg[s]) : v1;
+        }
         *reinterpret_cast<d2_t*>(&As[buf * A_STAGE + (a_col + p * A_CPP) * LDA_S + a_row]) =
             (d2_t){v0, v1};
       }
@@ -276,11 +279,10 @@ struct Fp64Tile {
         double v0 = sum_first(rb[0][p].x, b_neg[0]);
         double v1 = sum_first(rb[0][p].y, b_neg[0]);
 #pragma unroll
-        for (int s = 1; s < MAXT; ++s)
-          if (s < nb) {
-            v0 = sum_next(v0, rb[s][p].x, b_neg[s]);
-            v1 = sum_next(v1, rb[s][p].y, b_neg[s]);
-          }
+        for (int s = 1; s < MAXT; ++s) {
+          v0 = s < nb ? sum_next(v0, rb[s][p].x, b_neg[s]) : v0;
+          v1 = s < nb ? sum_next(v1, rb[s][p].y, b_neg[s]) : v1;
+        }
         const int j = b_col + p * B_CPP;
         Bs[buf * B_STAGE + b_k * LDB_S + j] = v0;
         Bs[buf * B_STAGE + (b_k + 1) * LDB_S + j] = v1;
