@@ -188,6 +188,15 @@ struct Fp64Tile {
     }
     const bool tile_full = rows_full && cols_full;
     const int nk = (int)((args.kq + BK - 1) / BK);
+    // Sum coefficients: +-1 for a live term, -0.0 for an absent one.  fma(+-1, x, v) rounds
+    // exactly like v +- x, and fma(-0.0, 0.0, v) == v bit for bit (also for v == -0.0); an
+    // absent term's loads return +0.0.
+    double a_sg[MAXT], b_sg[MAXT];
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      a_sg[s] = s < na ? (a_neg[s] ? -1.0 : 1.0) : -0.0;
+      b_sg[s] = s < nb ? (b_neg[s] ? -1.0 : 1.0) : -0.0;
+    }
 
     // ---- tile bases (uniform) and per-thread byte offsets shared by all terms ----
 #pragma unroll
@@ -260,28 +269,29 @@ struct Fp64Tile {
       }
     };
 
-    // Signed sums in registers, then into LDS stage `buf`.
-    auto store_stage = [&](int buf) {
+    // Signed sums in registers, then into LDS stage `buf`.  The first term is scaled by its
+    // sign (exact), each further term is added with one FMA.
+    auto store_a = [&](int buf) {
 #pragma unroll
       for (int p = 0; p < A_PASSES; ++p) {
-        double v0 = sum_first(ra[0][p].x, a_neg[0]);
-        double v1 = sum_first(ra[0][p].y, a_neg[0]);
+        double v0 = a_sg[0] * ra[0][p].x, v1 = a_sg[0] * ra[0][p].y;
 #pragma unroll
         for (int s = 1; s < MAXT; ++s) {
-          v0 = s < na ? sum_next(v0, ra[s][p].x, a_neg[s]) : v0;
-          v1 = s < na ? sum_next(v1, ra[s][p].y, a_neg[s]) : v1;
+          v0 = __builtin_fma(a_sg[s], ra[s][p].x, v0);
+          v1 = __builtin_fma(a_sg[s], ra[s][p].y, v1);
         }
         *reinterpret_cast<d2_t*>(&As[buf * A_STAGE + (a_col + p * A_CPP) * LDA_S + a_row]) =
             (d2_t){v0, v1};
       }
+    };
+    auto store_b = [&](int buf) {
 #pragma unroll
       for (int p = 0; p < B_PASSES; ++p) {
-        double v0 = sum_first(rb[0][p].x, b_neg[0]);
-        double v1 = sum_first(rb[0][p].y, b_neg[0]);
+        double v0 = b_sg[0] * rb[0][p].x, v1 = b_sg[0] * rb[0][p].y;
 #pragma unroll
         for (int s = 1; s < MAXT; ++s) {
-          v0 = s < nb ? sum_next(v0, rb[s][p].x, b_neg[s]) : v0;
-          v1 = s < nb ? sum_next(v1, rb[s][p].y, b_neg[s]) : v1;
+          v0 = __builtin_fma(b_sg[s], rb[s][p].x, v0);
+          v1 = __builtin_fma(b_sg[s], rb[s][p].y, v1);
         }
         const int j = b_col + p * B_CPP;
         Bs[buf * B_STAGE + b_k * LDB_S + j] = v0;
@@ -289,24 +299,21 @@ struct Fp64Tile {
       }
     };
 
-    auto mfma_stage = [&](int buf) {
+    // One k sub-step (k = 4): FM x FN MFMAs on fragments read from LDS stage `buf`.
+    auto mfma_substep = [&](int buf, int ks) {
       const double* as = As + buf * A_STAGE + wm * WM + (lane & 15);
       const double* bs = Bs + buf * B_STAGE + wn * WN + (lane & 15);
+      const int kr = ks * 4 + (lane >> 4);
+      double af[FM], bf[FN];
 #pragma unroll
-      for (int ks = 0; ks < BK / 4; ++ks) {
-        const int kr = ks * 4 + (lane >> 4);
-        double af[FM], bf[FN];
+      for (int fm = 0; fm < FM; ++fm) af[fm] = as[kr * LDA_S + fm * 16];
 #pragma unroll
-        for (int fm = 0; fm < FM; ++fm) af[fm] = as[kr * LDA_S + fm * 16];
+      for (int fn = 0; fn < FN; ++fn) bf[fn] = bs[kr * LDB_S + fn * 16];
 #pragma unroll
-        for (int fn = 0; fn < FN; ++fn) bf[fn] = bs[kr * LDB_S + fn * 16];
+      for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
-        for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-          for (int fn = 0; fn < FN; ++fn)
-            acc[fm][fn] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(bf[fn], af[fm], acc[fm][fn], 0, 0, 0);
-      }
+        for (int fn = 0; fn < FN; ++fn)
+          acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[fn], af[fm], acc[fm][fn], 0, 0, 0);
     };
 
 #pragma unroll
@@ -314,16 +321,33 @@ struct Fp64Tile {
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
+    // Software pipeline.  At the top of iteration kt the registers hold the raw terms of step
+    // kt+1, loaded during iteration kt-1.  Their sums go to the other LDS stage while the first
+    // sub-steps of step kt run on the MFMA (no wait: the data is already there), then the loads
+    // of step kt+2 are issued into the freed registers and the remaining sub-steps run.
+    constexpr int KS = BK / 4;
     load_stage(0);
-    store_stage(0);
+    store_a(0);
+    store_b(0);
+    load_stage(1);   // past the end of k every position is out of range: no memory access
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
+    for (int kt = 0; kt + 1 < nk; ++kt) {
       const int cur = kt & 1;
-      if (kt + 1 < nk) load_stage(kt + 1);
-      mfma_stage(cur);
-      if (kt + 1 < nk) store_stage(cur ^ 1);
+      mfma_substep(cur, 0);
+      store_a(cur ^ 1);
+      if (KS > 1) mfma_substep(cur, 1);
+      store_b(cur ^ 1);
+      // keep the next loads after the sums: hoisting them would keep two stages of raw
+      // terms live at once
+      asm volatile("" ::: "memory");
+      load_stage(kt + 2);
+#pragma unroll
+      for (int ks = 2; ks < KS; ++ks) mfma_substep(cur, ks);
       __syncthreads();
     }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) mfma_substep((nk - 1) & 1, ks);
+    __syncthreads();
   }
 
   // Accumulator element (fm, fn, e) of this lane sits at tile row  wm*WM + fm*16 + lane%16  and
