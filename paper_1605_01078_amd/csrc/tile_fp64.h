@@ -114,96 +114,81 @@ struct Fp64Tile {
 
   // Computes M = (sum_s delta_s X_s)(sum_t eps_t V_t) for the tile at (row0, col0) of the
   // sub-block grid into acc.  lds: LDS_DOUBLES doubles.  Ends with a barrier, so the caller may
-  // reuse the LDS right away.
+  // reuse the LDS right away.  The term counts select a loop specialised for them (a uniform
+  // branch per product), so no k step carries work for absent terms.
   __device__ static void product(const GemmArgs& args, const ProdDesc& pd, int64_t row0,
                                  int64_t col0, double* lds, Acc& acc) {
+    const int na = (pd.flags & 1) ? 1 : pd.na, nb = (pd.flags & 2) ? 1 : pd.nb;
+    if (MAXT == 1 || (na == 1 && nb == 1)) return product_n<1, 1>(args, pd, row0, col0, lds, acc);
+    if (MAXT >= 2) {
+      if (na == 2 && nb == 2) return product_n<2, 2>(args, pd, row0, col0, lds, acc);
+      if (na == 2 && nb == 1) return product_n<2, 1>(args, pd, row0, col0, lds, acc);
+      if (na == 1 && nb == 2) return product_n<1, 2>(args, pd, row0, col0, lds, acc);
+    }
+    if (MAXT >= 4) {
+      if (na == 4 && nb == 4) return product_n<4, 4>(args, pd, row0, col0, lds, acc);
+      if (na == 4 && nb == 2) return product_n<4, 2>(args, pd, row0, col0, lds, acc);
+      if (na == 2 && nb == 4) return product_n<2, 4>(args, pd, row0, col0, lds, acc);
+      if (na == 4 && nb == 1) return product_n<4, 1>(args, pd, row0, col0, lds, acc);
+      if (na == 1 && nb == 4) return product_n<1, 4>(args, pd, row0, col0, lds, acc);
+    }
+  }
+
+  template <int NA, int NB>
+  __device__ static void product_n(const GemmArgs& args, const ProdDesc& pd, int64_t row0,
+                                   int64_t col0, double* lds, Acc& acc) {
     double* As = lds;
     double* Bs = lds + 2 * A_STAGE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int a_row = 2 * (tid % A_TPC), a_col = tid / A_TPC;
     const int b_k = 2 * (tid % B_TPC), b_col = tid / B_TPC;
-    const int na = pd.na, nb = pd.nb;
 
-    // ---- per-term (wave-uniform) setup ----
-    const double* a_base[MAXT];
-    const double* b_base[MAXT];
-    int64_t a_rlim[MAXT], a_klim[MAXT], b_klim[MAXT], b_clim[MAXT];
-    bool a_neg[MAXT], b_neg[MAXT];
-    int64_t lda_e, ldb_e;
-    const double* a_safe;
-    const double* b_safe;
-    if (pd.flags & 1) {
-      lda_e = args.mq;
-      a_safe = args.TA;
-    } else {
-      lda_e = args.lda;
-      a_safe = args.A;
-    }
-    if (pd.flags & 2) {
-      ldb_e = args.kq;
-      b_safe = args.TB;
-    } else {
-      ldb_e = args.ldb;
-      b_safe = args.B;
-    }
-    int64_t kmin = args.kq;
-    bool rows_full = true, cols_full = true;   // (kept for the masked-path statistics below)
+    // ---- per-term (wave-uniform) setup: base pointer of the tile, valid extents, sign ----
+    const double* a_base[NA];
+    const double* b_base[NB];
+    int64_t a_klim[NA], b_klim[NB];
+    int a_rv[NA], b_cv[NB];             // valid rows / columns of the term inside this tile
+    double a_sg[NA], b_sg[NB];
+    const int64_t lda_e = (pd.flags & 1) ? args.mq : args.lda;
+    const int64_t ldb_e = (pd.flags & 2) ? args.kq : args.ldb;
 #pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-      const uint8_t ca = s < na ? pd.a[s] : pd.a[0];
-      if (pd.flags & 1) {
+    for (int s = 0; s < NA; ++s) {
+      if (pd.flags & 1) {  // Naive temporary: zero-padded to the full sub-block
         a_base[s] = args.TA + (int64_t)pd.tslot_a * args.ta_stride;
-        a_rlim[s] = args.mq;
+        a_rv[s] = (int)min64(BM, args.mq - row0);
         a_klim[s] = args.kq;
-        a_neg[s] = false;
+        a_sg[s] = 1.0;
       } else {
-        const int64_t bi = code_row(ca), bp = code_col(ca);
+        const uint8_t c = pd.a[s];
+        const int64_t bi = code_row(c), bp = code_col(c);
         a_base[s] = args.A + bi * args.mq + bp * args.kq * args.lda;
-        a_rlim[s] = min64(args.mq, args.m - bi * args.mq);
+        a_rv[s] = (int)min64(BM, min64(args.mq, args.m - bi * args.mq) - row0);
         a_klim[s] = min64(args.kq, args.k - bp * args.kq);
-        a_neg[s] = code_neg(ca);
+        a_sg[s] = code_neg(c) ? -1.0 : 1.0;
       }
-      const uint8_t cb = s < nb ? pd.b[s] : pd.b[0];
+      a_base[s] += row0;
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
       if (pd.flags & 2) {
         b_base[s] = args.TB + (int64_t)pd.tslot_b * args.tb_stride;
+        b_cv[s] = (int)min64(BN, args.nq - col0);
         b_klim[s] = args.kq;
-        b_clim[s] = args.nq;
-        b_neg[s] = false;
+        b_sg[s] = 1.0;
       } else {
-        const int64_t bp = code_row(cb), bj = code_col(cb);
+        const uint8_t c = pd.b[s];
+        const int64_t bp = code_row(c), bj = code_col(c);
         b_base[s] = args.B + bp * args.kq + bj * args.nq * args.ldb;
+        b_cv[s] = (int)min64(BN, min64(args.nq, args.n - bj * args.nq) - col0);
         b_klim[s] = min64(args.kq, args.k - bp * args.kq);
-        b_clim[s] = min64(args.nq, args.n - bj * args.nq);
-        b_neg[s] = code_neg(cb);
+        b_sg[s] = code_neg(c) ? -1.0 : 1.0;
       }
-      if (s < na) {
-        rows_full = rows_full && row0 + BM <= a_rlim[s];
-        kmin = min64(kmin, a_klim[s]);
-      }
-      if (s < nb) {
-        cols_full = cols_full && col0 + BN <= b_clim[s];
-        kmin = min64(kmin, b_klim[s]);
-      }
-    }
-    const bool tile_full = rows_full && cols_full;
-    const int nk = (int)((args.kq + BK - 1) / BK);
-    // Sum coefficients: +-1 for a live term, -0.0 for an absent one.  fma(+-1, x, v) rounds
-    // exactly like v +- x, and fma(-0.0, 0.0, v) == v bit for bit (also for v == -0.0); an
-    // absent term's loads return +0.0.
-    double a_sg[MAXT], b_sg[MAXT];
-#pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-      a_sg[s] = s < na ? (a_neg[s] ? -1.0 : 1.0) : -0.0;
-      b_sg[s] = s < nb ? (b_neg[s] ? -1.0 : 1.0) : -0.0;
-    }
-
-    // ---- tile bases (uniform) and per-thread byte offsets shared by all terms ----
-#pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-      a_base[s] += row0;
       b_base[s] += col0 * ldb_e;
     }
+    const int nk = (int)((args.kq + BK - 1) / BK);
+
+    // per-thread byte offsets inside a tile, shared by all terms
     uint32_t oa[A_PASSES], ob[B_PASSES];
 #pragma unroll
     for (int p = 0; p < A_PASSES; ++p)
@@ -211,33 +196,19 @@ struct Fp64Tile {
 #pragma unroll
     for (int p = 0; p < B_PASSES; ++p)
       ob[p] = (uint32_t)(8 * (b_k + (int64_t)(b_col + p * B_CPP) * ldb_e));
-    // valid rows of each A term and valid columns of each B term inside this tile
-    int a_rv[MAXT], b_cv[MAXT];
-#pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-      a_rv[s] = (int)min64(BM, a_rlim[s] - row0);
-      b_cv[s] = (int)min64(BN, b_clim[s] - col0);
-    }
-    (void)a_safe;
-    (void)b_safe;
-    (void)kmin;
-    (void)tile_full;
 
-    d2_t ra[MAXT][A_PASSES], rb[MAXT][B_PASSES];
+    d2_t ra[NA][A_PASSES], rb[NB][B_PASSES];
 
-    // Global loads of k step kt for every term.  Buffer loads: an out-of-range position gets
-    // an offset past the buffer's range and the hardware returns zero, so there is no branch
-    // and every load stays in flight across the MFMA stage.
+    // Global loads of k step kt for every term.  Buffer loads: an out-of-range position (fringe
+    // of the matrix or of its sub-block, or a k step past the end) gets an offset past the
+    // buffer's range and the hardware returns zero without touching memory, so the loads need
+    // no branch and all stay in flight across the MFMA work.
     auto load_stage = [&](int kt) {
       const int64_t kb = (int64_t)kt * BK;
-      // Every term slot is loaded unconditionally (a slot past the product's term count gets
-      // the out-of-range offset): a branch around the loads would make the compiler wait for
-      // the loads already in flight before issuing the next ones.
 #pragma unroll
-      for (int s = 0; s < MAXT; ++s) {
-        const bool live = s < na;
+      for (int s = 0; s < NA; ++s) {
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(a_base[s] + kb * lda_e);
-        const int kv = live ? (int)min64(BK, a_klim[s] - kb) : 0;
+        const int kv = (int)min64(BK, a_klim[s] - kb);
         const bool r0 = a_row < a_rv[s], r1 = a_row + 1 < a_rv[s];
 #pragma unroll
         for (int p = 0; p < A_PASSES; ++p) {
@@ -251,10 +222,9 @@ struct Fp64Tile {
         }
       }
 #pragma unroll
-      for (int s = 0; s < MAXT; ++s) {
-        const bool live = s < nb;
+      for (int s = 0; s < NB; ++s) {
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb);
-        const int kv = live ? (int)min64(BK, b_klim[s] - kb) : 0;
+        const int kv = (int)min64(BK, b_klim[s] - kb);
         const bool k0 = b_k < kv, k1 = b_k + 1 < kv;
 #pragma unroll
         for (int p = 0; p < B_PASSES; ++p) {
@@ -269,14 +239,15 @@ struct Fp64Tile {
       }
     };
 
-    // Signed sums in registers, then into LDS stage `buf`.  The first term is scaled by its
-    // sign (exact), each further term is added with one FMA.
+    // Signed sums in registers, then into LDS stage `buf`.  The first term is scaled by its sign
+    // (exact), each further term is added with one FMA: fma(+-1, x, v) rounds exactly like
+    // v +- x, the rounding the Naive operand-sum kernel performs.
     auto store_a = [&](int buf) {
 #pragma unroll
       for (int p = 0; p < A_PASSES; ++p) {
         double v0 = a_sg[0] * ra[0][p].x, v1 = a_sg[0] * ra[0][p].y;
 #pragma unroll
-        for (int s = 1; s < MAXT; ++s) {
+        for (int s = 1; s < NA; ++s) {
           v0 = __builtin_fma(a_sg[s], ra[s][p].x, v0);
           v1 = __builtin_fma(a_sg[s], ra[s][p].y, v1);
         }
@@ -289,7 +260,7 @@ struct Fp64Tile {
       for (int p = 0; p < B_PASSES; ++p) {
         double v0 = b_sg[0] * rb[0][p].x, v1 = b_sg[0] * rb[0][p].y;
 #pragma unroll
-        for (int s = 1; s < MAXT; ++s) {
+        for (int s = 1; s < NB; ++s) {
           v0 = __builtin_fma(b_sg[s], rb[s][p].x, v0);
           v1 = __builtin_fma(b_sg[s], rb[s][p].y, v1);
         }
@@ -322,9 +293,9 @@ struct Fp64Tile {
       for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
     // Software pipeline.  At the top of iteration kt the registers hold the raw terms of step
-    // kt+1, loaded during iteration kt-1.  Their sums go to the other LDS stage while the first
-    // sub-steps of step kt run on the MFMA (no wait: the data is already there), then the loads
-    // of step kt+2 are issued into the freed registers and the remaining sub-steps run.
+    // kt+1, loaded during iteration kt-1.  Their sums go to the other LDS stage between the
+    // first sub-steps of step kt (no wait: the data is already there), then the loads of step
+    // kt+2 are issued into the freed registers and the remaining sub-steps run.
     constexpr int KS = BK / 4;
     load_stage(0);
     store_a(0);
