@@ -1,0 +1,251 @@
+"""Benchmark: Strassen DGEMM on one MI355X (gfx950), effective TFLOPS = 2mnk / time.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384] [--levels 2] [--variant abc]
+
+One step is one call C := A*B + C of the library at m = n = k = n (default 16384, FP64, entries
+uniform on [-1, 1], inputs resident in HBM) with `levels` levels of Strassen in the given variant
+(default: two-level ABC, whose single kernel launch is the step).  Printed as ONE JSON line:
+the headline value plus, measured in the same run,
+  * the library's own classical FP64 MFMA GEMM (levels = 0) and every (levels, variant) pair,
+    timed with HIP events, with the speedup over classical;
+  * the relative Frobenius error of the headline result against the CPU oracle on sampled
+    columns (and of the classical result), checked against 1e-12 (one level) / 1e-11 (two);
+  * roofline of the dominant kernel (the FP64 tile kernel): executed MFMA flops per launch over
+    its average duration, against the 78.6 TFLOP/s FP64 matrix peak; `traffic` comes from the
+    committed rocprofv3 counter summary when it was taken on the current kernel source;
+  * cpu_baseline: the oracle's plain triple-loop GEMM timed on the host cores over a bounded
+    column sample of the same problem.
+Diagnostics go to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective TFLOPS (2mnk/t), Strassen vs own classical GEMM, at stated rel error"
+PEAK_F64_MFMA = 78.6   # TFLOP/s, MI355X datasheet, dense FP64 matrix
+TOL = {0: None, 1: 1e-12, 2: 1e-11}
+KERNEL_SOURCES = ["paper_1605_01078_amd/csrc/tile_fp64.h", "paper_1605_01078_amd/csrc/kernels_fp64.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=16384)
+    p.add_argument("--levels", type=int, default=2)
+    p.add_argument("--variant", default="abc")
+    p.add_argument("--no-compare", action="store_true", help="skip the per-variant table")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    p.add_argument("--no-parity", action="store_true", help="skip the sampled oracle check")
+    p.add_argument("--cpu-seconds", type=float, default=20.0)
+    return p.parse_args()
+
+
+def timed(fn, reps, stream):
+    """Median milliseconds of `reps` calls, each bracketed by events on `stream`."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), ts
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this library has no multi-GPU path); got --gpus "
+              f"{args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1605_01078_amd as sx
+    import workloads as W
+
+    sx.lib()  # fails loudly if the HIP library is not built
+    dev = torch.cuda.current_device()
+    props = torch.cuda.get_device_properties(dev)
+    log(f"device: {props.name} {getattr(props, 'gcnArchName', '')} CUs={props.multi_processor_count}")
+    n, L, variant = args.n, args.levels, args.variant
+    stream = torch.cuda.current_stream()
+    A = W.device_uniform(1, n, n)
+    B = W.device_uniform(2, n, n)
+    C0 = W.device_uniform(3, n, n)
+    C = C0.clone()
+    flops = 2.0 * n * n * n
+    q = 2 ** L
+    nq = -(-n // q)
+    exec_flops = (7 ** L) * 2.0 * nq * nq * nq
+
+    def call(levels, var, Cm):
+        return lambda: sx.dgemm(A, B, Cm, 1.0, 1.0, levels, var, stream)
+
+    # ---- parity on sampled columns against the CPU oracle --------------------------------------
+    parity = {}
+    A_h = None
+    if not args.no_parity:
+        from oracle import oracle_dgemm, rel_fro
+        g = np.random.default_rng(0)
+        cols = np.sort(g.choice(n, size=4, replace=False))
+        A_h = sx.to_host(A)
+        Bc = np.asfortranarray(sx.to_host(B)[:, cols])
+        Cc = np.asfortranarray(sx.to_host(C0)[:, cols])
+        ref = oracle_dgemm(A_h, Bc, Cc.copy(order="F"), 1.0, 1.0)
+        for lev, var in ((0, "abc"), (L, variant)):
+            Ct = C0.clone()
+            sx.dgemm(A, B, Ct, 1.0, 1.0, lev, var, stream)
+            torch.cuda.synchronize()
+            got = Ct[:, torch.as_tensor(cols, device=Ct.device)].cpu().numpy()
+            err = float(rel_fro(got, ref))
+            parity[f"L{lev}_{var}"] = err
+            del Ct
+        tol = TOL[L]
+        parity["tolerance"] = tol
+        parity["columns"] = [int(c) for c in cols]
+        parity["pass"] = bool(tol is None or parity[f"L{L}_{variant}"] <= tol)
+        log(f"parity (rel Frobenius on sampled columns vs oracle): {parity}")
+
+    # ---- headline: warmup, then exactly K timed steps -------------------------------------------
+    step = call(L, variant, C)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    start_all = torch.cuda.Event(enable_timing=True)
+    end_all = torch.cuda.Event(enable_timing=True)
+    start_all.record(stream)
+    for e0, e1 in ev:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    end_all.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start_all.elapsed_time(end_all)
+    per_launch = [e0.elapsed_time(e1) for e0, e1 in ev]
+    ms_per_step = total_ms / args.steps
+    value = flops / (ms_per_step * 1e-3) * 1e-12
+    log(f"headline L={L} {variant}: {ms_per_step:.3f} ms/step, {value:.2f} effective TFLOP/s "
+        f"(wall {wall:.2f} s)")
+
+    # ---- classical and every variant (same inputs, outside the timed steps) --------------------
+    variants = {}
+    if not args.no_compare:
+        Cw = C0.clone()
+        pairs = [(0, "abc")] + [(lv, v) for lv in (1, 2) for v in ("abc", "ab", "naive")]
+        for lev, var in pairs:
+            f = call(lev, var, Cw)
+            f()
+            torch.cuda.synchronize()
+            ms, _ = timed(f, 3, stream)
+            variants[f"L{lev}_{var}"] = {"ms": round(ms, 3),
+                                         "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
+            log(f"  L={lev} {var:5s}: {ms:8.3f} ms  {variants[f'L{lev}_{var}']['tflops']:6.2f} TF")
+        base = variants["L0_abc"]["tflops"]
+        for key, v in variants.items():
+            v["speedup_vs_classical"] = round(v["tflops"] / base, 4)
+        del Cw
+        sx.release_workspace()
+
+    # ---- roofline of the dominant kernel --------------------------------------------------------
+    # The ABC step is one launch of the FP64 tile kernel, so its average duration is the event
+    # time around each step.  Executed MFMA flops per launch: 7^L products of 2*mq*nq*kq each.
+    avg_launch_ms = float(np.mean(per_launch))
+    achieved = exec_flops / (avg_launch_ms * 1e-3) * 1e-12
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"traffic_fp64_tile_L{L}_{variant}_{n}.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA, 4), "traffic": traffic,
+                "kernel": "fp64_tile_kernel (ABC)" if variant == "abc" else "fp64_tile_kernel",
+                "exec_flops_per_launch": exec_flops, "avg_launch_ms": round(avg_launch_ms, 3)}
+
+    # ---- CPU baseline: the oracle on a bounded column sample -----------------------------------
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle_dgemm
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        if A_h is None:
+            A_h = sx.to_host(A)
+        Bh = sx.to_host(B)
+        Ch = sx.to_host(C0)
+
+        def run_cols(ncols):
+            Bc = np.asfortranarray(Bh[:, :ncols])
+            Cc = np.asfortranarray(Ch[:, :ncols])
+            t = time.perf_counter()
+            oracle_dgemm(A_h, Bc, Cc, 1.0, 1.0)
+            return time.perf_counter() - t
+        probe_cols = 32
+        tp = run_cols(probe_cols)
+        ncols = int(max(probe_cols, min(n, probe_cols * args.cpu_seconds / max(tp, 1e-6))))
+        tc = run_cols(ncols)
+        cpu_tflops = 2.0 * n * n * ncols / tc * 1e-12
+        cpu = {"value": round(cpu_tflops, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+               "sample": f"plain triple-loop oracle (FP64, sequential sum over k) on A {n}x{n} times "
+                         f"the first {ncols} columns of B ({2.0 * n * n * ncols:.3e} flops, "
+                         f"{tc:.1f} s); rate scaled to TFLOP/s"}
+        log(f"cpu baseline: {cpu}")
+        del A_h, Bh, Ch
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"strassen_dgemm L={L} {variant.upper()} m=n=k={n} FP64 "
+                               f"C:=A*B+C, entries uniform[-1,1]",
+                   "m": n, "n": n, "k": n, "levels": L, "variant": variant,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "variants": variants,
+    }
+    if variants:
+        out["classical_tflops"] = variants["L0_abc"]["tflops"]
+        out["speedup_vs_classical"] = round(value / variants["L0_abc"]["tflops"], 4)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
