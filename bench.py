@@ -59,7 +59,64 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--no-parity", action="store_true", help="skip the sampled oracle check")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run a plain copy kernel of known size first (for HBM counter scaling)")
+    p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                   help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script "
+                        "with --copy-calibration into the traffic summary under profiles/, then exit")
     return p.parse_args()
+
+
+COPY_BYTES = 1 << 30   # the calibration copy reads and writes this many bytes
+
+
+def copy_calibration():
+    """Plain copy kernel of known size: y := -x over COPY_BYTES of doubles (reads COPY_BYTES,
+    writes COPY_BYTES)."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
+def traffic_summary(args):
+    """Per-launch HBM bytes of the tile kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by known/measured bytes of the calibration copy in the same run."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        tile, copy = [], []
+        for row in csv.DictReader(open(f)):
+            if row["Counter_Name"] != counter:
+                continue
+            v = float(row["Counter_Value"])
+            name = row["Kernel_Name"]
+            if "fp64_tile_kernel" in name:
+                tile.append(v)
+            elif "neg" in name:
+                copy.append(v)
+        return tile, copy
+    ft, fc = read(args.traffic_from[0], "FETCH_SIZE")
+    wt, wc = read(args.traffic_from[1], "WRITE_SIZE")
+    f_fetch = COPY_BYTES / (fc[-1] * 1024.0)
+    f_write = COPY_BYTES / (wc[-1] * 1024.0)
+    fetch = float(np.mean(ft)) * 1024.0 * f_fetch
+    write = float(np.mean(wt)) * 1024.0 * f_write
+    L, variant, n = args.levels, args.variant, args.n
+    out = {"kernel": "fp64_tile_kernel", "workload": f"L={L} {variant} m=n=k={n}",
+           "kernel_source_hash": kernel_source_hash(),
+           "fetch_kib_per_launch": float(np.mean(ft)), "write_kib_per_launch": float(np.mean(wt)),
+           "copy_fetch_kib": fc[-1], "copy_write_kib": wc[-1], "copy_bytes": COPY_BYTES,
+           "fetch_scale": f_fetch, "write_scale": f_write,
+           "hbm_bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write}
+    path = os.path.join(ROOT, "profiles", f"traffic_fp64_tile_L{L}_{variant}_{n}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    log(json.dumps(out, indent=1))
 
 
 def timed(fn, reps, stream):
@@ -79,6 +136,9 @@ def timed(fn, reps, stream):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_summary(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this library has no multi-GPU path); got --gpus "
               f"{args.gpus}", file=sys.stderr)
@@ -88,6 +148,8 @@ def main():
     import workloads as W
 
     sx.lib()  # fails loudly if the HIP library is not built
+    if args.copy_calibration:
+        copy_calibration()
     dev = torch.cuda.current_device()
     props = torch.cuda.get_device_properties(dev)
     log(f"device: {props.name} {getattr(props, 'gcnArchName', '')} CUs={props.multi_processor_count}")
