@@ -215,9 +215,8 @@ static Plan make_plan(int64_t m, int64_t n, int64_t k, int levels, int variant) 
   return p;
 }
 
-// Tile configuration: 128 x 128 when there are enough tiles to fill the 256 CUs twice over,
-// else 64 x 64.  Four-term tables (two levels) use the one-workgroup-per-CU variant, whose 512
-// registers per lane hold four quadrant tiles of staging beside the 128 x 128 accumulator.
+// Tile configuration: 128 x 128 (k step 16, two workgroups per CU) when there are enough tiles
+// to fill the 256 CUs twice over, else 64 x 64.
 // STRASSEN_TILE_CFG=<0..3> forces one configuration (used by the tuning sweeps).
 static std::atomic<int> g_forced_cfg{[] {
   const char* e = std::getenv("STRASSEN_TILE_CFG");
@@ -229,7 +228,8 @@ static int pick_cfg(const Plan& p, int64_t products_per_launch, int maxt) {
   if (forced >= 0 && forced < kNumCfgs) return forced;
   const int64_t t128 = cdiv(p.mq, 128) * cdiv(p.nq, 128) * products_per_launch;
   if (t128 < 512) return kCfg64;
-  return maxt >= 4 ? kCfg128w1 : kCfg128;
+  (void)maxt;
+  return kCfg128;
 }
 
 static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15) == 0; }

@@ -203,7 +203,7 @@ struct Fp64Tile {
     // of the matrix or of its sub-block, or a k step past the end) gets an offset past the
     // buffer's range and the hardware returns zero without touching memory, so the loads need
     // no branch and all stay in flight across the MFMA work.
-    auto load_stage = [&](int kt) {
+    auto load_a = [&](int kt) {
       const int64_t kb = (int64_t)kt * BK;
 #pragma unroll
       for (int s = 0; s < NA; ++s) {
@@ -221,6 +221,9 @@ struct Fp64Tile {
           }
         }
       }
+    };
+    auto load_b = [&](int kt) {
+      const int64_t kb = (int64_t)kt * BK;
 #pragma unroll
       for (int s = 0; s < NB; ++s) {
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb);
@@ -237,6 +240,10 @@ struct Fp64Tile {
           }
         }
       }
+    };
+    auto load_stage = [&](int kt) {
+      load_a(kt);
+      load_b(kt);
     };
 
     // Signed sums in registers, then into LDS stage `buf`.  The first term is scaled by its sign
@@ -292,29 +299,62 @@ struct Fp64Tile {
 #pragma unroll
       for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
-    // Software pipeline.  At the top of iteration kt the registers hold the raw terms of step
-    // kt+1, loaded during iteration kt-1.  Their sums go to the other LDS stage between the
-    // first sub-steps of step kt (no wait: the data is already there), then the loads of step
-    // kt+2 are issued into the freed registers and the remaining sub-steps run.
     constexpr int KS = BK / 4;
-    load_stage(0);
-    store_a(0);
-    store_b(0);
-    load_stage(1);   // past the end of k every position is out of range: no memory access
-    __syncthreads();
-    for (int kt = 0; kt + 1 < nk; ++kt) {
-      const int cur = kt & 1;
-      mfma_substep(cur, 0);
-      store_a(cur ^ 1);
-      if (KS > 1) mfma_substep(cur, 1);
-      store_b(cur ^ 1);
-      // keep the next loads after the sums: hoisting them would keep two stages of raw
-      // terms live at once
-      asm volatile("" ::: "memory");
-      load_stage(kt + 2);
-#pragma unroll
-      for (int ks = 2; ks < KS; ++ks) mfma_substep(cur, ks);
+    // Products with many terms keep only one operand's raw tiles in registers at a time: the
+    // A and B staging share the same registers (their live ranges do not overlap), which lets
+    // a four-term product run beside the 128 x 128 accumulator at two workgroups per CU.
+    constexpr bool SPLIT = (NA + NB >= 5) && KS >= 4;
+    if (!SPLIT) {
+      // At the top of iteration kt the registers hold the raw terms of step kt+1, loaded during
+      // iteration kt-1.  Their sums go to the other LDS stage between the first sub-steps of
+      // step kt (no wait: the data is already there), then the loads of step kt+2 are issued
+      // into the freed registers and the remaining sub-steps run.
+      load_stage(0);
+      store_a(0);
+      store_b(0);
+      load_stage(1);   // past the end of k every position is out of range: no memory access
       __syncthreads();
+      for (int kt = 0; kt + 1 < nk; ++kt) {
+        const int cur = kt & 1;
+        mfma_substep(cur, 0);
+        store_a(cur ^ 1);
+        if (KS > 1) mfma_substep(cur, 1);
+        store_b(cur ^ 1);
+        // keep the next loads after the sums: hoisting them would keep two stages of raw
+        // terms live at once
+        asm volatile("" ::: "memory");
+        load_stage(kt + 2);
+#pragma unroll
+        for (int ks = 2; ks < KS; ++ks) mfma_substep(cur, ks);
+        __syncthreads();
+      }
+    } else {
+      // Top of iteration kt: registers hold the raw A terms of step kt+1.  Sum them during
+      // sub-step 0, load B of step kt+1 into the same registers, sum B two sub-steps later,
+      // then load A of step kt+2 for the next iteration.
+      load_a(0);
+      store_a(0);
+      asm volatile("" ::: "memory");
+      load_b(0);
+      store_b(0);
+      asm volatile("" ::: "memory");
+      load_a(1);
+      __syncthreads();
+      for (int kt = 0; kt + 1 < nk; ++kt) {
+        const int cur = kt & 1;
+        mfma_substep(cur, 0);
+        store_a(cur ^ 1);
+        asm volatile("" ::: "memory");
+        load_b(kt + 1);
+        mfma_substep(cur, 1);
+        mfma_substep(cur, 2);
+        store_b(cur ^ 1);
+        asm volatile("" ::: "memory");
+        load_a(kt + 2);
+#pragma unroll
+        for (int ks = 3; ks < KS; ++ks) mfma_substep(cur, ks);
+        __syncthreads();
+      }
     }
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) mfma_substep((nk - 1) & 1, ks);
