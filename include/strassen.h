@@ -134,9 +134,13 @@ int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
 
 /*
  * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the
- * tile configuration per call; 0..3 forces one for every later call in the process:
+ * kernel and tile configuration per call; 0..4 forces one for every later call in the process:
  *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;
- *   2: 128 x 128, k step 8, two workgroups per CU;        3: 128 x 128, k step 16, one per CU.
+ *   2: 128 x 128, k step 8, two workgroups per CU;        3: 128 x 128, k step 16, one per CU;
+ *   4: ABC with levels >= 1 runs the all-products kernel (the seven products of a level side
+ *      by side on 64 x 64 tiles of the four quadrants) wherever its layout applies (m and k
+ *      multiples of 2^(levels+1), 16-byte aligned A, B, C, even leading dimensions), the
+ *      default choice otherwise.  The default (-1) also uses it wherever it applies.
  * Results do not depend on the configuration (bitwise).  The environment variable
  * STRASSEN_TILE_CFG sets the initial value.  Returns 0 or -1 (cfg out of range).
  */

@@ -221,7 +221,8 @@ def set_workspace(tensor_or_none):
 
 
 def set_tile_config(cfg):
-    """Force a tile configuration (0..3) for later calls, or -1 for the automatic choice."""
+    """Force a kernel / tile configuration (0..4, see strassen.h) for later calls, or -1 for the
+    automatic choice."""
     check(lib().strassen_set_tile_config(int(cfg)))
 
 

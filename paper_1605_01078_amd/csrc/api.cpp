@@ -225,7 +225,7 @@ static std::atomic<int> g_forced_cfg{[] {
 
 static int pick_cfg(const Plan& p, int64_t products_per_launch, int maxt) {
   const int forced = g_forced_cfg.load(std::memory_order_relaxed);
-  if (forced >= 0 && forced < kNumCfgs) return forced;
+  if (forced >= 0 && forced < kCfgAll) return forced;
   const int64_t t128 = cdiv(p.mq, 128) * cdiv(p.nq, 128) * products_per_launch;
   if (t128 < 512) return kCfg64;
   (void)maxt;
@@ -233,6 +233,84 @@ static int pick_cfg(const Plan& p, int64_t products_per_launch, int maxt) {
 }
 
 static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15) == 0; }
+
+// The all-products kernel needs every sub-block full with even extents in m and k, 16-byte
+// aligned operands with even leading dimensions (16-byte loads of element pairs), and per-tile
+// byte offsets that fit its 32-bit lane offsets.
+static bool all_products_applies(int64_t m, int64_t k, const double* A, int64_t lda,
+                                 const double* B, int64_t ldb, const double* C, int64_t ldc,
+                                 int levels) {
+  if (levels < 1) return false;
+  const int64_t unit = int64_t(2) << levels;
+  if (m % unit != 0 || k % unit != 0) return false;
+  if (!aligned16(A) || !aligned16(B) || !aligned16(C)) return false;
+  if (lda % 2 != 0 || ldb % 2 != 0 || ldc % 2 != 0) return false;
+  const int64_t lim = int64_t(1) << 31;
+  return 8 * 16 * lda < lim && 8 * 64 * ldb < lim && 8 * 64 * ldc < lim;
+}
+
+// ABC through the all-products kernel: one launch at one level, seven (one per outer product
+// of the one-level table, in order) at two.
+static int run_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
+                            double beta, hipStream_t stream) {
+  FusedArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.A = A;
+  f.B = B;
+  f.C = C;
+  f.lda = lda;
+  f.ldb = ldb;
+  f.ldc = ldc;
+  f.n = n;
+  f.mq = p.mq;
+  f.nq = p.nq;
+  f.kq = p.kq;
+  f.alpha = alpha;
+  f.beta = beta;
+  f.tiles_m = (int32_t)cdiv(p.mq, 64);
+  f.tiles_n = (int32_t)cdiv(p.nq, 64);
+  if ((int64_t)f.tiles_m * f.tiles_n >= (int64_t(1) << 30))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+  if (p.levels == 1) {
+    f.nc = 1;
+    f.c_first = 1;
+    f.a_sg[0] = f.b_sg[0] = f.c_sg[0] = 1.0;
+    SMX_HIP(launch_all_products(f, 1, 1, stream));
+    return 0;
+  }
+  // two levels: outer blocks are 2 x 2 inner sub-blocks
+  const int64_t om = 2 * p.mq, on = 2 * p.nq, ok = 2 * p.kq;
+  bool touched[4] = {false, false, false, false};
+  for (int R = 0; R < 7; ++R) {
+    const QProduct& P = kOneLevel[R];
+    if (P.a[0].sign != 1 || P.b[0].sign != 1)   // the kernel takes the first term's sign as +1
+      return fail(STRASSEN_ERR_UNSUPPORTED, "outer product %d: first term negative", R);
+    for (int s = 0; s < P.na; ++s) {
+      const int q = P.a[s].q;
+      f.a_off[s] = (q >> 1) * om + (q & 1) * ok * lda;
+      f.a_sg[s] = P.a[s].sign;
+    }
+    for (int s = 0; s < P.nb; ++s) {
+      const int q = P.b[s].q;
+      f.b_off[s] = (q >> 1) * ok + (q & 1) * on * ldb;
+      f.b_cb[s] = 2 * (q & 1);
+      f.b_sg[s] = P.b[s].sign;
+    }
+    f.nc = P.nc;
+    f.c_first = 0;
+    for (int d = 0; d < P.nc; ++d) {
+      const int q = P.c[d].q;
+      f.c_off[d] = (q >> 1) * om + (q & 1) * on * ldc;
+      f.c_cb[d] = 2 * (q & 1);
+      f.c_sg[d] = P.c[d].sign;
+      if (!touched[q]) f.c_first |= 1 << d;
+      touched[q] = true;
+    }
+    SMX_HIP(launch_all_products(f, P.na, P.nb, stream));
+  }
+  return 0;
+}
 
 static int validate(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double* C, int64_t ldc, int levels,
@@ -300,6 +378,10 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
              k % 2 == 0 && p.mq % 2 == 0 && p.kq % 2 == 0;
 
   if (p.variant == STRASSEN_ABC) {
+    const int forced = g_forced_cfg.load(std::memory_order_relaxed);
+    if ((forced == -1 || forced == kCfgAll) &&
+        all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels))
+      return run_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta, stream);
     const int cfg = pick_cfg(p, 1, maxt);
     g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
     g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));

@@ -99,15 +99,21 @@ __global__ __launch_bounds__(256) void sum_kernel(const SumArgs args) {
   const ProdDesc& pd = tab.prod[r];
   const int nt = args.side == 0 ? pd.na : pd.nb;
   const uint8_t* codes = args.side == 0 ? pd.a : pd.b;
-  double v = 0.0;
+  // Same arithmetic as signed_sum: each pair is c0 * (x0 + (c0*c1) x1), a four-term sum adds
+  // the two pairs.
+  double x[kMaxTerms], sg[kMaxTerms];
   for (int t = 0; t < nt; ++t) {
     const uint8_t code = codes[t];
     const int64_t row = code_row(code) * args.rows_q + i;
     const int64_t col = code_col(code) * args.cols_q + j;
     const bool ok = row < args.rows && col < args.cols;
-    const double x = ok ? args.src[row + col * args.ld] : 0.0;
-    v = t == 0 ? sum_first(x, code_neg(code)) : sum_next(v, x, code_neg(code));
+    x[t] = ok ? args.src[row + col * args.ld] : 0.0;
+    sg[t] = code_neg(code) ? -1.0 : 1.0;
   }
+  double v;
+  if (nt == 1) v = signed_sum<1>(sg, x);
+  else if (nt == 2) v = signed_sum<2>(sg, x);
+  else v = signed_sum<4>(sg, x);
   args.dst[(int64_t)slot * args.dst_stride + i + j * args.rows_q] = v;
 }
 

@@ -12,7 +12,8 @@ enum TileCfg : int {
   kCfg64 = 1,      // 64 x 64, BK 16
   kCfg128k8 = 2,   // 128 x 128, BK 8, two workgroups per CU
   kCfg128w1 = 3,   // 128 x 128, BK 16, one workgroup per CU (512 registers per lane)
-  kNumCfgs = 4
+  kCfgAll = 4,     // ABC with levels >= 1: the all-products kernel (where its layout applies)
+  kNumCfgs = 5
 };
 inline int cfg_bm(int cfg) { return cfg == kCfg64 ? 64 : 128; }
 inline int cfg_bn(int cfg) { return cfg == kCfg64 ? 64 : 128; }
@@ -25,6 +26,9 @@ hipError_t upload_tables(const TableDev* tabs);
 // pairs of doubles can be loaded together.  grid = number of workgroups.
 hipError_t launch_fp64_tile(const GemmArgs& a, int cfg, int maxt, bool vec, int grid,
                             hipStream_t s);
+// All-products kernel for one outer product with na A terms and nb B terms (1 or 2 each);
+// grid = a.tiles_m * a.tiles_n workgroups of 512 threads.
+hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s);
 hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);

@@ -65,6 +65,25 @@ struct GemmArgs {
   int32_t prod_begin;   // StoreM: first product of this launch
 };
 
+// Arguments of the all-products kernel: one launch computes the seven products of the one-level
+// table on the 2 x 2 inner sub-blocks of one outer product's operands (at one level the outer
+// product is the identity: one term of sign +1 covering the whole matrix).
+struct FusedArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int64_t n;                    // columns of B and C
+  int64_t mq, nq, kq;           // inner sub-block extents (mq and kq even and exact)
+  double alpha, beta;
+  int32_t tiles_m, tiles_n;     // 64 x 64 tiles of one inner sub-block
+  int32_t nc;                   // outer destinations (1 or 2)
+  int32_t c_first;              // bit d: outer destination d gets its first update in this launch
+  int64_t a_off[2], b_off[2], c_off[2];   // element offsets of the outer blocks
+  int32_t b_cb[2], c_cb[2];     // first column block (units of nq) of outer B terms / destinations
+  double a_sg[2], b_sg[2], c_sg[2];
+};
+
 // C assembly for AB / Naive: C_s := beta*C_s at the first update, then C_s += alpha*gamma*M_r
 // for the products r feeding sub-block s, in increasing r.
 struct AssembleArgs {
@@ -92,6 +111,21 @@ struct ScaleArgs {
   double* C;
   int64_t ldc, m, n;
   double beta;
+};
+
+// The one-level table of Fig. "All operations for one-level Strassen" (Sec. 3.1) with sub-blocks
+// named by quadrant index q = 2*row + col: for product r its A terms, B terms and C destinations,
+// each with a sign.  Both the host table builder and the all-products kernel read it.
+struct QTerm { int8_t q, sign; };
+struct QProduct { int8_t na, nb, nc; QTerm a[2], b[2], c[2]; };
+constexpr QProduct kOneLevel[7] = {
+    {2, 2, 2, {{0, 1}, {3, 1}}, {{0, 1}, {3, 1}}, {{0, 1}, {3, 1}}},     // (A00+A11)(B00+B11)
+    {2, 1, 2, {{2, 1}, {3, 1}}, {{0, 1}, {0, 0}}, {{2, 1}, {3, -1}}},    // (A10+A11) B00
+    {1, 2, 2, {{0, 1}, {0, 0}}, {{1, 1}, {3, -1}}, {{1, 1}, {3, 1}}},    // A00 (B01-B11)
+    {1, 2, 2, {{3, 1}, {0, 0}}, {{2, 1}, {0, -1}}, {{0, 1}, {2, 1}}},    // A11 (B10-B00)
+    {2, 1, 2, {{0, 1}, {1, 1}}, {{3, 1}, {0, 0}}, {{1, 1}, {0, -1}}},    // (A00+A01) B11
+    {2, 2, 1, {{2, 1}, {0, -1}}, {{0, 1}, {1, 1}}, {{3, 1}, {0, 0}}},    // (A10-A00)(B00+B01)
+    {2, 2, 1, {{1, 1}, {3, -1}}, {{2, 1}, {3, 1}}, {{0, 1}, {0, 0}}},    // (A01-A11)(B10+B11)
 };
 
 struct Term { int row, col, sign; };

@@ -12,23 +12,15 @@ namespace smx {
 namespace {
 
 std::vector<Product> one_level() {
-  // {A terms}, {B terms}, {C updates}; each term is {row block, col block, sign}.
-  return {
-      // M0 = (A00 + A11)(B00 + B11); C00 += M0; C11 += M0
-      {{{0, 0, 1}, {1, 1, 1}}, {{0, 0, 1}, {1, 1, 1}}, {{0, 0, 1}, {1, 1, 1}}},
-      // M1 = (A10 + A11) B00; C10 += M1; C11 -= M1
-      {{{1, 0, 1}, {1, 1, 1}}, {{0, 0, 1}}, {{1, 0, 1}, {1, 1, -1}}},
-      // M2 = A00 (B01 - B11); C01 += M2; C11 += M2
-      {{{0, 0, 1}}, {{0, 1, 1}, {1, 1, -1}}, {{0, 1, 1}, {1, 1, 1}}},
-      // M3 = A11 (B10 - B00); C00 += M3; C10 += M3
-      {{{1, 1, 1}}, {{1, 0, 1}, {0, 0, -1}}, {{0, 0, 1}, {1, 0, 1}}},
-      // M4 = (A00 + A01) B11; C01 += M4; C00 -= M4
-      {{{0, 0, 1}, {0, 1, 1}}, {{1, 1, 1}}, {{0, 1, 1}, {0, 0, -1}}},
-      // M5 = (A10 - A00)(B00 + B01); C11 += M5
-      {{{1, 0, 1}, {0, 0, -1}}, {{0, 0, 1}, {0, 1, 1}}, {{1, 1, 1}}},
-      // M6 = (A01 - A11)(B10 + B11); C00 += M6
-      {{{0, 1, 1}, {1, 1, -1}}, {{1, 0, 1}, {1, 1, 1}}, {{0, 0, 1}}},
-  };
+  std::vector<Product> t;
+  for (const QProduct& qp : kOneLevel) {
+    Product p;
+    for (int s = 0; s < qp.na; ++s) p.a.push_back({qp.a[s].q >> 1, qp.a[s].q & 1, qp.a[s].sign});
+    for (int s = 0; s < qp.nb; ++s) p.b.push_back({qp.b[s].q >> 1, qp.b[s].q & 1, qp.b[s].sign});
+    for (int s = 0; s < qp.nc; ++s) p.c.push_back({qp.c[s].q >> 1, qp.c[s].q & 1, qp.c[s].sign});
+    t.push_back(p);
+  }
+  return t;
 }
 
 std::vector<Term> kron(const std::vector<Term>& outer, const std::vector<Term>& inner, int q_in) {

@@ -42,10 +42,23 @@ __device__ __forceinline__ double c_update(double c, double mv, double ag, doubl
   return __builtin_fma(ag, mv, beta * c);
 }
 
-// Signed operand sum, term by term in table order: v = +-x0, then v = v +- x_s.
-__device__ __forceinline__ double sum_first(double x, bool neg) { return neg ? -x : x; }
-__device__ __forceinline__ double sum_next(double v, double x, bool neg) {
-  return neg ? v - x : v + x;
+// Signed operand sums.  A pair of terms c0*x0 + c1*x1 (c = +-1) is rounded once as
+// c0 * (x0 + (c0*c1) x1): the first term's sign is factored out (exact), so the sum of the
+// negated pair is the exact negation of the pair's sum.  A four-term sum of the two-level table
+// (terms listed inner-term-major: (outer 0, inner 0), (outer 1, inner 0), (outer 0, inner 1),
+// (outer 1, inner 1)) adds its two pair sums: each pair is the outer-level sum for one inner
+// block, so the association is that of applying the one-level algorithm recursively.
+// (fma(+-1, x, v) rounds exactly like v +- x.)
+__device__ __forceinline__ double pair_sum(double c0, double x0, double c1, double x1) {
+  return c0 * __builtin_fma(c0 * c1, x1, x0);
+}
+template <int N>
+__device__ __forceinline__ double signed_sum(const double* sg, const double* x) {
+  static_assert(N == 1 || N == 2 || N == 4, "term count");
+  if (N == 1) return sg[0] * x[0];
+  const double p01 = pair_sum(sg[0], x[0], sg[1], x[1]);
+  if (N == 2) return p01;
+  return p01 + pair_sum(sg[2], x[2], sg[3], x[3]);
 }
 
 // Raw buffer access (gfx9 buffer resource: stride 0, 2 GiB range).  A load whose offset lies
@@ -106,7 +119,7 @@ struct Fp64Tile {
   static constexpr int FM = WM / 16, FN = WN / 16;
   static constexpr int A_STAGE = BK * LDA_S, B_STAGE = BK * LDB_S;
   static constexpr int LDS_DOUBLES = 2 * (A_STAGE + B_STAGE);
-  static_assert(A_PASSES >= 1 && B_PASSES >= 1 && BK % 4 == 0 && A_CPP * A_PASSES == BK &&
+  static_assert(A_PASSES >= 1 && B_PASSES >= 1 && BK % 8 == 0 && A_CPP * A_PASSES == BK &&
                     B_CPP * B_PASSES == BN,
                 "tile shape");
 
@@ -246,18 +259,18 @@ struct Fp64Tile {
       load_b(kt);
     };
 
-    // Signed sums in registers, then into LDS stage `buf`.  The first term is scaled by its sign
-    // (exact), each further term is added with one FMA: fma(+-1, x, v) rounds exactly like
-    // v +- x, the rounding the Naive operand-sum kernel performs.
+    // Signed sums in registers (signed_sum: the association every kernel uses), then into LDS
+    // stage `buf`.
     auto store_a = [&](int buf) {
 #pragma unroll
       for (int p = 0; p < A_PASSES; ++p) {
-        double v0 = a_sg[0] * ra[0][p].x, v1 = a_sg[0] * ra[0][p].y;
+        double xs[NA], ys[NA];
 #pragma unroll
-        for (int s = 1; s < NA; ++s) {
-          v0 = __builtin_fma(a_sg[s], ra[s][p].x, v0);
-          v1 = __builtin_fma(a_sg[s], ra[s][p].y, v1);
+        for (int s = 0; s < NA; ++s) {
+          xs[s] = ra[s][p].x;
+          ys[s] = ra[s][p].y;
         }
+        const double v0 = signed_sum<NA>(a_sg, xs), v1 = signed_sum<NA>(a_sg, ys);
         *reinterpret_cast<d2_t*>(&As[buf * A_STAGE + (a_col + p * A_CPP) * LDA_S + a_row]) =
             (d2_t){v0, v1};
       }
@@ -265,23 +278,28 @@ struct Fp64Tile {
     auto store_b = [&](int buf) {
 #pragma unroll
       for (int p = 0; p < B_PASSES; ++p) {
-        double v0 = b_sg[0] * rb[0][p].x, v1 = b_sg[0] * rb[0][p].y;
+        double xs[NB], ys[NB];
 #pragma unroll
-        for (int s = 1; s < NB; ++s) {
-          v0 = __builtin_fma(b_sg[s], rb[s][p].x, v0);
-          v1 = __builtin_fma(b_sg[s], rb[s][p].y, v1);
+        for (int s = 0; s < NB; ++s) {
+          xs[s] = rb[s][p].x;
+          ys[s] = rb[s][p].y;
         }
+        const double v0 = signed_sum<NB>(b_sg, xs), v1 = signed_sum<NB>(b_sg, ys);
         const int j = b_col + p * B_CPP;
         Bs[buf * B_STAGE + b_k * LDB_S + j] = v0;
         Bs[buf * B_STAGE + (b_k + 1) * LDB_S + j] = v1;
       }
     };
 
-    // One k sub-step (k = 4): FM x FN MFMAs on fragments read from LDS stage `buf`.
+    // One k sub-step (four k values): FM x FN MFMAs on fragments read from LDS stage `buf`.
+    // Within each group of eight k values, lane group g = lane / 16 takes k = 2g in the first
+    // sub-step and k = 2g + 1 in the second (the pairing that 16-byte operand reads give the
+    // all-products kernel); every FP64 kernel feeds the MFMA this way, so the products agree
+    // bit for bit across kernels.
     auto mfma_substep = [&](int buf, int ks) {
       const double* as = As + buf * A_STAGE + wm * WM + (lane & 15);
       const double* bs = Bs + buf * B_STAGE + wn * WN + (lane & 15);
-      const int kr = ks * 4 + (lane >> 4);
+      const int kr = (ks >> 1) * 8 + 2 * (lane >> 4) + (ks & 1);
       double af[FM], bf[FN];
 #pragma unroll
       for (int fm = 0; fm < FM; ++fm) af[fm] = as[kr * LDA_S + fm * 16];

@@ -180,7 +180,7 @@ def test_caller_workspace():
         sx.set_workspace(None)
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("levels", [0, 1, 2])
 def test_every_tile_config_bitwise_and_exact(cfg, levels):
     """Every tile configuration gives the oracle's exact integer result and, on reals, the
@@ -197,5 +197,41 @@ def test_every_tile_config_bitwise_and_exact(cfg, levels):
         for i, v in enumerate(VARIANTS if levels else ["abc"]):
             assert np.array_equal(run(A, B, C, 1.0, 1.0, levels, v), ref), v
             assert np.array_equal(run(Ar, Br, Cr, 1.0, 1.0, levels, v), auto[i]), v
+    finally:
+        sx.set_tile_config(-1)
+
+
+# Shapes on which ABC runs the all-products kernel (m and k multiples of 2^(L+1)): full tiles,
+# tile fringes inside the sub-blocks (m/4 = 194 = 3*64 + 2) and ragged n at both levels.
+ALL_PRODUCTS_SHAPES = [(512, 512, 512), (1024, 1030, 1032), (776, 333, 1048), (64, 9, 8)]
+
+
+@pytest.mark.parametrize("shape", ALL_PRODUCTS_SHAPES)
+@pytest.mark.parametrize("levels", [1, 2])
+def test_all_products_kernel(shape, levels):
+    """ABC on the all-products kernel: exact on integers, within the Strassen tolerance on reals,
+    bitwise equal to AB, Naive and every tile configuration of the general kernel."""
+    m, n, k = shape
+    print(f"case all-products {shape} L={levels}", flush=True)
+    A, B, C = W.problem(21, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    Ar, Br, Cr = W.problem(22, m, n, k, "uniform")
+    refr = oracle_dgemm(Ar, Br, Cr.copy(order="F"), -0.5, 2.5)
+    try:
+        sx.set_tile_config(4)
+        assert np.array_equal(run(A, B, C, 1.0, 1.0, levels, "abc"), ref)
+        fused = run(Ar, Br, Cr, -0.5, 2.5, levels, "abc")
+        assert rel_fro(fused, refr) <= TOL[levels]
+        for v in ("ab", "naive"):
+            assert np.array_equal(run(Ar, Br, Cr, -0.5, 2.5, levels, v), fused), v
+        for cfg in (0, 1, 2, 3):
+            sx.set_tile_config(cfg)
+            assert np.array_equal(run(Ar, Br, Cr, -0.5, 2.5, levels, "abc"), fused), cfg
+        # beta = 0: C is write-only (NaN in C must not show)
+        sx.set_tile_config(4)
+        Cn = np.full_like(Cr, np.nan)
+        out = run(Ar, Br, Cn, 1.0, 0.0, levels, "abc")
+        assert np.isfinite(out).all()
+        assert np.array_equal(out, run(Ar, Br, Cn, 1.0, 0.0, levels, "naive"))
     finally:
         sx.set_tile_config(-1)
