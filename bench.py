@@ -4,15 +4,17 @@
 
 One step is one call C := A*B + C of the library at m = n = k = n (default 16384, FP64, entries
 uniform on [-1, 1], inputs resident in HBM) with `levels` levels of Strassen in the given variant
-(default: two-level ABC, whose single kernel launch is the step).  Printed as ONE JSON line:
+(default: two-level ABC, which runs as seven back-to-back launches of the all-products kernel,
+one per outer product).  Printed as ONE JSON line:
 the headline value plus, measured in the same run,
   * the library's own classical FP64 MFMA GEMM (levels = 0) and every (levels, variant) pair,
     timed with HIP events, with the speedup over classical;
   * the relative Frobenius error of the headline result against the CPU oracle on sampled
     columns (and of the classical result), checked against 1e-12 (one level) / 1e-11 (two);
-  * roofline of the dominant kernel (the FP64 tile kernel): executed MFMA flops per launch over
-    its average duration, against the 78.6 TFLOP/s FP64 matrix peak; `traffic` comes from the
-    committed rocprofv3 counter summary when it was taken on the current kernel source;
+  * roofline of the dominant kernel (the all-products kernel for ABC, the FP64 tile kernel
+    otherwise): executed MFMA flops per launch over its average duration, against the 78.6
+    TFLOP/s FP64 matrix peak; `traffic` comes from the committed rocprofv3 counter summary when
+    it was taken on the current kernel source;
   * cpu_baseline: the oracle's plain triple-loop GEMM timed on the host cores over a bounded
     column sample of the same problem.
 Diagnostics go to stderr.
@@ -32,7 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "effective TFLOPS (2mnk/t), Strassen vs own classical GEMM, at stated rel error"
 PEAK_F64_MFMA = 78.6   # TFLOP/s, MI355X datasheet, dense FP64 matrix
 TOL = {0: None, 1: 1e-12, 2: 1e-11}
-KERNEL_SOURCES = ["paper_1605_01078_amd/csrc/tile_fp64.h", "paper_1605_01078_amd/csrc/kernels_fp64.hip"]
+KERNEL_SOURCES = ["paper_1605_01078_amd/csrc/tile_fp64.h", "paper_1605_01078_amd/csrc/kernels_fp64.hip",
+                  "paper_1605_01078_amd/csrc/fused_fp64.hip"]
 
 
 def log(*a):
@@ -81,11 +84,21 @@ def copy_calibration():
     del x, y
 
 
+def dominant_kernel(L, variant):
+    return "all_products_kernel" if (variant == "abc" and L >= 1) else "fp64_tile_kernel"
+
+
+def traffic_path(L, variant, n):
+    return os.path.join(ROOT, "profiles", f"traffic_{dominant_kernel(L, variant)}_L{L}_{variant}_{n}.json")
+
+
 def traffic_summary(args):
-    """Per-launch HBM bytes of the tile kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
-    each scaled by known/measured bytes of the calibration copy in the same run."""
+    """Per-launch HBM bytes of the dominant kernel from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch, averaged over its dispatches), each scaled by known/measured bytes of the
+    calibration copy in the same run."""
     import csv
     import glob
+    kname = dominant_kernel(args.levels, args.variant)
 
     def read(d, counter):
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
@@ -95,7 +108,7 @@ def traffic_summary(args):
                 continue
             v = float(row["Counter_Value"])
             name = row["Kernel_Name"]
-            if "fp64_tile_kernel" in name:
+            if kname in name:
                 tile.append(v)
             elif "neg" in name:
                 copy.append(v)
@@ -107,13 +120,13 @@ def traffic_summary(args):
     fetch = float(np.mean(ft)) * 1024.0 * f_fetch
     write = float(np.mean(wt)) * 1024.0 * f_write
     L, variant, n = args.levels, args.variant, args.n
-    out = {"kernel": "fp64_tile_kernel", "workload": f"L={L} {variant} m=n=k={n}",
+    out = {"kernel": kname, "workload": f"L={L} {variant} m=n=k={n}",
            "kernel_source_hash": kernel_source_hash(),
            "fetch_kib_per_launch": float(np.mean(ft)), "write_kib_per_launch": float(np.mean(wt)),
            "copy_fetch_kib": fc[-1], "copy_write_kib": wc[-1], "copy_bytes": COPY_BYTES,
            "fetch_scale": f_fetch, "write_scale": f_write,
            "hbm_bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write}
-    path = os.path.join(ROOT, "profiles", f"traffic_fp64_tile_L{L}_{variant}_{n}.json")
+    path = traffic_path(L, variant, n)
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     log(json.dumps(out, indent=1))
@@ -237,12 +250,17 @@ def main():
         sx.release_workspace()
 
     # ---- roofline of the dominant kernel --------------------------------------------------------
-    # The ABC step is one launch of the FP64 tile kernel, so its average duration is the event
-    # time around each step.  Executed MFMA flops per launch: 7^L products of 2*mq*nq*kq each.
-    avg_launch_ms = float(np.mean(per_launch))
-    achieved = exec_flops / (avg_launch_ms * 1e-3) * 1e-12
+    # ABC at one level is one launch of the all-products kernel (7 products); at two levels it is
+    # seven back-to-back launches on the step's stream, one per outer product, each computing 7
+    # inner products, so one launch executes 7 * 2*mq*nq*kq MFMA flops and its average duration
+    # is the event time of a step over 7.  AB / Naive: one tile-kernel launch holds all 7^L
+    # products (the assembly and sum kernels are small beside it).
+    launches = 7 ** (L - 1) if (variant == "abc" and L >= 1) else 1
+    avg_launch_ms = float(np.mean(per_launch)) / launches
+    exec_flops_launch = exec_flops / launches
+    achieved = exec_flops_launch / (avg_launch_ms * 1e-3) * 1e-12
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", f"traffic_fp64_tile_L{L}_{variant}_{n}.json")
+    tpath = traffic_path(L, variant, n)
     if os.path.exists(tpath):
         with open(tpath) as f:
             tr = json.load(f)
@@ -250,8 +268,9 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA, 4), "traffic": traffic,
-                "kernel": "fp64_tile_kernel (ABC)" if variant == "abc" else "fp64_tile_kernel",
-                "exec_flops_per_launch": exec_flops, "avg_launch_ms": round(avg_launch_ms, 3)}
+                "kernel": dominant_kernel(L, variant),
+                "launches_per_step": launches,
+                "exec_flops_per_launch": exec_flops_launch, "avg_launch_ms": round(avg_launch_ms, 3)}
 
     # ---- CPU baseline: the oracle on a bounded column sample -----------------------------------
     cpu = None
