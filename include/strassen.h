@@ -114,23 +114,38 @@ int strassen_set_workspace(void *ptr, size_t bytes);
 int strassen_release_workspace(void);
 
 /*
- * strassen_gemm_ex — the reduced-precision mode.  C (FP64) := alpha*A*B + beta*C where each
- * product M_r runs on BF16 MFMA with FP32 accumulation (compute = STRASSEN_COMPUTE_BF16 or
- * _BF16X3; _F64 forwards to strassen_dgemm).  A, B, C are FP64 as in strassen_dgemm.
- *   sum_prec: precision in which the quadrant sums sum_s delta_s X_s are formed before the
- *             rounding to bf16 (F32: every term is first rounded to FP32; F64: the sum is
- *             formed in FP64 and rounded once to FP32).  Rounding is to nearest-even.
+ * strassen_gemm_ex — the reduced-precision mode (an extension; the paper is FP64 only, and
+ * Strassen's weaker error bound (Sec. 1) is why the sums and the C update keep FP32 or FP64).
+ * C (FP64) := alpha*A*B + beta*C where each product M_r of the table runs on BF16 MFMA with FP32
+ * accumulation (compute = STRASSEN_COMPUTE_BF16 or _BF16X3; _F64 forwards to strassen_dgemm).
+ * A, B, C are FP64 as in strassen_dgemm; levels 0 is the classical product in the same mode.
+ *   sum_prec: precision in which each operand sum sum_s delta_s X_s is formed (F32: every term
+ *             is first rounded to FP32; F64: formed in FP64, then rounded once to FP32); the
+ *             FP32 value x becomes hi = bf16(x) and, for bf16x3, lo = bf16(x - hi), rounding
+ *             to nearest even; bf16x3 computes hi*hi + hi*lo + lo*hi.
  *   c_prec  : precision of the C update  c := c + alpha*gamma*M  (F32: c is rounded to FP32
- *             before the first update of the call and each update is an FP32 operation;
- *             F64: FP64 operations).  C is stored as FP64 either way.
- * Only STRASSEN_ABC is offered (variant must be 0).  Argument positions as strassen_dgemm,
- * then compute=14, sum_prec=15, c_prec=16.
+ *             before the first update of the call and each update is one FP32 fused
+ *             multiply-add; F64: FP64 fused multiply-add).  C is stored as FP64 either way.
+ * The products add straight into every destination C sub-block (variant must be STRASSEN_ABC).
+ * The operand sums are rounded to bf16 in a first pass into workspace (library-owned, or the
+ * caller's: strassen_workspace_size_ex gives the size), since a bf16 operand needs its
+ * full-precision sum first.  Argument positions as strassen_dgemm, then compute=14,
+ * sum_prec=15, c_prec=16.
  */
 int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                      const double *A, int64_t lda, const double *B, int64_t ldb,
                      double beta, double *C, int64_t ldc,
                      int levels, int variant, int compute, int sum_prec, int c_prec,
                      void *stream);
+
+/*
+ * strassen_workspace_size_ex — bytes of workspace strassen_gemm_ex needs: 7^levels products
+ * times (ceil(m/2^L) rounded up to 128 + ceil(n/2^L) rounded up to 128) times ceil(k/2^L)
+ * rounded up to 64, two bytes each, twice for bf16x3; 0 for STRASSEN_COMPUTE_F64.
+ * Returns 0 or -i (m=1 n=2 k=3 levels=4 compute=5 bytes=6).
+ */
+int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int compute,
+                               size_t *bytes);
 
 /*
  * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the

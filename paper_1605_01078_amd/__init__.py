@@ -45,6 +45,8 @@ def lib():
         L.strassen_gemm_ex.restype = ci
         L.strassen_workspace_size.argtypes = [i64, i64, i64, ci, ci, ctypes.POINTER(ctypes.c_size_t)]
         L.strassen_workspace_size.restype = ci
+        L.strassen_workspace_size_ex.argtypes = [i64, i64, i64, ci, ci, ctypes.POINTER(ctypes.c_size_t)]
+        L.strassen_workspace_size_ex.restype = ci
         L.strassen_set_workspace.argtypes = [vp, ctypes.c_size_t]
         L.strassen_set_workspace.restype = ci
         L.strassen_release_workspace.argtypes = []
@@ -207,6 +209,12 @@ def raw_dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, str
 def workspace_size(m, n, k, levels, variant):
     out = ctypes.c_size_t(0)
     check(lib().strassen_workspace_size(m, n, k, levels, _variant(variant), ctypes.byref(out)))
+    return out.value
+
+
+def workspace_size_ex(m, n, k, levels, compute):
+    out = ctypes.c_size_t(0)
+    check(lib().strassen_workspace_size_ex(m, n, k, levels, COMPUTE[compute], ctypes.byref(out)))
     return out.value
 
 

@@ -135,6 +135,7 @@ static int device_ready(int* dev_out) {
       return fail(STRASSEN_ERR_NO_DEVICE, "device %d is %s, the library is built for gfx950", dev,
                   prop.gcnArchName);
     SMX_HIP(upload_tables(host_tables()));
+    SMX_HIP(upload_tables_bf16(host_tables()));
     SMX_HIP(hipDeviceSynchronize());
     g_dev[dev].ready = true;
   }
@@ -470,6 +471,121 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
   return 0;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Reduced-precision mode (BF16 / bf16x3 products).
+// ---------------------------------------------------------------------------------------------
+struct LowPlan {
+  int64_t mq, nq, kq, mp, np, kp, slot_a, slot_b, nslots;
+  bool x3;
+  size_t bytes;
+};
+
+static LowPlan make_low_plan(int64_t m, int64_t n, int64_t k, int levels, int compute) {
+  LowPlan p;
+  const int64_t q = int64_t(1) << levels;
+  p.mq = cdiv(m, q);
+  p.nq = cdiv(n, q);
+  p.kq = cdiv(k, q);
+  p.mp = round_up(p.mq, 128);
+  p.np = round_up(p.nq, 128);
+  p.kp = round_up(p.kq, 64);
+  p.slot_a = p.mp * p.kp;
+  p.slot_b = p.np * p.kp;
+  p.nslots = host_tables()[table_id(levels, false)].nprod;
+  p.x3 = compute == STRASSEN_COMPUTE_BF16X3;
+  p.bytes = (size_t)(p.slot_a + p.slot_b) * p.nslots * 2 * (p.x3 ? 2 : 1);
+  return p;
+}
+
+int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
+            int variant, int compute, int sum_prec, int c_prec, hipStream_t stream) {
+  g_last_error.clear();
+  if (int rc = validate(m, n, k, alpha, A, lda, B, ldb, C, ldc, levels, variant)) return rc;
+  if (compute < 0 || compute > 2) return fail(-14, "compute = %d not in 0..2", compute);
+  if (sum_prec < 0 || sum_prec > 1) return fail(-15, "sum_prec = %d not in 0..1", sum_prec);
+  if (c_prec < 0 || c_prec > 1) return fail(-16, "c_prec = %d not in 0..1", c_prec);
+  if (compute == STRASSEN_COMPUTE_F64)
+    return dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, stream);
+  if (variant != STRASSEN_ABC)
+    return fail(-13, "the reduced-precision mode runs the ABC variant only (variant = %d)", variant);
+  if (m == 0 || n == 0) return 0;
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
+  if (alpha == 0.0 || k == 0) {
+    if (beta == 1.0) return 0;
+    return run_scale(C, ldc, m, n, beta, stream);
+  }
+  const LowPlan p = make_low_plan(m, n, k, levels, compute);
+  const int64_t lim = int64_t(1) << 31;
+  if (2 * p.slot_a * p.nslots >= lim || 2 * p.slot_b * p.nslots >= lim || 8 * 128 * ldc >= lim)
+    return fail(STRASSEN_ERR_UNSUPPORTED, "reduced-precision operands past the 32-bit offset range");
+  void* ws = nullptr;
+  if (int rc = get_workspace(dev, p.bytes, &ws)) return rc;
+  uint16_t* w = static_cast<uint16_t*>(ws);
+  uint16_t* TAh = w;
+  uint16_t* TBh = TAh + p.slot_a * p.nslots;
+  uint16_t* TAl = p.x3 ? TBh + p.slot_b * p.nslots : nullptr;
+  uint16_t* TBl = p.x3 ? TAl + p.slot_a * p.nslots : nullptr;
+  const int tab = table_id(levels, false);
+
+  CastArgs ca;
+  std::memset(&ca, 0, sizeof ca);
+  ca.src = A;
+  ca.hi = TAh;
+  ca.lo = TAl;
+  ca.ld = lda;
+  ca.rows = m;
+  ca.cols = k;
+  ca.rq = p.mq;
+  ca.cq = p.kq;
+  ca.outer_pad = p.mp;
+  ca.kpad = p.kp;
+  ca.slot_stride = p.slot_a;
+  ca.tab = tab;
+  ca.side = 0;
+  ca.sum_f64 = sum_prec == STRASSEN_PREC_F64;
+  SMX_HIP(launch_cast(ca, (int)p.nslots, stream));
+  CastArgs cb = ca;
+  cb.src = B;
+  cb.hi = TBh;
+  cb.lo = TBl;
+  cb.ld = ldb;
+  cb.rows = k;
+  cb.cols = n;
+  cb.rq = p.kq;
+  cb.cq = p.nq;
+  cb.outer_pad = p.np;
+  cb.slot_stride = p.slot_b;
+  cb.side = 1;
+  SMX_HIP(launch_cast(cb, (int)p.nslots, stream));
+
+  Bf16Args g;
+  std::memset(&g, 0, sizeof g);
+  g.TAh = TAh;
+  g.TAl = TAl;
+  g.TBh = TBh;
+  g.TBl = TBl;
+  g.stride_a = p.slot_a;
+  g.stride_b = p.slot_b;
+  g.kpad = p.kp;
+  g.C = C;
+  g.ldc = ldc;
+  g.m = m;
+  g.n = n;
+  g.mq = p.mq;
+  g.nq = p.nq;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.tab = tab;
+  g.tiles_m = (int32_t)(p.mp / 128);
+  g.tiles_n = (int32_t)(p.np / 128);
+  g.x3 = p.x3;
+  g.c_f64 = c_prec == STRASSEN_PREC_F64;
+  SMX_HIP(launch_bf16_gemm(g, stream));
+  return 0;
+}
+
 }  // namespace smx
 
 // ---------------------------------------------------------------------------------------------
@@ -532,13 +648,25 @@ int strassen_release_workspace(void) {
 int strassen_gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
                      int variant, int compute, int sum_prec, int c_prec, void* stream) {
+  return smx::gemm_ex(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, compute,
+                      sum_prec, c_prec, static_cast<hipStream_t>(stream));
+}
+
+int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int compute,
+                               size_t* bytes) {
   smx::g_last_error.clear();
-  if (compute < 0 || compute > 2) return smx::fail(-14, "compute out of range");
-  if (sum_prec < 0 || sum_prec > 1) return smx::fail(-15, "sum_prec out of range");
-  if (c_prec < 0 || c_prec > 1) return smx::fail(-16, "c_prec out of range");
-  if (compute == STRASSEN_COMPUTE_F64)
-    return strassen_dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, stream);
-  return smx::fail(STRASSEN_ERR_UNSUPPORTED, "reduced-precision mode not built yet");
+  if (m < 0) return smx::fail(-1, "m < 0");
+  if (n < 0) return smx::fail(-2, "n < 0");
+  if (k < 0) return smx::fail(-3, "k < 0");
+  if (levels < 0 || levels > smx::kMaxLevels) return smx::fail(-4, "levels out of range");
+  if (compute < 0 || compute > 2) return smx::fail(-5, "compute out of range");
+  if (!bytes) return smx::fail(-6, "bytes is NULL");
+  if (compute == STRASSEN_COMPUTE_F64 || m == 0 || n == 0 || k == 0) {
+    *bytes = 0;
+    return 0;
+  }
+  *bytes = smx::make_low_plan(m, n, k, levels, compute).bytes;
+  return 0;
 }
 
 int strassen_set_tile_config(int cfg) {

@@ -1,0 +1,328 @@
+// Reduced-precision mode: the Strassen products on BF16 MFMA (v_mfma_f32_16x16x32_bf16) with
+// FP32 accumulation; the operand sums and the C update stay in FP32 or FP64.
+//
+// A bf16 operand can only be formed once its full-precision sum exists, so the mode runs in two
+// passes:
+//   cast_kernel     forms, for every product r, the A-side sum  sum_s delta_s X_s  and the B-side
+//                   sum over the zero-padded sub-blocks (FP64, or FP32 with every term rounded to
+//                   FP32 first; pairs as c0*(x0 + (c0*c1) x1), four terms as the sum of the two
+//                   pairs, as in the FP64 kernels), rounds it to FP32, and writes hi = bf16(x)
+//                   (and lo = bf16(x - hi) for bf16x3), rounding to nearest even.  Both sides are
+//                   stored k-contiguous: A-side slot r holds row i at [i * kpad, +kpad), B-side
+//                   slot r column j at [j * kpad, +kpad); padding is zero.  This pass is bound
+//                   by HBM bandwidth.
+//   bf16_gemm_kernel  owns one 128 x 128 tile position in every C sub-block and runs every
+//                   product on it in table order (ABC epilogue: each product is added to each of
+//                   its destination C sub-blocks, beta at the first update).  BF16 operands go
+//                   HBM -> LDS by direct-to-LDS buffer loads, four stages deep, streamed across
+//                   the product boundary; bf16x3 runs hi*hi + hi*lo + lo*hi into the same FP32
+//                   accumulator.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "plan.h"
+#include "tile_fp64.h"
+
+namespace smx {
+
+__constant__ TableDev g_tables_bf16[kNumTables];
+
+hipError_t upload_tables_bf16(const TableDev* tabs) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_tables_bf16), tabs, sizeof(TableDev) * kNumTables, 0,
+                           hipMemcpyHostToDevice);
+}
+
+namespace {
+
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// float -> bf16 bits, round to nearest, ties to even (NaN -> quiet NaN).
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, x);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Operand pass.  One workgroup: a 64 (outer index) x 64 (k) block of one product's operand.
+// ---------------------------------------------------------------------------------------------
+constexpr int kCastT = 64;
+
+template <int NT>
+__device__ __forceinline__ float pair_rule_sum(const double* x, const double* sg, bool f64) {
+  if (f64) return (float)signed_sum<NT>(sg, x);
+  float xf[NT], sf[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    xf[t] = (float)x[t];
+    sf[t] = (float)sg[t];
+  }
+  if (NT == 1) return sf[0] * xf[0];
+  const float p01 = sf[0] * (xf[0] + (sf[0] * sf[1]) * xf[1]);
+  if (NT == 2) return p01;
+  return p01 + sf[2] * (xf[2] + (sf[2] * sf[3]) * xf[3]);
+}
+
+__global__ __launch_bounds__(256) void cast_kernel(const CastArgs args) {
+  __shared__ float tile[kCastT][kCastT + 1];
+  const TableDev& tab = g_tables_bf16[args.tab];
+  const int slot = blockIdx.z;
+  const ProdDesc& pd = tab.prod[slot];
+  const int nt = args.side == 0 ? pd.na : pd.nb;
+  const uint8_t* codes = args.side == 0 ? pd.a : pd.b;
+  const int64_t o0 = (int64_t)blockIdx.x * kCastT;   // outer index (A: row, B: column)
+  const int64_t k0 = (int64_t)blockIdx.y * kCastT;
+  const int t = threadIdx.x;
+  // source element (outer o, k kk) of the sub-block term: A (row o, col kk), B (row kk, col o)
+  auto load_sum = [&](int64_t o, int64_t kk) -> float {
+    double x[kMaxTerms], sg[kMaxTerms];
+    for (int s = 0; s < nt; ++s) {
+      const uint8_t c = codes[s];
+      // A: row block code_row, col block code_col; B: row block code_row (k), col code_col
+      const int64_t r = args.side == 0 ? code_row(c) * args.rq + o : code_row(c) * args.rq + kk;
+      const int64_t cidx = args.side == 0 ? code_col(c) * args.cq + kk : code_col(c) * args.cq + o;
+      const bool in_blk = args.side == 0 ? (o < args.rq && kk < args.cq) : (kk < args.rq && o < args.cq);
+      const bool ok = in_blk && r < args.rows && cidx < args.cols;
+      x[s] = ok ? args.src[r + cidx * args.ld] : 0.0;
+      sg[s] = code_neg(c) ? -1.0 : 1.0;
+    }
+    if (nt == 1) return pair_rule_sum<1>(x, sg, args.sum_f64);
+    if (nt == 2) return pair_rule_sum<2>(x, sg, args.sum_f64);
+    return pair_rule_sum<4>(x, sg, args.sum_f64);
+  };
+  const size_t slot_off = (size_t)slot * args.slot_stride;
+  auto store16 = [&](int64_t o, int64_t kc, const float* v) {
+    // 16 consecutive k of outer index o: hi (and lo) as two 16-byte stores each
+    uint32_t hw[8], lw[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint16_t h0 = bf16_bits(v[2 * e]), h1 = bf16_bits(v[2 * e + 1]);
+      hw[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      const uint16_t l0 = bf16_bits(v[2 * e] - bf16_value(h0));
+      const uint16_t l1 = bf16_bits(v[2 * e + 1] - bf16_value(h1));
+      lw[e] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+    const size_t off = slot_off + (size_t)o * args.kpad + kc;
+    u4_t* dh = reinterpret_cast<u4_t*>(args.hi + off);
+    dh[0] = (u4_t){hw[0], hw[1], hw[2], hw[3]};
+    dh[1] = (u4_t){hw[4], hw[5], hw[6], hw[7]};
+    if (args.lo) {
+      u4_t* dl = reinterpret_cast<u4_t*>(args.lo + off);
+      dl[0] = (u4_t){lw[0], lw[1], lw[2], lw[3]};
+      dl[1] = (u4_t){lw[4], lw[5], lw[6], lw[7]};
+    }
+  };
+  const int oo = t >> 2, kc = (t & 3) * 16;   // this thread's outer index and 16 k values
+  if (args.side == 1) {
+    // B: k runs down a source column, contiguous both ways
+    float v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = load_sum(o0 + oo, k0 + kc + e);
+    store16(o0 + oo, k0 + kc, v);
+    return;
+  }
+  // A: read down source columns (rows o contiguous), transpose through LDS
+  {
+    const int kk = t >> 2, ob = (t & 3) * 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tile[kk][ob + e] = load_sum(o0 + ob + e, k0 + kk);
+  }
+  __syncthreads();
+  float v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = tile[kc + e][oo];
+  store16(o0 + oo, k0 + kc, v);
+}
+
+// ---------------------------------------------------------------------------------------------
+// BF16 product kernel.
+// ---------------------------------------------------------------------------------------------
+template <bool X3>
+struct Bf16Gemm {
+  static constexpr int BM = 128, BN = 128, BK = 64;   // BK in bf16 elements (128 bytes a row)
+  static constexpr int NS = X3 ? 2 : 4;               // LDS stages
+  static constexpr int TILE_B = BM * BK * 2;          // bytes of one 128 x 64 bf16 tile (16 KB)
+  static constexpr int NTL = X3 ? 4 : 2;              // tiles per stage: A hi, B hi (, A lo, B lo)
+  static constexpr int STAGE_B = NTL * TILE_B;
+  static constexpr int IPT = TILE_B / 1024;           // 64-lane x 16-byte loads per tile (16)
+  static constexpr int IPW = NTL * IPT / 4;           // per wave and step (4 waves)
+  static constexpr int LDS_B = NS * STAGE_B;
+  static_assert(LDS_B <= 160 * 1024, "LDS");
+
+  __device__ static void run(const Bf16Args& args, char* lds) {
+    const TableDev& tab = g_tables_bf16[args.tab];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    int ti, tj;
+    tile_coords(logical, args.tiles_m, args.tiles_n, ti, tj);
+    const int64_t row0 = (int64_t)ti * BM, col0 = (int64_t)tj * BN;
+    const int nk = (int)(args.kpad / BK);
+    const int nprod = tab.nprod;
+    const int total = nprod * nk;
+
+    // Loads: tile position p = 64 u + lane of a 128 x 8-chunk tile: row p / 8, stored chunk p % 8
+    // holds logical k-chunk (p % 8) ^ ((row / 2) % 8).  The swizzle keeps the sixteen lanes of a
+    // fragment read (16 rows, one chunk) on distinct banks.
+    auto issue = [&](int s, int stage) {
+      const bool live = s < total;
+      const int r = live ? s / nk : 0, kt = live ? s - r * nk : 0;
+      char* sb = lds + stage * STAGE_B;
+#pragma unroll
+      for (int j = 0; j < IPW; ++j) {
+        const int u = wave + 4 * j;            // load index over the stage
+        const int tl = u / IPT, part = u % IPT;
+        const int p = part * 64 + lane;
+        const int row = p >> 3, pc = p & 7, c = pc ^ ((row >> 1) & 7);
+        const bool is_a = (tl & 1) == 0, is_lo = tl >= 2;
+        const uint16_t* base = is_a ? (is_lo ? args.TAl : args.TAh) : (is_lo ? args.TBl : args.TBh);
+        const int64_t slot_elems = is_a ? args.stride_a : args.stride_b;
+        const int64_t rc0 = is_a ? row0 : col0;
+        const uint16_t* src = base + (int64_t)r * slot_elems + (rc0 + row) * args.kpad +
+                              (int64_t)kt * BK + c * 8;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(base), (short)0, 0x7fffffff, 0x00020000);
+        const int64_t off = (const char*)src - (const char*)base;
+        // offsets are below 2^31 (host-checked); steps past the last one load nothing
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(sb + tl * TILE_B + part * 1024),
+                                                 16, live ? (uint32_t)off : kOOB, 0, 0, 0);
+      }
+    };
+
+    // fragment reads: rows (A) / columns (B) 16 f + lane % 16 of the wave's 64, k-chunk 4 kk + g
+    const int g = lane >> 4, li = lane & 15;
+    auto frag = [&](const char* tile, int rr, int chunk) {
+      const int pc = chunk ^ ((rr >> 1) & 7);
+      return *reinterpret_cast<const bf8_t*>(tile + rr * 128 + pc * 16);
+    };
+
+    f4_t acc[4][4];
+    auto zero = [&]() {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f4_t){0.f, 0.f, 0.f, 0.f};
+    };
+    auto compute = [&](int stage) {
+      const char* sb = lds + stage * STAGE_B;
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        bf8_t ah[4], bh[4], al[4], bl[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          ah[f] = frag(sb, wm * 64 + 16 * f + li, 4 * kk + g);
+          bh[f] = frag(sb + TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
+          if (X3) {
+            al[f] = frag(sb + 2 * TILE_B, wm * 64 + 16 * f + li, 4 * kk + g);
+            bl[f] = frag(sb + 3 * TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
+          }
+        }
+#pragma unroll
+        for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < 4; ++fn) {
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fm], bh[fn], acc[fm][fn], 0, 0, 0);
+            if (X3) {
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fm], bl[fn], acc[fm][fn], 0, 0, 0);
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[fm], bh[fn], acc[fm][fn], 0, 0, 0);
+            }
+          }
+      }
+    };
+
+    // Epilogue of product r: lane l, element e of block (fm, fn) is tile row
+    // 64 wm + 16 fm + 4 (l / 16) + e, column 64 wn + 16 fn + l % 16.
+    auto epilogue = [&](int r) {
+      const ProdDesc& pd = tab.prod[r];
+      const int64_t ldc = args.ldc;
+      for (int d = 0; d < pd.nc; ++d) {
+        const uint8_t cc = pd.c[d];
+        const int64_t ci = code_row(cc), cj = code_col(cc);
+        const double ag = code_neg(cc) ? -args.alpha : args.alpha;
+        const bool first = (pd.first >> d) & 1;
+        const bool read_c = !(first && args.beta == 0.0);
+        const int64_t rlim = min64(args.mq, args.m - ci * args.mq) - row0;
+        const int64_t clim = min64(args.nq, args.n - cj * args.nq) - col0;
+        const __amdgpu_buffer_rsrc_t rs =
+            make_rsrc(args.C + (ci * args.mq + row0) + (cj * args.nq + col0) * ldc);
+#pragma unroll
+        for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+          for (int fn = 0; fn < 4; ++fn) {
+            const int cl = wn * 64 + 16 * fn + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int rl = wm * 64 + 16 * fm + 4 * g + e;
+              const bool ok = rl < rlim && cl < clim;
+              const uint32_t off = (uint32_t)(8 * (rl + (int64_t)cl * ldc));
+              double c = __builtin_bit_cast(
+                  double, __builtin_amdgcn_raw_buffer_load_b64(rs, (ok && read_c) ? off : kOOB, 0, 0));
+              const float mv = acc[fm][fn][e];
+              double out;
+              if (args.c_f64) {
+                out = c_update(c, (double)mv, ag, args.beta, first);
+              } else {
+                const float ag32 = (float)ag, b32 = (float)args.beta;
+                float c32 = (float)c;
+                if (first) c32 = args.beta == 0.0 ? ag32 * mv : __builtin_fmaf(ag32, mv, b32 * c32);
+                else c32 = __builtin_fmaf(ag32, mv, c32);
+                out = (double)c32;
+              }
+              __builtin_amdgcn_raw_buffer_store_b64(as_u2(out), rs, ok ? off : kOOB, 0, 0);
+            }
+          }
+      }
+    };
+
+    // Step s = (product s / nk, k step s % nk) lives in stage s % NS.  Iteration s: with step s
+    // landed (the NS - 2 newest batches may still fly) the barrier publishes it and has every
+    // read of step s - 1 done, so the loads of step s + NS - 1 go into that step's stage.
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s) issue(s, s);
+    zero();
+    int stage = 0;
+    for (int s = 0; s < total; ++s) {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IPW * (NS - 2)) : "memory");
+      __syncthreads();
+      issue(s + NS - 1, stage == 0 ? NS - 1 : stage - 1);
+      compute(stage);
+      stage = stage + 1 == NS ? 0 : stage + 1;
+      const int r = s / nk;
+      if (s - r * nk == nk - 1) {
+        epilogue(r);
+        zero();
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+};
+
+template <bool X3>
+__global__ __launch_bounds__(256, 1) void bf16_gemm_kernel(const Bf16Args args) {
+  using K = Bf16Gemm<X3>;
+  __shared__ __attribute__((aligned(16))) char lds[K::LDS_B];
+  K::run(args, lds);
+}
+
+}  // namespace
+
+hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
+  const dim3 grid((unsigned)(a.outer_pad / kCastT), (unsigned)(a.kpad / kCastT), (unsigned)nslots);
+  hipLaunchKernelGGL(cast_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s) {
+  const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(256);
+  if (a.x3) hipLaunchKernelGGL(bf16_gemm_kernel<true>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(bf16_gemm_kernel<false>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace smx

@@ -106,6 +106,37 @@ struct SumArgs {
   int32_t chunks_r;
 };
 
+// Reduced-precision mode, operand pass: slot r (product r) gets the bf16 operand(s) of the
+// product's A-side (side 0) or B-side (side 1) sum, k-contiguous: element (outer o, k) at
+// hi/lo + r * slot_stride + o * kpad + k, where outer is the row (A) or the column (B).
+struct CastArgs {
+  const double* src;
+  uint16_t* hi;
+  uint16_t* lo;                 // null: BF16 (no low part)
+  int64_t ld, rows, cols;       // source matrix (A: m x k, B: k x n)
+  int64_t rq, cq;               // sub-block extents (A: mq x kq, B: kq x nq)
+  int64_t outer_pad, kpad;      // padded outer extent (multiple of 128) and k extent (of 64)
+  int64_t slot_stride;          // elements per slot
+  int32_t tab;
+  int32_t side;
+  int32_t sum_f64;              // 1: sums in FP64 then rounded to FP32; 0: FP32 throughout
+};
+
+// Reduced-precision mode, product kernel.
+struct Bf16Args {
+  const uint16_t* TAh;
+  const uint16_t* TAl;
+  const uint16_t* TBh;
+  const uint16_t* TBl;
+  int64_t stride_a, stride_b, kpad;   // slot strides (elements); padded k (multiple of 64)
+  double* C;
+  int64_t ldc, m, n, mq, nq;
+  double alpha, beta;
+  int32_t tab, tiles_m, tiles_n;
+  int32_t x3;                   // 1: bf16x3 (hi*hi + hi*lo + lo*hi)
+  int32_t c_f64;                // 1: C update in FP64, 0: in FP32
+};
+
 // C := beta*C (alpha == 0 or k == 0).
 struct ScaleArgs {
   double* C;

@@ -116,9 +116,33 @@ def test_workspace_size_errors():
 
 def test_gemm_ex_argument_checks():
     L = sx.lib()
-    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, None, 4, 1.0, None, 4, 1, 0, 7, 0, 0, None)
+    p = ctypes.c_void_p(256)   # never dereferenced: every call below fails its checks first
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, p, 4, p, 4, 1.0, p, 4, 1, 0, 7, 0, 0, None)
     assert rc == -14
-    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, None, 4, 1.0, None, 4, 1, 0, 1, 2, 0, None)
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, p, 4, p, 4, 1.0, p, 4, 1, 0, 1, 2, 0, None)
     assert rc == -15
-    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, None, 4, 1.0, None, 4, 1, 0, 1, 0, 5, None)
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, p, 4, p, 4, 1.0, p, 4, 1, 0, 1, 0, 5, None)
     assert rc == -16
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, p, 4, p, 4, 1.0, p, 4, 1, 1, 1, 0, 0, None)
+    assert rc == -13          # the reduced-precision mode is ABC only
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, None, 4, p, 4, 1.0, p, 4, 1, 0, 1, 0, 0, None)
+    assert rc == -5
+    rc = L.strassen_gemm_ex(4, 4, 4, 1.0, p, 4, p, 4, 1.0, p, 4, 3, 0, 1, 0, 0, None)
+    assert rc == -12
+    # m == 0: quick return before any device work
+    assert L.strassen_gemm_ex(0, 4, 4, 1.0, p, 1, p, 4, 1.0, p, 1, 1, 0, 1, 0, 0, None) == 0
+
+
+@pytest.mark.parametrize("m,n,k", [(512, 512, 512), (1000, 777, 333), (8192, 8192, 8192)])
+def test_workspace_size_ex(m, n, k):
+    for levels in (0, 1, 2):
+        q = 2 ** levels
+        mp = _cdiv(_cdiv(m, q), 128) * 128
+        np_ = _cdiv(_cdiv(n, q), 128) * 128
+        kp = _cdiv(_cdiv(k, q), 64) * 64
+        nprod = 7 ** levels
+        assert sx.workspace_size_ex(m, n, k, levels, "f64") == 0
+        assert sx.workspace_size_ex(m, n, k, levels, "bf16") == 2 * nprod * (mp + np_) * kp
+        assert sx.workspace_size_ex(m, n, k, levels, "bf16x3") == 4 * nprod * (mp + np_) * kp
+    out = ctypes.c_size_t()
+    assert sx.lib().strassen_workspace_size_ex(1, 1, 1, 1, 3, ctypes.byref(out)) == -5

@@ -1,0 +1,69 @@
+"""Reduced-precision mode on the GPU (BF16 / bf16x3 products on MFMA with FP32 accumulation)
+against the CPU oracle of the same mode (oracle/lowprec.py) and the FP64 oracle.
+
+  * small-integer inputs: every step is exact, so every mode must return the exact product
+    (bit-exact against the FP64 oracle);
+  * real inputs: |C_gpu - C_mode_oracle| <= the oracle's elementwise bound, which allows for
+    FP32 accumulation in any order and the fused multiply-add of the update (the operands
+    themselves, sums and bf16 rounding, must be identical on both sides).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle_dgemm, rel_fro
+from oracle.lowprec import gemm_lowprec
+
+torch = pytest.importorskip("torch")
+sx = pytest.importorskip("paper_1605_01078_amd")
+
+pytestmark = pytest.mark.gpu
+MODES = [(c, s, u) for c in ("bf16", "bf16x3") for s in ("f32", "f64") for u in ("f32", "f64")]
+
+
+def run_ex(A, B, C, alpha, beta, levels, mode):
+    compute, sp, cp = mode
+    dA, dB, dC = sx.to_device(A), sx.to_device(B), sx.to_device(C)
+    sx.gemm_ex(dA, dB, dC, alpha, beta, levels, compute, sp, cp)
+    torch.cuda.synchronize()
+    return sx.to_host(dC)
+
+
+@pytest.mark.parametrize("shape", [(512, 512, 512), (300, 260, 270), (130, 70, 200)])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_integer_inputs_bit_exact(shape, levels):
+    m, n, k = shape
+    print(f"case lowprec integer {shape} L={levels}", flush=True)
+    A, B, C = W.problem(41, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    for mode in MODES:
+        assert np.array_equal(run_ex(A, B, C, 1.0, 1.0, levels, mode), ref), mode
+
+
+@pytest.mark.parametrize("shape,kind", [((256, 256, 256), "uniform"), ((300, 260, 270), "uniform"),
+                                        ((256, 192, 320), "wide_both")])
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_real_inputs_within_bound(shape, kind, levels):
+    m, n, k = shape
+    print(f"case lowprec reals {shape} {kind} L={levels}", flush=True)
+    A, B, C = W.problem(42, m, n, k, kind)
+    for mode in MODES:
+        ref, bound = gemm_lowprec(A, B, C, -0.5, 2.5, levels, *mode)
+        got = run_ex(A, B, C, -0.5, 2.5, levels, mode)
+        excess = np.abs(got - ref) - bound
+        assert (excess <= 0).all(), (mode, float(excess.max()), float(np.abs(got - ref).max()))
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+def test_beta_zero_nan_and_error_order(levels):
+    m = n = k = 256
+    print(f"case lowprec beta0 L={levels}", flush=True)
+    A, B, C = W.problem(43, m, n, k, "uniform")
+    Cn = np.full_like(C, np.nan)
+    exact = oracle_dgemm(A, B, np.zeros_like(C, order="F"), 1.0, 0.0)
+    err = {}
+    for mode in (("bf16", "f64", "f64"), ("bf16x3", "f64", "f64")):
+        got = run_ex(A, B, Cn, 1.0, 0.0, levels, mode)
+        assert np.isfinite(got).all()
+        err[mode[0]] = rel_fro(got, exact)
+    assert err["bf16"] < 3e-2 and err["bf16x3"] < 1e-4 and err["bf16x3"] < 0.05 * err["bf16"]
