@@ -64,6 +64,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
+    p.add_argument("--suite", default="headline", choices=["headline", "precision"],
+                   help="headline: the FP64 step above; precision: the reduced-precision mode "
+                        "table (m=n=k=--n, default 8192 for this suite), one JSON line")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script "
                         "with --copy-calibration into the traffic summary under profiles/, then exit")
@@ -147,6 +150,78 @@ def timed(fn, reps, stream):
     return float(np.median(ts)), ts
 
 
+def precision_suite(args):
+    """Reduced-precision mode at m=n=k (default 8192): for each level, product type, sum and
+    update precision and input class, the time of one call and the relative Frobenius error
+    against the FP64 oracle on sampled columns; beside them the FP64 classical GEMM and the
+    same-mode classical (levels 0) product, and the roofline of the BF16 product kernel."""
+    import torch
+    import paper_1605_01078_amd as sx
+    import workloads as W
+    from oracle import oracle_dgemm, rel_fro
+
+    n = args.n if args.n != 16384 else 8192
+    stream = torch.cuda.current_stream()
+    flops = 2.0 * n ** 3
+    g = np.random.default_rng(0)
+    cols = np.sort(g.choice(n, size=16, replace=False))
+    tcols = torch.as_tensor(cols, device="cuda")
+    kinds = ["uniform", "wide_a", "wide_b", "wide_both"]
+    modes = [(c, s_, u) for c in ("bf16", "bf16x3") for s_ in ("f32", "f64") for u in ("f32", "f64")]
+    rows, kernel_ms = [], {}
+    for kind in kinds:
+        A_h, B_h, C_h = W.problem(7, n, n, n, kind)
+        ref = oracle_dgemm(A_h, np.asfortranarray(B_h[:, cols]), np.asfortranarray(C_h[:, cols]),
+                           1.0, 1.0)
+        A, B, C0 = sx.to_device(A_h), sx.to_device(B_h), sx.to_device(C_h)
+        del A_h, B_h, C_h
+        sel = modes if kind == "uniform" else [("bf16", "f32", "f32"), ("bf16x3", "f64", "f64")]
+        if kind == "uniform":
+            C = C0.clone()
+            f = lambda: sx.dgemm(A, B, C, 1.0, 1.0, 0, "abc", stream)
+            f()
+            ms64, _ = timed(f, 3, stream)
+            rows.append({"input": kind, "levels": 0, "mode": "f64", "ms": round(ms64, 3),
+                         "tflops": round(flops / (ms64 * 1e-3) * 1e-12, 2)})
+        for L in (0, 1, 2):
+            for mode in sel:
+                C = C0.clone()
+                f = lambda: sx.gemm_ex(A, B, C, 1.0, 1.0, L, *mode, stream=stream)
+                f()
+                torch.cuda.synchronize()
+                err = float(rel_fro(C[:, tcols].cpu().numpy(), ref))
+                ms, _ = timed(f, 3, stream)
+                rows.append({"input": kind, "levels": L, "mode": "/".join(mode), "ms": round(ms, 3),
+                             "tflops": round(flops / (ms * 1e-3) * 1e-12, 2),
+                             "rel_err_vs_fp64": float(f"{err:.3e}")})
+                log(f"  {kind:9s} L={L} {'/'.join(mode):18s} {ms:8.3f} ms  err {err:.3e}")
+        del A, B, C0, C
+        sx.release_workspace()
+        torch.cuda.empty_cache()
+    # headline of the suite: two-level bf16x3 (FP64 sums and update) on uniform inputs
+    base = {(r["mode"], r["levels"]): r for r in rows if r["input"] == "uniform"}
+    head = base[("bf16x3/f64/f64", 2)]
+    for r in rows:
+        if r["input"] == "uniform" and r["levels"] > 0:
+            r["speedup_vs_same_mode_classical"] = round(base[(r["mode"], 0)]["ms"] / r["ms"], 4)
+    q = 4
+    exec_flops = 49 * 2.0 * (n // q) ** 3 * 3
+    out = {"metric": "effective TFLOPS (2mnk/t) of the reduced-precision mode, with rel error vs FP64",
+           "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16x3 products, FP32 accumulation, FP64 sums/update",
+           "data": "synthetic",
+           "config": {"workload": f"strassen_gemm_ex L=2 bf16x3 m=n=k={n}, inputs uniform[-1,1] "
+                                  "and wide-range rows 2^U[-8,8]", "m": n, "n": n, "k": n},
+           "roofline": {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s",
+                        "achieved_note": "executed bf16 MFMA flops of the two-level bf16x3 call "
+                                         "(operand pass included) over its time",
+                        "achieved": round(exec_flops / (head["ms"] * 1e-3) * 1e-12, 2),
+                        "frac": round(exec_flops / (head["ms"] * 1e-3) * 1e-12 / 2500.0, 4)},
+           "table": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -161,6 +236,9 @@ def main():
     import workloads as W
 
     sx.lib()  # fails loudly if the HIP library is not built
+    if args.suite == "precision":
+        precision_suite(args)
+        return
     if args.copy_calibration:
         copy_calibration()
     dev = torch.cuda.current_device()

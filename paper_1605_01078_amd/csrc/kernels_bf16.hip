@@ -53,9 +53,9 @@ __device__ __forceinline__ float bf16_value(uint16_t h) {
 // ---------------------------------------------------------------------------------------------
 constexpr int kCastT = 64;
 
-template <int NT>
-__device__ __forceinline__ float pair_rule_sum(const double* x, const double* sg, bool f64) {
-  if (f64) return (float)signed_sum<NT>(sg, x);
+template <int NT, bool F64>
+__device__ __forceinline__ float pair_rule_sum(const double* x, const double* sg) {
+  if (F64) return (float)signed_sum<NT>(sg, x);
   float xf[NT], sf[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -68,33 +68,61 @@ __device__ __forceinline__ float pair_rule_sum(const double* x, const double* sg
   return p01 + sf[2] * (xf[2] + (sf[2] * sf[3]) * xf[3]);
 }
 
+// Each thread sums 16 consecutive elements of one source column: A side, rows ob.. of column
+// kk (written through an LDS transpose, since the operand is stored k-contiguous); B side,
+// k values kc.. of column oo (already k-contiguous).  The term pointers and their valid extents
+// are set up once per thread; the element loop only loads and adds.
+template <int NT, bool F64>
+__device__ __forceinline__ void cast_column(const CastArgs& args, const ProdDesc& pd, int64_t o0,
+                                            int64_t k0, int col_local, int row_local,
+                                            float* v) {
+  const uint8_t* codes = args.side == 0 ? pd.a : pd.b;
+  // per term: a buffer over the workgroup's block of the term (uniform base), the lane's byte
+  // offset in it and how many of its 16 elements exist; missing ones get an offset past the
+  // buffer range and load as zero, without a branch
+  __amdgpu_buffer_rsrc_t rs[NT];
+  uint32_t off[NT];
+  int nrow[NT];
+  double sg[NT];
+  const int64_t r_blk = args.side == 0 ? o0 : k0, c_blk = args.side == 0 ? k0 : o0;
+#pragma unroll
+  for (int s = 0; s < NT; ++s) {
+    const uint8_t c = codes[s];
+    const int64_t br = code_row(c), bc = code_col(c);
+    const int64_t r_ext = min64(args.rq, args.rows - br * args.rq);   // valid rows of the block
+    const int64_t c_ext = min64(args.cq, args.cols - bc * args.cq);
+    rs[s] = make_rsrc(args.src + (br * args.rq + r_blk) + (bc * args.cq + c_blk) * args.ld);
+    const bool col_ok = c_blk + col_local < c_ext;
+    nrow[s] = col_ok ? (int)min64(16, max(int64_t(0), r_ext - r_blk - row_local)) : 0;
+    off[s] = (uint32_t)(8 * (row_local + (int64_t)col_local * args.ld));
+    sg[s] = code_neg(c) ? -1.0 : 1.0;
+  }
+  double xs[NT][16];
+#pragma unroll
+  for (int s = 0; s < NT; ++s)
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      xs[s][e] = __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(rs[s], e < nrow[s] ? off[s] + 8 * e : kOOB, 0, 0));
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    double x[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) x[s] = xs[s][e];
+    v[e] = pair_rule_sum<NT, F64>(x, sg);
+  }
+}
+
+template <bool F64>
 __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args) {
   __shared__ float tile[kCastT][kCastT + 1];
   const TableDev& tab = g_tables_bf16[args.tab];
   const int slot = blockIdx.z;
   const ProdDesc& pd = tab.prod[slot];
   const int nt = args.side == 0 ? pd.na : pd.nb;
-  const uint8_t* codes = args.side == 0 ? pd.a : pd.b;
   const int64_t o0 = (int64_t)blockIdx.x * kCastT;   // outer index (A: row, B: column)
   const int64_t k0 = (int64_t)blockIdx.y * kCastT;
   const int t = threadIdx.x;
-  // source element (outer o, k kk) of the sub-block term: A (row o, col kk), B (row kk, col o)
-  auto load_sum = [&](int64_t o, int64_t kk) -> float {
-    double x[kMaxTerms], sg[kMaxTerms];
-    for (int s = 0; s < nt; ++s) {
-      const uint8_t c = codes[s];
-      // A: row block code_row, col block code_col; B: row block code_row (k), col code_col
-      const int64_t r = args.side == 0 ? code_row(c) * args.rq + o : code_row(c) * args.rq + kk;
-      const int64_t cidx = args.side == 0 ? code_col(c) * args.cq + kk : code_col(c) * args.cq + o;
-      const bool in_blk = args.side == 0 ? (o < args.rq && kk < args.cq) : (kk < args.rq && o < args.cq);
-      const bool ok = in_blk && r < args.rows && cidx < args.cols;
-      x[s] = ok ? args.src[r + cidx * args.ld] : 0.0;
-      sg[s] = code_neg(c) ? -1.0 : 1.0;
-    }
-    if (nt == 1) return pair_rule_sum<1>(x, sg, args.sum_f64);
-    if (nt == 2) return pair_rule_sum<2>(x, sg, args.sum_f64);
-    return pair_rule_sum<4>(x, sg, args.sum_f64);
-  };
   const size_t slot_off = (size_t)slot * args.slot_stride;
   auto store16 = [&](int64_t o, int64_t kc, const float* v) {
     // 16 consecutive k of outer index o: hi (and lo) as two 16-byte stores each
@@ -117,23 +145,20 @@ __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args) {
       dl[1] = (u4_t){lw[4], lw[5], lw[6], lw[7]};
     }
   };
-  const int oo = t >> 2, kc = (t & 3) * 16;   // this thread's outer index and 16 k values
-  if (args.side == 1) {
-    // B: k runs down a source column, contiguous both ways
-    float v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = load_sum(o0 + oo, k0 + kc + e);
-    store16(o0 + oo, k0 + kc, v);
+  const int cl = t >> 2, rl = (t & 3) * 16;   // column within the block, first of 16 rows
+  float v[16];
+  if (nt == 1) cast_column<1, F64>(args, pd, o0, k0, cl, rl, v);
+  else if (nt == 2) cast_column<2, F64>(args, pd, o0, k0, cl, rl, v);
+  else cast_column<4, F64>(args, pd, o0, k0, cl, rl, v);
+  if (args.side == 1) {   // B: column cl is outer index o0 + cl, rows are k values k0 + rl..
+    store16(o0 + cl, k0 + rl, v);
     return;
   }
-  // A: read down source columns (rows o contiguous), transpose through LDS
-  {
-    const int kk = t >> 2, ob = (t & 3) * 16;
+  // A: column cl is k value k0 + cl, rows are outer indices o0 + rl..; transpose through LDS
 #pragma unroll
-    for (int e = 0; e < 16; ++e) tile[kk][ob + e] = load_sum(o0 + ob + e, k0 + kk);
-  }
+  for (int e = 0; e < 16; ++e) tile[cl][rl + e] = v[e];
   __syncthreads();
-  float v[16];
+  const int oo = t >> 2, kc = (t & 3) * 16;
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = tile[kc + e][oo];
   store16(o0 + oo, k0 + kc, v);
@@ -314,7 +339,8 @@ __global__ __launch_bounds__(256, 1) void bf16_gemm_kernel(const Bf16Args args) 
 
 hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
   const dim3 grid((unsigned)(a.outer_pad / kCastT), (unsigned)(a.kpad / kCastT), (unsigned)nslots);
-  hipLaunchKernelGGL(cast_kernel, grid, dim3(256), 0, s, a);
+  if (a.sum_f64) hipLaunchKernelGGL(cast_kernel<true>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(cast_kernel<false>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
