@@ -148,6 +148,55 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
                                size_t *bytes);
 
 /*
+ * Batched mode — many independent FP64 GEMMs  C_p := alpha*A_p*B_p + beta*C_p  (p < count) in
+ * one persistent kernel launch.  The paper chooses "the right member of the family" per problem
+ * size (Sec. 5); here every problem gets its own Strassen level (0, 1, 2; the ABC variant) and
+ * tile shape (0: 128 x 128, 1: 64 x 64).  A work item is one tile position of one problem, on
+ * which one workgroup runs all the problem's products; items are handed out longest first
+ * through a device counter.  Per problem the result is bitwise that of strassen_dgemm with the
+ * same level and tile shape (strassen_set_tile_config 0 / 1).
+ *
+ * strassen_batched_plan(count, m, n, k, levels, cfg, plan): problem sizes (host arrays of
+ *   `count`).  levels / cfg (host, may be NULL = all -1): -1 lets the library choose by its rule
+ *   (level from min(m, n, k) thresholds, 64 x 64 tiles when the 128 x 128 grid of a sub-block is
+ *   small); the chosen values are written back.  *plan receives an opaque handle (host memory).
+ *   Returns 0, -1 count < 0, -2 NULL or negative sizes, -5 / -6 a level / cfg out of range,
+ *   -7 plan NULL.  Needs no device.
+ * strassen_batched_autotune(plan, sample, seed, stream): times the persistent kernel on `sample`
+ *   problems of the plan (seeded choice; 0 = all) under candidate rule thresholds, on zeroed
+ *   library-owned buffers of the same shapes, and re-chooses every -1 entry with the fastest
+ *   rule.  Synchronises `stream`.  Returns 0, -1, -2, or a positive error.
+ * strassen_batched_choice(plan, i, level, cfg): the current choice for problem i.
+ * strassen_batched_run(plan, A, lda, B, ldb, C, ldc, alpha, beta, stream): host arrays of
+ *   `count` device pointers and leading dimensions (column-major, as strassen_dgemm); enqueues
+ *   the launch on `stream` (after copying the work list to the device, which synchronises the
+ *   stream).  alpha, beta are common to the batch; problems with alpha == 0 or k == 0 only
+ *   scale C.  Returns 0, -1 plan NULL, -2 NULL arrays, -3 a bad problem (message names it), or
+ *   a positive error.
+ * strassen_batched_capture(...same arguments...): prepares the work list for these operands
+ *   and records the launch (counter clear + persistent kernel) as a HIP graph in the plan,
+ *   without running it.  alpha == 0 / k == 0 problems are refused (STRASSEN_ERR_UNSUPPORTED).
+ * strassen_batched_replay(plan, stream): launches the recorded graph on `stream`; every replay
+ *   recomputes C from the operands recorded at capture.  A later run or capture on the plan
+ *   discards the recording (replay then returns -1 until the next capture).
+ * strassen_batched_destroy(plan): synchronises the device and frees the plan (NULL is a no-op).
+ * A plan's device buffers are shared by its runs and replays: calls on one plan that overlap in
+ * time (different streams) race.
+ */
+int strassen_batched_plan(int count, const int64_t *m, const int64_t *n, const int64_t *k,
+                          int *levels, int *cfg, void **plan);
+int strassen_batched_autotune(void *plan, int sample, uint64_t seed, void *stream);
+int strassen_batched_choice(void *plan, int i, int *level, int *cfg);
+int strassen_batched_run(void *plan, const double *const *A, const int64_t *lda,
+                         const double *const *B, const int64_t *ldb, double *const *C,
+                         const int64_t *ldc, double alpha, double beta, void *stream);
+int strassen_batched_capture(void *plan, const double *const *A, const int64_t *lda,
+                             const double *const *B, const int64_t *ldb, double *const *C,
+                             const int64_t *ldc, double alpha, double beta, void *stream);
+int strassen_batched_replay(void *plan, void *stream);
+int strassen_batched_destroy(void *plan);
+
+/*
  * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the
  * kernel and tile configuration per call; 0..4 forces one for every later call in the process:
  *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;

@@ -68,24 +68,25 @@ def lib():
 
 
 def _optional(L):
-    """Signatures of the batched-mode and selector entry points (present in full builds)."""
+    """Signatures of the batched-mode entry points."""
     i64p = ctypes.POINTER(ctypes.c_int64)
     vp, ci, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    ops = [vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p,
+           dbl, dbl, vp]
     specs = {
         "strassen_batched_plan": ([ci, i64p, i64p, i64p, ctypes.POINTER(ci), ctypes.POINTER(ci),
                                    ctypes.POINTER(vp)], ci),
-        "strassen_batched_run": ([vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p,
-                                  ctypes.POINTER(vp), i64p, dbl, dbl, vp], ci),
-        "strassen_batched_capture": ([vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p,
-                                      ctypes.POINTER(vp), i64p, dbl, dbl, vp], ci),
+        "strassen_batched_autotune": ([vp, ci, ctypes.c_uint64, vp], ci),
+        "strassen_batched_choice": ([vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
+        "strassen_batched_run": (ops, ci),
+        "strassen_batched_capture": (ops, ci),
         "strassen_batched_replay": ([vp, vp], ci),
         "strassen_batched_destroy": ([vp], ci),
     }
     for name, (args, res) in specs.items():
-        if hasattr(L, name):
-            f = getattr(L, name)
-            f.argtypes = args
-            f.restype = res
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
 
 
 def last_error():
@@ -260,3 +261,74 @@ def table(levels):
         out.append(([dec(a[i]) for i in range(na.value)], [dec(b[i]) for i in range(nb.value)],
                     [dec(c[i]) for i in range(nc.value)]))
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# batched mode
+# ---------------------------------------------------------------------------------------------
+class Batched:
+    """A batch of independent FP64 GEMMs run by one persistent kernel (see strassen.h).
+
+    shapes: list of (m, n, k); levels / cfg: per-problem lists with -1 = library choice
+    (None = all -1)."""
+
+    def __init__(self, shapes, levels=None, cfg=None):
+        self.count = len(shapes)
+        i64 = ctypes.c_int64 * max(1, self.count)
+        ci = ctypes.c_int * max(1, self.count)
+        self._m = i64(*[s[0] for s in shapes])
+        self._n = i64(*[s[1] for s in shapes])
+        self._k = i64(*[s[2] for s in shapes])
+        lv = ci(*(levels if levels is not None else [-1] * self.count))
+        cf = ci(*(cfg if cfg is not None else [-1] * self.count))
+        self._plan = ctypes.c_void_p()
+        check(lib().strassen_batched_plan(self.count, self._m, self._n, self._k, lv, cf,
+                                          ctypes.byref(self._plan)))
+
+    def autotune(self, sample=64, seed=0, stream=None):
+        check(lib().strassen_batched_autotune(self._plan, int(sample), int(seed), _stream(stream)))
+
+    def choices(self):
+        out = []
+        for i in range(self.count):
+            lv, cf = ctypes.c_int(), ctypes.c_int()
+            check(lib().strassen_batched_choice(self._plan, i, ctypes.byref(lv), ctypes.byref(cf)))
+            out.append((lv.value, cf.value))
+        return out
+
+    def _operands(self, As, Bs, Cs):
+        vp = ctypes.c_void_p * max(1, self.count)
+        i64 = ctypes.c_int64 * max(1, self.count)
+        pa, pb, pc, la, lb, lc = [], [], [], [], [], []
+        for A, B, C in zip(As, Bs, Cs):
+            a, _, _, lda = _mat(A, "A")
+            b, _, _, ldb = _mat(B, "B")
+            c, _, _, ldc = _mat(C, "C")
+            pa.append(a); pb.append(b); pc.append(c)
+            la.append(lda); lb.append(ldb); lc.append(ldc)
+        self._keep = (vp(*pa), i64(*la), vp(*pb), i64(*lb), vp(*pc), i64(*lc))
+        return self._keep
+
+    def run(self, As, Bs, Cs, alpha=1.0, beta=1.0, stream=None):
+        a, la, b, lb, c, lc = self._operands(As, Bs, Cs)
+        check(lib().strassen_batched_run(self._plan, a, la, b, lb, c, lc, alpha, beta,
+                                         _stream(stream)))
+
+    def capture(self, As, Bs, Cs, alpha=1.0, beta=1.0, stream=None):
+        a, la, b, lb, c, lc = self._operands(As, Bs, Cs)
+        check(lib().strassen_batched_capture(self._plan, a, la, b, lb, c, lc, alpha, beta,
+                                             _stream(stream)))
+
+    def replay(self, stream=None):
+        check(lib().strassen_batched_replay(self._plan, _stream(stream)))
+
+    def close(self):
+        if self._plan:
+            check(lib().strassen_batched_destroy(self._plan))
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/strassen.h"
+#include "internal.h"
 #include "launch.h"
 #include "plan.h"
 
@@ -21,7 +22,7 @@ namespace smx {
 // ---------------------------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char* fmt, ...) {
+int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -31,15 +32,11 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-static int hip_fail(hipError_t e, const char* what) {
+int hip_fail(hipError_t e, const char* what) {
   return fail(STRASSEN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define SMX_HIP(call)                                    \
-  do {                                                   \
-    hipError_t e_ = (call);                              \
-    if (e_ != hipSuccess) return smx::hip_fail(e_, #call); \
-  } while (0)
+void clear_error() { g_last_error.clear(); }
 
 // ---------------------------------------------------------------------------------------------
 // Tables.
@@ -86,7 +83,7 @@ static TableDev make_table_dev(int levels, bool naive) {
   return td;
 }
 
-static const TableDev* host_tables() {
+const TableDev* host_tables() {
   static TableDev tabs[kNumTables];
   static std::once_flag once;
   std::call_once(once, [] {
@@ -122,7 +119,7 @@ static std::vector<DeviceState> g_dev;
 static void* g_user_ws = nullptr;
 static size_t g_user_ws_bytes = 0;
 
-static int device_ready(int* dev_out) {
+int device_ready(int* dev_out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail(STRASSEN_ERR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
@@ -136,6 +133,7 @@ static int device_ready(int* dev_out) {
                   prop.gcnArchName);
     SMX_HIP(upload_tables(host_tables()));
     SMX_HIP(upload_tables_bf16(host_tables()));
+    SMX_HIP(upload_tables_batched(host_tables()));
     SMX_HIP(hipDeviceSynchronize());
     g_dev[dev].ready = true;
   }
@@ -175,8 +173,6 @@ static int get_workspace(int dev, size_t bytes, void** out) {
 // ---------------------------------------------------------------------------------------------
 // Planning.
 // ---------------------------------------------------------------------------------------------
-static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-static inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
 struct Plan {
   int levels, variant, q;

@@ -33,6 +33,12 @@ hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s
 hipError_t upload_tables_bf16(const TableDev* tabs);
 hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s);
 hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s);
+// Batched mode: clear the item counter, then the persistent kernel over `grid` workgroups.
+hipError_t upload_tables_batched(const TableDev* tabs);
+hipError_t launch_batched(const BatchProblem* probs, const BatchItem* items, int n_items,
+                          unsigned* counter, bool vec, int grid, hipStream_t s);
+const void* batched_kernel_fn(bool vec);   // kernel symbols, for graph nodes
+const void* clear_counter_fn();
 hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);

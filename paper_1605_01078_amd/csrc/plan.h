@@ -137,6 +137,17 @@ struct Bf16Args {
   int32_t c_f64;                // 1: C update in FP64, 0: in FP32
 };
 
+// Batched mode: one problem (its tile-kernel arguments and tile shape) and one work item.
+struct BatchProblem {
+  GemmArgs g;
+  int32_t cfg;                  // 0: 128 x 128 tiles, 1: 64 x 64
+  int32_t pad;
+};
+struct BatchItem {
+  int32_t problem;
+  int32_t tile;                 // tile index, ti + tiles_m * tj
+};
+
 // C := beta*C (alpha == 0 or k == 0).
 struct ScaleArgs {
   double* C;
