@@ -64,9 +64,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
-    p.add_argument("--suite", default="headline", choices=["headline", "precision"],
+    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
-                        "table (m=n=k=--n, default 8192 for this suite), one JSON line")
+                        "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
+                        "one persistent graph launch; each prints one JSON line")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script "
                         "with --copy-calibration into the traffic summary under profiles/, then exit")
@@ -222,6 +223,110 @@ def precision_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def batched_suite(args):
+    """512 independent FP64 GEMMs, m, n, k uniform over the multiples of 64 in [256, 4096],
+    entries uniform[-1, 1]: the autotuned batch as one graph replay (the timed step), beside the
+    same batch run eagerly, the all-classical batch and the problems one call at a time."""
+    import torch
+    import paper_1605_01078_amd as sx
+    import workloads as W
+    from oracle import oracle_dgemm, rel_fro
+
+    shapes = W.batched_shapes(0)
+    stream = torch.cuda.current_stream()
+    flops = sum(2.0 * m * n * k for m, n, k in shapes)
+    As = [W.device_uniform(10_000 + 3 * i, m, k) for i, (m, n, k) in enumerate(shapes)]
+    Bs = [W.device_uniform(10_001 + 3 * i, k, n) for i, (m, n, k) in enumerate(shapes)]
+    C0 = [W.device_uniform(10_002 + 3 * i, m, n) for i, (m, n, k) in enumerate(shapes)]
+    Cs = [c.clone() for c in C0]
+    torch.cuda.synchronize()
+
+    def reset():
+        for c, c0 in zip(Cs, C0):
+            c.copy_(c0)
+
+    def ev_time(fn, reps):
+        ts = []
+        for _ in range(reps):
+            reset()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), ts
+
+    t0 = time.perf_counter()
+    tuned = sx.Batched(shapes)
+    tuned.autotune(sample=64, seed=0, stream=stream)
+    tune_s = time.perf_counter() - t0
+    choices = tuned.choices()
+    hist = {}
+    for lv, cf in choices:
+        hist[f"L{lv}_{'128' if cf == 0 else '64'}"] = hist.get(f"L{lv}_{'128' if cf == 0 else '64'}", 0) + 1
+    log(f"autotune: {tune_s:.1f} s, choices {hist}")
+    # timed step: the captured graph
+    tuned.capture(As, Bs, Cs, 1.0, 1.0, stream)
+    for _ in range(args.warmup):
+        reset()
+        tuned.replay(stream)
+    torch.cuda.synchronize()
+    ms_graph, ts_graph = ev_time(lambda: tuned.replay(stream), max(3, args.steps))
+    # parity: four problems, eight sampled columns each, against the oracle
+    reset()
+    tuned.replay(stream)
+    torch.cuda.synchronize()
+    g = np.random.default_rng(0)
+    errs = []
+    for i in g.choice(len(shapes), size=4, replace=False):
+        m, n, k = shapes[i]
+        cols = np.sort(g.choice(n, size=8, replace=False))
+        A_h = sx.to_host(As[i])
+        Bc = np.asfortranarray(sx.to_host(Bs[i])[:, cols])
+        Cc = np.asfortranarray(sx.to_host(C0[i])[:, cols])
+        ref = oracle_dgemm(A_h, Bc, Cc, 1.0, 1.0)
+        got = Cs[i][:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+        errs.append({"problem": int(i), "level": choices[i][0], "rel_err": float(rel_fro(got, ref))})
+    tol = {0: 1e-13, 1: 1e-12, 2: 1e-11}
+    parity_pass = all(e["rel_err"] <= tol[e["level"]] for e in errs)
+    # the same batch run eagerly (work list upload included)
+    ms_eager, _ = ev_time(lambda: tuned.run(As, Bs, Cs, 1.0, 1.0, stream), 3)
+    # all-classical batch
+    classical = sx.Batched(shapes, levels=[0] * len(shapes))
+    classical.capture(As, Bs, Cs, 1.0, 1.0, stream)
+    ms_classical, _ = ev_time(lambda: classical.replay(stream), 3)
+    # one call per problem (the library's default single-call path, classical and autotuned level)
+    def one_by_one(levels):
+        for (A, B, C), lv in zip(zip(As, Bs, Cs), levels):
+            sx.dgemm(A, B, C, 1.0, 1.0, lv, "abc", stream)
+    ms_single0, _ = ev_time(lambda: one_by_one([0] * len(shapes)), 3)
+    ms_single_t, _ = ev_time(lambda: one_by_one([lv for lv, _ in choices]), 3)
+    tuned.close()
+    classical.close()
+    tf = lambda ms: round(flops / (ms * 1e-3) * 1e-12, 2)
+    out = {"metric": "effective TFLOPS (sum of 2mnk / t) of 512 FP64 GEMMs in one persistent graph launch",
+           "value": tf(ms_graph), "unit": "TFLOP/s", "n_gpus": 1, "steps": len(ts_graph),
+           "warmup": args.warmup, "ms_per_step": round(ms_graph, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batched: 512 GEMMs, m, n, k uniform over multiples of 64 in "
+                                  "[256, 4096], entries uniform[-1,1], autotuned level and tile "
+                                  "per problem, one hipGraph replay", "problems": len(shapes),
+                      "total_flops": flops},
+           "choices": hist, "autotune_seconds": round(tune_s, 2),
+           "compare": {"graph_replay_ms": round(ms_graph, 3), "eager_run_ms": round(ms_eager, 3),
+                       "batched_all_classical_ms": round(ms_classical, 3),
+                       "one_call_per_problem_classical_ms": round(ms_single0, 3),
+                       "one_call_per_problem_tuned_levels_ms": round(ms_single_t, 3),
+                       "tflops": {"graph": tf(ms_graph), "eager": tf(ms_eager),
+                                  "batched_classical": tf(ms_classical),
+                                  "single_classical": tf(ms_single0),
+                                  "single_tuned": tf(ms_single_t)}},
+           "parity": {"sampled": errs, "pass": parity_pass}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -238,6 +343,9 @@ def main():
     sx.lib()  # fails loudly if the HIP library is not built
     if args.suite == "precision":
         precision_suite(args)
+        return
+    if args.suite == "batched":
+        batched_suite(args)
         return
     if args.copy_calibration:
         copy_calibration()
