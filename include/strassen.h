@@ -197,6 +197,45 @@ int strassen_batched_replay(void *plan, void *stream);
 int strassen_batched_destroy(void *plan);
 
 /*
+ * Selector — picks the member of the family for a shape: member c in 0..6 is
+ *   0 classical, 1 one-level ABC, 2 one-level AB, 3 one-level Naive,
+ *   4 two-level ABC, 5 two-level AB, 6 two-level Naive
+ * (the paper leaves this choice, as a function of problem size, to the user: Sec. 5).
+ *
+ * strassen_select(m, n, k, dtype, levels, variant): dtype 0 = FP64 (strassen_dgemm), 1 = BF16
+ *   (strassen_gemm_ex, ABC members only).  With a network loaded: arg-max of its scores
+ *   (computed by the library's inference kernel on the current device, blocking); otherwise:
+ *   arg-min of strassen_cost_model.  Returns 0 or -i.
+ * strassen_cost_model(m, n, k, dtype, seconds[7]): the analytical model of each member's time
+ *   (the GPU counterpart of the paper's Fig. "tab:breakdown": MFMA time at this library's
+ *   rates and efficiencies, launch latency, and HBM time of the extra passes); +inf for
+ *   members not offered for dtype.  Host only.
+ * strassen_selector_load(params): host array of 4935 floats (the network below) copied into
+ *   the library; NULL unloads it (back to the model).  -1 if a value is not finite.
+ *
+ * The network: x = ((ln s - ln 256) / (ln 20000 - ln 256) for s = m, n, k; dtype), then
+ * h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), scores = W3 h2 + b3 with W1 64x4, W2 64x64,
+ * W3 7x64 (row-major), FP32; parameters flat in the order W1, b1, W2, b2, W3, b3.  Training
+ * entry points (device pointers, enqueued on `stream`):
+ * strassen_mlp_forward(params, X, n, logits, stream): X n x 4, logits n x 7 (row-major).
+ * strassen_mlp_work_size(n, bytes): workspace bytes strassen_mlp_loss_grad needs for n samples.
+ * strassen_mlp_loss_grad(params, X, labels, n, work, grad, loss, stream): mean softmax
+ *   cross-entropy over the n samples into *loss and its gradient (flat, as params) into grad;
+ *   every gradient is summed over the samples in order (deterministic).
+ * strassen_mlp_adam(params, grad, m, v, t, lr, beta1, beta2, eps, stream): one Adam step
+ *   (t counts from 1; m, v the moment buffers, zero before the first step).
+ */
+int strassen_select(int64_t m, int64_t n, int64_t k, int dtype, int *levels, int *variant);
+int strassen_cost_model(int64_t m, int64_t n, int64_t k, int dtype, double *seconds);
+int strassen_selector_load(const float *params);
+int strassen_mlp_forward(const float *params, const float *X, int n, float *logits, void *stream);
+int strassen_mlp_work_size(int n, size_t *bytes);
+int strassen_mlp_loss_grad(const float *params, const float *X, const int *labels, int n,
+                           float *work, float *grad, float *loss, void *stream);
+int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int t, float lr,
+                      float beta1, float beta2, float eps, void *stream);
+
+/*
  * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the
  * kernel and tile configuration per call; 0..4 forces one for every later call in the process:
  *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;

@@ -68,7 +68,7 @@ def lib():
 
 
 def _optional(L):
-    """Signatures of the batched-mode entry points."""
+    """Signatures of the batched-mode and selector entry points."""
     i64p = ctypes.POINTER(ctypes.c_int64)
     vp, ci, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     ops = [vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p,
@@ -82,6 +82,16 @@ def _optional(L):
         "strassen_batched_capture": (ops, ci),
         "strassen_batched_replay": ([vp, vp], ci),
         "strassen_batched_destroy": ([vp], ci),
+        "strassen_select": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ci,
+                             ctypes.POINTER(ci), ctypes.POINTER(ci)], ci),
+        "strassen_cost_model": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ci,
+                                 ctypes.POINTER(ctypes.c_double)], ci),
+        "strassen_selector_load": ([vp], ci),
+        "strassen_mlp_forward": ([vp, vp, ci, vp, vp], ci),
+        "strassen_mlp_work_size": ([ci, ctypes.POINTER(ctypes.c_size_t)], ci),
+        "strassen_mlp_loss_grad": ([vp, vp, vp, ci, vp, vp, vp, vp], ci),
+        "strassen_mlp_adam": ([vp, vp, vp, vp, ci, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, vp], ci),
     }
     for name, (args, res) in specs.items():
         f = getattr(L, name)

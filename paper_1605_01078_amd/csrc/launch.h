@@ -39,6 +39,14 @@ hipError_t launch_batched(const BatchProblem* probs, const BatchItem* items, int
                           unsigned* counter, bool vec, int grid, hipStream_t s);
 const void* batched_kernel_fn(bool vec);   // kernel symbols, for graph nodes
 const void* clear_counter_fn();
+// Selector network (kernels_mlp.hip): flat FP32 parameters W1, b1, W2, b2, W3, b3.
+constexpr int kMlpParams = 64 * 4 + 64 + 64 * 64 + 64 + 7 * 64 + 7;
+hipError_t launch_mlp_forward(const float* params, const float* X, int n, float* logits,
+                              float* A1, float* A2, hipStream_t s);
+hipError_t launch_mlp_backward(const float* params, const float* X, const int* y, int n,
+                               float* work, float* grad, float* loss, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, float lr,
+                           float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);

@@ -1,0 +1,57 @@
+"""Selector, host side: the analytical cost model and the model-based choice (no device)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+sx = pytest.importorskip("paper_1605_01078_amd")
+from paper_1605_01078_amd import selector as S
+
+
+def _model(m, n, k, d):
+    sec = (ctypes.c_double * 7)()
+    sx.check(sx.lib().strassen_cost_model(m, n, k, d, sec))
+    return list(sec)
+
+
+def test_cost_model_members():
+    t = _model(4096, 4096, 4096, 0)
+    assert all(math.isfinite(v) and v > 0 for v in t)
+    tb = _model(4096, 4096, 4096, 1)
+    assert [math.isfinite(v) for v in tb] == [True, True, False, False, True, False, False]
+    # classical time grows like m n k once the GPU is full
+    a, b = _model(8192, 8192, 8192, 0)[0], _model(16384, 16384, 16384, 0)[0]
+    assert 7.0 < b / a < 9.0
+
+
+def test_model_choice_valid_and_strassen_at_large_sizes():
+    for shape in [(256, 256, 256), (1000, 3000, 700), (20000, 300, 20000)]:
+        for d in (0, 1):
+            lv, var = S.select(*shape, d)
+            assert lv in (0, 1, 2) and (d == 0 or var == "abc")
+    # at 16384 the measured order (one-level ABC ahead of classical) is reproduced
+    t = _model(16384, 16384, 16384, 0)
+    assert t[1] < t[0] and S.select(16384, 16384, 16384, 0) == (1, "abc")
+    assert S.select(20000, 20000, 20000, 1)[1] == "abc"
+
+
+def test_select_argument_errors():
+    L = sx.lib()
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert L.strassen_select(-1, 1, 1, 0, ctypes.byref(a), ctypes.byref(b)) == -1
+    assert L.strassen_select(1, 1, 1, 2, ctypes.byref(a), ctypes.byref(b)) == -4
+    assert L.strassen_select(1, 1, 1, 0, None, ctypes.byref(b)) == -5
+    bad = np.full(4935, np.nan, dtype=np.float32)
+    assert L.strassen_selector_load(bad.ctypes.data) == -1
+    assert L.strassen_selector_load(None) == 0
+    sz = ctypes.c_size_t()
+    assert L.strassen_mlp_work_size(10, ctypes.byref(sz)) == 0 and sz.value == 10 * 271 * 4
+
+
+def test_features_match_oracle_definition():
+    from oracle import mlp
+    g = np.random.default_rng(0)
+    m, n, k = (g.integers(256, 20001, 50) for _ in range(3))
+    d = g.integers(0, 2, 50)
+    assert np.allclose(S.features(m, n, k, d), mlp.features(m, n, k, d), rtol=0, atol=1e-6)
