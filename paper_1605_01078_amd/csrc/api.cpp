@@ -514,7 +514,7 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   }
   const LowPlan p = make_low_plan(m, n, k, levels, compute);
   const int64_t lim = int64_t(1) << 31;
-  if (2 * p.slot_a * p.nslots >= lim || 2 * p.slot_b * p.nslots >= lim || 8 * 128 * ldc >= lim)
+  if (2 * p.slot_a >= lim || 2 * p.slot_b >= lim || 8 * 128 * ldc >= lim)
     return fail(STRASSEN_ERR_UNSUPPORTED, "reduced-precision operands past the 32-bit offset range");
   void* ws = nullptr;
   if (int rc = get_workspace(dev, p.bytes, &ws)) return rc;

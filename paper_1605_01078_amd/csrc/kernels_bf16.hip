@@ -206,15 +206,14 @@ struct Bf16Gemm {
         const int p = part * 64 + lane;
         const int row = p >> 3, pc = p & 7, c = pc ^ ((row >> 1) & 7);
         const bool is_a = (tl & 1) == 0, is_lo = tl >= 2;
-        const uint16_t* base = is_a ? (is_lo ? args.TAl : args.TAh) : (is_lo ? args.TBl : args.TBh);
-        const int64_t slot_elems = is_a ? args.stride_a : args.stride_b;
+        // the buffer starts at product r's slot (uniform); offsets inside one slot are below
+        // 2^31 (host-checked); steps past the last one load nothing
+        const uint16_t* base = (is_a ? (is_lo ? args.TAl : args.TAh) : (is_lo ? args.TBl : args.TBh)) +
+                               (int64_t)r * (is_a ? args.stride_a : args.stride_b);
         const int64_t rc0 = is_a ? row0 : col0;
-        const uint16_t* src = base + (int64_t)r * slot_elems + (rc0 + row) * args.kpad +
-                              (int64_t)kt * BK + c * 8;
+        const int64_t off = 2 * ((rc0 + row) * args.kpad + (int64_t)kt * BK + c * 8);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<uint16_t*>(base), (short)0, 0x7fffffff, 0x00020000);
-        const int64_t off = (const char*)src - (const char*)base;
-        // offsets are below 2^31 (host-checked); steps past the last one load nothing
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(sb + tl * TILE_B + part * 1024),
                                                  16, live ? (uint32_t)off : kOOB, 0, 0, 0);
       }

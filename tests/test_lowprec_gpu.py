@@ -67,3 +67,24 @@ def test_beta_zero_nan_and_error_order(levels):
         assert np.isfinite(got).all()
         err[mode[0]] = rel_fro(got, exact)
     assert err["bf16"] < 3e-2 and err["bf16x3"] < 1e-4 and err["bf16x3"] < 0.05 * err["bf16"]
+
+
+def test_two_level_operands_larger_than_2gib():
+    """Two-level bf16x3 operands of all 49 products exceed 2 GiB per side (m = k = 19200); every
+    product's operand buffer is addressed from its own base.  Integer inputs: exact."""
+    m, n, k = 19200, 128, 19200
+    print(f"case lowprec large L=2 {m}x{n}x{k}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(44)
+    A = torch.randint(-8, 9, (k, m), generator=g, device="cuda").to(torch.float64).t()
+    B = torch.randint(-8, 9, (n, k), generator=g, device="cuda").to(torch.float64).t()
+    C = torch.zeros((n, m), dtype=torch.float64, device="cuda").t()
+    assert sx.workspace_size_ex(m, n, k, 2, "bf16x3") > 2 ** 32
+    sx.gemm_ex(A, B, C, 1.0, 0.0, 2, "bf16x3", "f64", "f64")
+    torch.cuda.synchronize()
+    cols = np.array([0, 17, 64, 127])
+    A_h = sx.to_host(A)
+    ref = oracle_dgemm(A_h, np.asfortranarray(sx.to_host(B)[:, cols]),
+                       np.zeros((m, len(cols)), order="F"), 1.0, 0.0)
+    got = C[:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    assert np.array_equal(got, ref)
