@@ -64,10 +64,13 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
-    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched"],
+    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
                         "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
-                        "one persistent graph launch; each prints one JSON line")
+                        "one persistent graph launch; selector: the committed network's choice "
+                        "against exhaustive timing on held-out shapes; each prints one JSON line")
+    p.add_argument("--shapes", type=int, default=200,
+                   help="selector suite: held-out shapes timed exhaustively")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script "
                         "with --copy-calibration into the traffic summary under profiles/, then exit")
@@ -327,6 +330,53 @@ def batched_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def selector_suite(args):
+    """The learned selector against exhaustive timing, measured live: a seeded sample of the
+    held-out shapes (m, n, k log-uniform in [256, 20000], FP64 or BF16), every member timed
+    (best of two calls), the choice of the committed network (through the library's selection
+    call and its inference kernel), of the analytical cost model and of each fixed member;
+    regret = total time of the chosen members / total time of the best ones - 1."""
+    import torch
+    import paper_1605_01078_amd as sx
+    from paper_1605_01078_amd import selector as S
+
+    shapes, dtypes = S.dataset()
+    g = np.random.default_rng(7)
+    idx = np.sort(g.choice(np.arange(20000, len(shapes)), size=min(args.shapes, 2000), replace=False))
+    sh = [shapes[i] for i in idx]
+    dt = [dtypes[i] for i in idx]
+    log(f"selector: {len(sh)} held-out shapes, every member timed twice")
+    t0 = time.perf_counter()
+    times = np.minimum(S.collect(sh, dt), S.collect(sh, dt))
+    log(f"  timed in {time.perf_counter() - t0:.0f} s")
+    if not S.install_committed():
+        raise SystemExit("no committed selector network (selector_data/weights.json)")
+    member = {mv: c for c, mv in enumerate(S.MEMBERS)}
+    t1 = time.perf_counter()
+    net = np.array([member[S.select(m, n, k, d)] for (m, n, k), d in zip(sh, dt)])
+    sel_us = (time.perf_counter() - t1) / len(sh) * 1e6
+    model = S.model_choice(sh, dt)
+    reg = {"network": S.regret(times, net), "cost_model": S.regret(times, model)}
+    for c, (lv, v) in enumerate(S.MEMBERS):
+        ch = np.array([c if S.available(int(d))[c] else 0 for d in dt])
+        reg[f"always_L{lv}_{v}"] = S.regret(times, ch)
+    reg["best_fixed"] = min(v for k_, v in reg.items() if k_.startswith("always_"))
+    hits = float(np.mean(net == times.argmin(axis=1)))
+    out = {"metric": "regret of the learned selector against exhaustive timing (held-out shapes)",
+           "value": round(100.0 * reg["network"], 3), "unit": "%", "n_gpus": 1,
+           "steps": len(sh), "warmup": 0, "ms_per_step": round(float(times.min(axis=1).mean()), 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "selector: held-out GEMM shapes, m, n, k log-uniform in "
+                                  "[256, 20000], FP64 or BF16, every member timed", "shapes": len(sh),
+                      "members": [f"L{lv}_{v}" for lv, v in S.MEMBERS]},
+           "regret": {k_: round(v, 5) for k_, v in reg.items()},
+           "network_picks_best": round(hits, 4), "select_call_us": round(sel_us, 1),
+           "total_best_ms": round(float(times.min(axis=1).sum()), 2),
+           "total_network_ms": round(float(times[np.arange(len(sh)), net].sum()), 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -346,6 +396,9 @@ def main():
         return
     if args.suite == "batched":
         batched_suite(args)
+        return
+    if args.suite == "selector":
+        selector_suite(args)
         return
     if args.copy_calibration:
         copy_calibration()

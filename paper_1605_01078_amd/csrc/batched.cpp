@@ -60,17 +60,17 @@ static void apply_rule(const Rule& r, int64_t m, int64_t n, int64_t k, int* leve
 }
 
 static void drop_graph(BatchedPlan* p) {
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
 }
 
 static void free_device(BatchedPlan* p) {
   drop_graph(p);
-  if (p->d_probs) hipFree(p->d_probs);
-  if (p->d_items) hipFree(p->d_items);
-  if (p->d_counter) hipFree(p->d_counter);
+  if (p->d_probs) (void)hipFree(p->d_probs);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_counter) (void)hipFree(p->d_counter);
   p->d_probs = nullptr;
   p->d_items = nullptr;
   p->d_counter = nullptr;
@@ -319,10 +319,10 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
     }
   }
   free_device(&sp);
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   hipError_t ef = hipStreamSynchronize(s);
-  hipFree(buf);
+  (void)hipFree(buf);
   if (rc != 0) return rc;
   if (e != hipSuccess) return hip_fail(e, "batched autotune");
   if (ef != hipSuccess) return hip_fail(ef, "batched autotune");
@@ -469,7 +469,7 @@ int strassen_batched_destroy(void* plan) {
   smx::clear_error();
   auto* p = static_cast<smx::BatchedPlan*>(plan);
   if (!p) return 0;
-  if (p->dev >= 0) hipDeviceSynchronize();
+  if (p->dev >= 0) (void)hipDeviceSynchronize();
   smx::free_device(p);
   delete p;
   return 0;

@@ -116,9 +116,9 @@ static int ensure_device_copy() {
   SMX_HIP(hipGetDevice(&dev));
   if (g_sel.dev == dev && g_sel.d_params) return 0;
   if (g_sel.d_params) {
-    hipFree(g_sel.d_params);
-    hipFree(g_sel.d_io);
-    if (g_sel.stream) hipStreamDestroy(g_sel.stream);
+    (void)hipFree(g_sel.d_params);
+    (void)hipFree(g_sel.d_io);
+    if (g_sel.stream) (void)hipStreamDestroy(g_sel.stream);
   }
   g_sel.d_params = nullptr;
   g_sel.d_io = nullptr;

@@ -248,19 +248,42 @@ def load(path=WEIGHTS):
         return np.asarray(json.load(f)["params"], dtype=np.float32)
 
 
+# None: the committed network is installed on the first select(); True/False: decided already
+_network_state = None
+
+
 def install(params):
     """Hand the network to the library: strassen_select uses it from now on."""
+    global _network_state
     a = np.ascontiguousarray(params, dtype=np.float32)
     check(lib().strassen_selector_load(a.ctypes.data))
+    _network_state = True
 
 
 def uninstall():
+    """Back to the analytical cost model (also for later select() calls)."""
+    global _network_state
     check(lib().strassen_selector_load(None))
+    _network_state = False
+
+
+def install_committed():
+    """Install the network trained on this library's own timings (selector_data/weights.json),
+    if present; returns whether a network is installed."""
+    global _network_state
+    if _network_state is None:
+        if os.path.exists(WEIGHTS):
+            install(load())
+        else:
+            _network_state = False
+    return bool(_network_state)
 
 
 def select(m, n, k, dtype=0):
-    """(levels, variant) chosen by the library for one shape."""
+    """(levels, variant) chosen by the library for one shape: by the committed network unless
+    uninstall() was called or none is committed, else by the analytical cost model."""
     import ctypes
+    install_committed()
     lv, var = ctypes.c_int(), ctypes.c_int()
     check(lib().strassen_select(m, n, k, dtype, ctypes.byref(lv), ctypes.byref(var)))
     return lv.value, ["abc", "ab", "naive"][var.value]

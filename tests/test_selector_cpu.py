@@ -7,6 +7,7 @@ import pytest
 
 sx = pytest.importorskip("paper_1605_01078_amd")
 from paper_1605_01078_amd import selector as S
+from oracle import mlp
 
 
 def _model(m, n, k, d):
@@ -26,6 +27,7 @@ def test_cost_model_members():
 
 
 def test_model_choice_valid_and_strassen_at_large_sizes():
+    S.uninstall()   # the analytical cost model decides
     for shape in [(256, 256, 256), (1000, 3000, 700), (20000, 300, 20000)]:
         for d in (0, 1):
             lv, var = S.select(*shape, d)
@@ -55,3 +57,25 @@ def test_features_match_oracle_definition():
     m, n, k = (g.integers(256, 20001, 50) for _ in range(3))
     d = g.integers(0, 2, 50)
     assert np.allclose(S.features(m, n, k, d), mlp.features(m, n, k, d), rtol=0, atol=1e-6)
+
+
+def test_committed_network_file():
+    """The committed network: every parameter finite, in the kernels' layout, with the held-out
+    evaluation it was accepted on."""
+    import json
+    import os
+    assert os.path.exists(S.WEIGHTS) and os.path.exists(S.TIMINGS)
+    p = S.load()
+    assert p.shape == (mlp.N_PARAMS,) and np.isfinite(p).all()
+    meta = json.load(open(S.WEIGHTS))["meta"]
+    assert meta["train_shapes"] == 20000 and meta["held_out_shapes"] == 2000
+    assert meta["held_out"]["network"] <= 0.05
+    times = np.load(S.TIMINGS)["times"]
+    assert times.shape == (22000, 7)
+    # the held-out regret recorded with the weights is the oracle network's on the stored timings
+    shapes, dtypes = S.dataset()
+    X = mlp.features(*np.array(shapes[20000:]).T, dtypes[20000:])
+    z, _ = mlp.forward(p.astype(np.float64), X.astype(np.float32).astype(np.float64))
+    ch = S.choose(z, dtypes[20000:])
+    r = mlp.regret(times[20000:].astype(np.float64), ch)
+    assert abs(r - meta["held_out"]["network"]) < 2e-3
