@@ -454,6 +454,10 @@ def main():
     t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
     end_all = torch.cuda.Event(enable_timing=True)
+    kind = "all_products" if dominant_kernel(L, variant) == "all_products_kernel" else "tile"
+    for k_ in sx.KERNEL_KINDS:   # drop what the warmup recorded
+        sx.timing_collect(k_)
+    sx.timing_enable(True)       # library-side event pairs around each kernel launch
     start_all.record(stream)
     for e0, e1 in ev:
         e0.record(stream)
@@ -461,6 +465,11 @@ def main():
         e1.record(stream)
     end_all.record(stream)
     torch.cuda.synchronize()
+    sx.timing_enable(False)
+    kern_ms, kern_launches = sx.timing_collect(kind)
+    sums_ms, sums_launches = sx.timing_collect("outer_sums")
+    for k_ in sx.KERNEL_KINDS:
+        sx.timing_collect(k_)
     wall = time.perf_counter() - t0
     total_ms = start_all.elapsed_time(end_all)
     per_launch = [e0.elapsed_time(e1) for e0, e1 in ev]
@@ -482,6 +491,18 @@ def main():
             variants[f"L{lev}_{var}"] = {"ms": round(ms, 3),
                                          "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
             log(f"  L={lev} {var:5s}: {ms:8.3f} ms  {variants[f'L{lev}_{var}']['tflops']:6.2f} TF")
+        # two-level ABC with its outer operand sums formed in the tile load (no staging)
+        sx.set_tile_config(4)
+        try:
+            f = call(2, "abc", Cw)
+            f()
+            torch.cuda.synchronize()
+            ms, _ = timed(f, 3, stream)
+        finally:
+            sx.set_tile_config(-1)
+        variants["L2_abc_unstaged"] = {"ms": round(ms, 3),
+                                       "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
+        log(f"  L=2 abc, outer sums in the load: {ms:8.3f} ms")
         base = variants["L0_abc"]["tflops"]
         for key, v in variants.items():
             v["speedup_vs_classical"] = round(v["tflops"] / base, 4)
@@ -490,12 +511,16 @@ def main():
 
     # ---- roofline of the dominant kernel --------------------------------------------------------
     # ABC at one level is one launch of the all-products kernel (7 products); at two levels it is
-    # seven back-to-back launches on the step's stream, one per outer product, each computing 7
-    # inner products, so one launch executes 7 * 2*mq*nq*kq MFMA flops and its average duration
-    # is the event time of a step over 7.  AB / Naive: one tile-kernel launch holds all 7^L
-    # products (the assembly and sum kernels are small beside it).
+    # seven launches, one per outer product, each computing 7 inner products, so one launch
+    # executes 7 * 2*mq*nq*kq MFMA flops.  AB / Naive: one tile-kernel launch holds all 7^L
+    # products.  The average launch duration comes from the library's event pairs around each
+    # launch of that kernel during the timed steps (the staged outer-sum passes of two-level ABC
+    # and the assembly / sum passes are timed apart from it).
     launches = 7 ** (L - 1) if (variant == "abc" and L >= 1) else 1
-    avg_launch_ms = float(np.mean(per_launch)) / launches
+    if kern_launches != launches * args.steps:
+        raise SystemExit(f"expected {launches * args.steps} launches of the {kind} kernel in the "
+                         f"timed steps, recorded {kern_launches}")
+    avg_launch_ms = kern_ms / kern_launches
     exec_flops_launch = exec_flops / launches
     achieved = exec_flops_launch / (avg_launch_ms * 1e-3) * 1e-12
     traffic = None
@@ -509,7 +534,11 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA, 4), "traffic": traffic,
                 "kernel": dominant_kernel(L, variant),
                 "launches_per_step": launches,
-                "exec_flops_per_launch": exec_flops_launch, "avg_launch_ms": round(avg_launch_ms, 3)}
+                "exec_flops_per_launch": exec_flops_launch, "avg_launch_ms": round(avg_launch_ms, 3),
+                "timing": "HIP event pair around each launch on the call's stream, timed steps"}
+    if sums_launches:
+        roofline["outer_sum_passes"] = {"launches_per_step": sums_launches // args.steps,
+                                        "ms_per_step": round(sums_ms / args.steps, 3)}
 
     # ---- CPU baseline: the oracle on a bounded column sample -----------------------------------
     cpu = None
@@ -555,6 +584,7 @@ def main():
         "config": {"workload": f"strassen_dgemm L={L} {variant.upper()} m=n=k={n} FP64 "
                                f"C:=A*B+C, entries uniform[-1,1]",
                    "m": n, "n": n, "k": n, "levels": L, "variant": variant,
+                   "outer_sums": ("staged" if sums_launches else "in the tile load") if L == 2 else None,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

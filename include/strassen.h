@@ -82,7 +82,12 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * The general operation is eq. (e:straprim1) at one level and eq. (e:straprim3) at two.
  * AB and NAIVE use a library-owned workspace (grown on demand, kept until
  * strassen_release_workspace or process exit) unless strassen_set_workspace gave one;
- * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 3.3).
+ * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 3.3).  Two-level ABC
+ * may use one to stage its outer-level operand sums (the ten two-term sums of the one-level
+ * table over the 2 x 2 outer blocks, formed once by a streaming pass; the seven outer products
+ * then run the one-level fused kernel on them and update C in place, bitwise as without
+ * staging): by default where n % 4 == 0, (m/2)(n/2) >= 2048^2 and k >= 2048 and a library-owned
+ * or large enough caller workspace is available; otherwise the sums are formed in the load.
  * Argument positions for -i: m=1 n=2 k=3 alpha=4 A=5 lda=6 B=7 ldb=8 beta=9 C=10 ldc=11
  * levels=12 variant=13.
  */
@@ -93,8 +98,10 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
 
 /*
  * strassen_workspace_size — bytes of device workspace strassen_dgemm needs for these sizes
- * (0 for ABC and for levels 0).  AB: one M_r temporary per product (7^L of
- * ceil(m/2^L) x ceil(n/2^L) doubles); NAIVE adds the operand-sum temporaries.
+ * (0 for levels 0 and one-level ABC).  AB: one M_r temporary per product (7^L of
+ * ceil(m/2^L) x ceil(n/2^L) doubles); NAIVE adds the operand-sum temporaries.  Two-level ABC:
+ * the staging buffers of its outer operand sums where staging is the default (five m/2 x k/2
+ * and five k/2 x n/2 slots, each rounded up to 32 doubles), else 0; less only turns staging off.
  * Returns 0 or -i as strassen_dgemm does for the same argument (m=1 n=2 k=3 levels=4
  * variant=5 bytes=6).
  */
@@ -237,17 +244,37 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
 
 /*
  * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the
- * kernel and tile configuration per call; 0..4 forces one for every later call in the process:
+ * kernel and tile configuration per call; 0..5 forces one for every later call in the process:
  *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;
  *   2: 128 x 128, k step 8, two workgroups per CU;        3: 128 x 128, k step 16, one per CU;
  *   4: ABC with levels >= 1 runs the all-products kernel (the seven products of a level side
  *      by side on 64 x 64 tiles of the four quadrants) wherever its layout applies (m and k
  *      multiples of 2^(levels+1), 16-byte aligned A, B, C, even leading dimensions), the
- *      default choice otherwise.  The default (-1) also uses it wherever it applies.
+ *      default choice otherwise, with the two-level outer sums formed in the load;
+ *   5: as 4, with the two-level outer operand sums staged wherever n % 4 == 0 (the workspace,
+ *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise).
+ * The default (-1) uses the all-products kernel wherever it applies and stages as described
+ * at strassen_dgemm.
  * Results do not depend on the configuration (bitwise).  The environment variable
  * STRASSEN_TILE_CFG sets the initial value.  Returns 0 or -1 (cfg out of range).
  */
 int strassen_set_tile_config(int cfg);
+
+/*
+ * Kernel timing (measurement support).  strassen_timing_enable(1) makes every later call record
+ * a pair of HIP events on its stream around each launch of the kernels below (events from an
+ * internal pool; the extra work is two event records per launch); 0 stops recording.
+ * strassen_timing_collect(kind, ms_total, launches) waits for the recorded launches of `kind`,
+ * returns their summed duration in milliseconds and their number, and forgets them (the other
+ * kinds stay recorded).  Returns 0, -2 (NULL output) or STRASSEN_ERR_HIP.
+ */
+enum strassen_kernel_kind {
+    STRASSEN_KERNEL_ALL_PRODUCTS = 0,  /* the fused ABC kernel (one level; each two-level outer product) */
+    STRASSEN_KERNEL_OUTER_SUMS = 1,    /* the staged outer-sum pass of two-level ABC            */
+    STRASSEN_KERNEL_TILE = 2           /* the general FP64 tile kernel (classical, AB, Naive, ABC fallback) */
+};
+int strassen_timing_enable(int on);
+int strassen_timing_collect(int kind, double *ms_total, int *launches);
 
 /*
  * Table introspection (host only, no device needed): the operation table the kernels execute.

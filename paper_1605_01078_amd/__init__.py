@@ -92,6 +92,8 @@ def _optional(L):
         "strassen_mlp_loss_grad": ([vp, vp, vp, ci, vp, vp, vp, vp], ci),
         "strassen_mlp_adam": ([vp, vp, vp, vp, ci, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, ctypes.c_float, vp], ci),
+        "strassen_timing_enable": ([ci], ci),
+        "strassen_timing_collect": ([ci, ctypes.POINTER(dbl), ctypes.POINTER(ci)], ci),
     }
     for name, (args, res) in specs.items():
         f = getattr(L, name)
@@ -240,9 +242,25 @@ def set_workspace(tensor_or_none):
 
 
 def set_tile_config(cfg):
-    """Force a kernel / tile configuration (0..4, see strassen.h) for later calls, or -1 for the
+    """Force a kernel / tile configuration (0..5, see strassen.h) for later calls, or -1 for the
     automatic choice."""
     check(lib().strassen_set_tile_config(int(cfg)))
+
+
+KERNEL_KINDS = {"all_products": 0, "outer_sums": 1, "tile": 2}
+
+
+def timing_enable(on=True):
+    """Record HIP events around every later launch of the library's main kernels."""
+    check(lib().strassen_timing_enable(1 if on else 0))
+
+
+def timing_collect(kind):
+    """(total milliseconds, launches) of the recorded launches of one kernel kind ("all_products",
+    "outer_sums", "tile"), which are then forgotten; waits for them."""
+    ms, cnt = ctypes.c_double(), ctypes.c_int()
+    check(lib().strassen_timing_collect(KERNEL_KINDS[kind], ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
 
 
 def release_workspace():

@@ -171,6 +171,57 @@ static int get_workspace(int dev, size_t bytes, void** out) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Optional kernel timing (strassen_timing_enable): a pair of events recorded on the launch's
+// stream around every launch of the main kernels; events come from a pool that collect refills.
+// ---------------------------------------------------------------------------------------------
+struct TimedLaunch {
+  int kind;
+  hipEvent_t e0, e1;
+};
+static std::mutex g_tm_mu;
+static std::atomic<bool> g_timing{false};
+static std::vector<TimedLaunch> g_tm_log;
+static std::vector<hipEvent_t> g_tm_pool;
+
+static int pooled_event(hipEvent_t* e) {
+  {
+    std::lock_guard<std::mutex> lk(g_tm_mu);
+    if (!g_tm_pool.empty()) {
+      *e = g_tm_pool.back();
+      g_tm_pool.pop_back();
+      return 0;
+    }
+  }
+  SMX_HIP(hipEventCreate(e));
+  return 0;
+}
+
+// Runs launch() (returning hipError_t), bracketed by events when timing is on.
+template <class F>
+static int timed_launch(int kind, hipStream_t s, F&& launch, const char* what) {
+  if (!g_timing.load(std::memory_order_relaxed)) {
+    hipError_t e = launch();
+    return e == hipSuccess ? 0 : hip_fail(e, what);
+  }
+  TimedLaunch t;
+  t.kind = kind;
+  if (int rc = pooled_event(&t.e0)) return rc;
+  if (int rc = pooled_event(&t.e1)) return rc;
+  SMX_HIP(hipEventRecord(t.e0, s));
+  hipError_t e = launch();
+  if (e != hipSuccess) return hip_fail(e, what);
+  SMX_HIP(hipEventRecord(t.e1, s));
+  std::lock_guard<std::mutex> lk(g_tm_mu);
+  g_tm_log.push_back(t);
+  return 0;
+}
+
+#define SMX_LAUNCH(kind, stream, call)                                                 \
+  do {                                                                                 \
+    if (int rc_ = timed_launch((kind), (stream), [&] { return (call); }, #call)) return rc_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------------
 // Planning.
 // ---------------------------------------------------------------------------------------------
 
@@ -246,11 +297,47 @@ static bool all_products_applies(int64_t m, int64_t k, const double* A, int64_t 
   return 8 * 16 * lda < lim && 8 * 64 * ldb < lim && 8 * 64 * ldc < lim;
 }
 
+// Two-level ABC with staged outer sums: the outer level's two-term operand sums (five on each
+// side in the one-level table) are formed once by a streaming pass into workspace slots, and
+// each outer product then runs the one-level all-products kernel on its staged (or single-term)
+// operands.  Every sum is rounded as in the unstaged kernel, so results are bitwise the same.
+struct StagePlan {
+  int na_slots = 0, nb_slots = 0;
+  int slot_a[7], slot_b[7];
+  int64_t ta_stride = 0, tb_stride = 0, total = 0;   // doubles
+};
+
+static StagePlan make_stage_plan(const Plan& p) {
+  StagePlan sp;
+  for (int R = 0; R < 7; ++R) {
+    sp.slot_a[R] = kOneLevel[R].na == 2 ? sp.na_slots++ : -1;
+    sp.slot_b[R] = kOneLevel[R].nb == 2 ? sp.nb_slots++ : -1;
+  }
+  sp.ta_stride = round_up(4 * p.mq * p.kq, 32);
+  sp.tb_stride = round_up(4 * p.kq * p.nq, 32);
+  sp.total = sp.na_slots * sp.ta_stride + sp.nb_slots * sp.tb_stride;
+  return sp;
+}
+
+// Staging needs every outer column block of B and C full (n a multiple of 4) besides the
+// all-products layout.  Measured on MI355X it is faster than forming the outer sums in the load
+// from 2048 x 2048 outer blocks of C and k = 2048 on (1.10x at m = n = k = 4096, 1.17x at
+// 16384 with k = 8192); below that the default stays unstaged.
+static bool staging_applies(int64_t m, int64_t n, int64_t k, int levels) {
+  return levels == 2 && n % 4 == 0 && (m / 2) * (n / 2) >= int64_t(2048) * 2048 && k >= 2048;
+}
+
+static bool user_workspace_below(size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_user_ws != nullptr && g_user_ws_bytes < bytes;
+}
+
 // ABC through the all-products kernel: one launch at one level, seven (one per outer product
-// of the one-level table, in order) at two.
+// of the one-level table, in order) at two; `stage` (two levels only, may be null) holds the
+// staged outer sums.
 static int run_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
                             int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
-                            double beta, hipStream_t stream) {
+                            double beta, double* stage, hipStream_t stream) {
   FusedArgs f;
   std::memset(&f, 0, sizeof f);
   f.A = A;
@@ -273,26 +360,84 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
     f.nc = 1;
     f.c_first = 1;
     f.a_sg[0] = f.b_sg[0] = f.c_sg[0] = 1.0;
-    SMX_HIP(launch_all_products(f, 1, 1, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, 1, 1, stream));
     return 0;
   }
   // two levels: outer blocks are 2 x 2 inner sub-blocks
   const int64_t om = 2 * p.mq, on = 2 * p.nq, ok = 2 * p.kq;
+  auto a_block = [&](int q) { return (q >> 1) * om + (q & 1) * ok * lda; };
+  auto b_block = [&](int q) { return (q >> 1) * ok + (q & 1) * on * ldb; };
+  for (int R = 0; R < 7; ++R)   // the kernels take the first term's sign as +1
+    if (kOneLevel[R].a[0].sign != 1 || kOneLevel[R].b[0].sign != 1)
+      return fail(STRASSEN_ERR_UNSUPPORTED, "outer product %d: first term negative", R);
+  StagePlan sp;
+  if (stage) {
+    sp = make_stage_plan(p);
+    OuterSumArgs oa, ob;
+    std::memset(&oa, 0, sizeof oa);
+    std::memset(&ob, 0, sizeof ob);
+    oa.src = A;
+    oa.dst = stage;
+    oa.ld = lda;
+    oa.rows = om;
+    oa.cols = ok;
+    oa.dst_stride = sp.ta_stride;
+    ob.src = B;
+    ob.dst = stage + sp.na_slots * sp.ta_stride;
+    ob.ld = ldb;
+    ob.rows = ok;
+    ob.cols = on;
+    ob.dst_stride = sp.tb_stride;
+    for (int R = 0; R < 7; ++R) {
+      const QProduct& P = kOneLevel[R];
+      if (sp.slot_a[R] >= 0) {
+        oa.off0[sp.slot_a[R]] = a_block(P.a[0].q);
+        oa.off1[sp.slot_a[R]] = a_block(P.a[1].q);
+        oa.sg1[sp.slot_a[R]] = P.a[1].sign;
+      }
+      if (sp.slot_b[R] >= 0) {
+        ob.off0[sp.slot_b[R]] = b_block(P.b[0].q);
+        ob.off1[sp.slot_b[R]] = b_block(P.b[1].q);
+        ob.sg1[sp.slot_b[R]] = P.b[1].sign;
+      }
+    }
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, sp.na_slots, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, sp.nb_slots, stream));
+  }
   bool touched[4] = {false, false, false, false};
   for (int R = 0; R < 7; ++R) {
     const QProduct& P = kOneLevel[R];
-    if (P.a[0].sign != 1 || P.b[0].sign != 1)   // the kernel takes the first term's sign as +1
-      return fail(STRASSEN_ERR_UNSUPPORTED, "outer product %d: first term negative", R);
-    for (int s = 0; s < P.na; ++s) {
-      const int q = P.a[s].q;
-      f.a_off[s] = (q >> 1) * om + (q & 1) * ok * lda;
-      f.a_sg[s] = P.a[s].sign;
+    int na = P.na, nb = P.nb;
+    f.A = A;
+    f.lda = lda;
+    if (stage && sp.slot_a[R] >= 0) {   // the staged sum, an om x ok matrix
+      f.A = stage + sp.slot_a[R] * sp.ta_stride;
+      f.lda = om;
+      f.a_off[0] = 0;
+      f.a_sg[0] = 1.0;
+      na = 1;
+    } else {
+      for (int s = 0; s < P.na; ++s) {
+        f.a_off[s] = a_block(P.a[s].q);
+        f.a_sg[s] = P.a[s].sign;
+      }
     }
-    for (int s = 0; s < P.nb; ++s) {
-      const int q = P.b[s].q;
-      f.b_off[s] = (q >> 1) * ok + (q & 1) * on * ldb;
-      f.b_cb[s] = 2 * (q & 1);
-      f.b_sg[s] = P.b[s].sign;
+    f.B = B;
+    f.ldb = ldb;
+    if (stage && sp.slot_b[R] >= 0) {   // an ok x on matrix whose columns all exist (n % 4 == 0)
+      f.B = stage + sp.na_slots * sp.ta_stride + sp.slot_b[R] * sp.tb_stride;
+      f.ldb = ok;
+      f.b_off[0] = 0;
+      f.b_cb[0] = 0;
+      f.b_sg[0] = 1.0;
+      nb = 1;
+    } else {
+      for (int s = 0; s < P.nb; ++s) {
+        const int q = P.b[s].q;
+        f.b_off[s] = b_block(q);
+        f.b_cb[s] = 2 * (q & 1);
+        f.b_sg[s] = P.b[s].sign;
+      }
     }
     f.nc = P.nc;
     f.c_first = 0;
@@ -304,7 +449,7 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
       if (!touched[q]) f.c_first |= 1 << d;
       touched[q] = true;
     }
-    SMX_HIP(launch_all_products(f, P.na, P.nb, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, na, nb, stream));
   }
   return 0;
 }
@@ -376,16 +521,30 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
 
   if (p.variant == STRASSEN_ABC) {
     const int forced = g_forced_cfg.load(std::memory_order_relaxed);
-    if ((forced == -1 || forced == kCfgAll) &&
-        all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels))
-      return run_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta, stream);
+    if ((forced == -1 || forced == kCfgAll || forced == kCfgAllStaged) &&
+        all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels)) {
+      double* stage = nullptr;
+      const bool want = levels == 2 && n % 4 == 0 &&
+                        (forced == kCfgAllStaged ||
+                         (forced == -1 && staging_applies(m, n, k, levels)));
+      if (want) {
+        const size_t bytes = (size_t)make_stage_plan(p).total * sizeof(double);
+        // a caller workspace too small for the staging buffers: form the sums in the load
+        if (forced == kCfgAllStaged || !user_workspace_below(bytes)) {
+          void* ws = nullptr;
+          if (int rc = get_workspace(dev, bytes, &ws)) return rc;
+          stage = static_cast<double*>(ws);
+        }
+      }
+      return run_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta, stage, stream);
+    }
     const int cfg = pick_cfg(p, 1, maxt);
     g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
     g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
     const int64_t grid = (int64_t)g.tiles_m * g.tiles_n;
     if (grid >= tiles_limit) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
     g.mode = kModeABC;
-    SMX_HIP(launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_TILE, stream, launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
     return 0;
   }
 
@@ -444,7 +603,7 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
   g.prod_begin = 0;
   const int64_t grid = (int64_t)g.tiles_m * g.tiles_n * p.td->nprod;
   if (grid >= tiles_limit) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
-  SMX_HIP(launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+  SMX_LAUNCH(STRASSEN_KERNEL_TILE, stream, launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
 
   AssembleArgs asmb;
   std::memset(&asmb, 0, sizeof asmb);
@@ -611,6 +770,8 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   }
   const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
   *bytes = (size_t)p.total * sizeof(double);
+  if (variant == STRASSEN_ABC && smx::staging_applies(m, n, k, levels))
+    *bytes = (size_t)smx::make_stage_plan(p).total * sizeof(double);
   return 0;
 }
 
@@ -663,6 +824,43 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
   }
   *bytes = smx::make_low_plan(m, n, k, levels, compute).bytes;
   return 0;
+}
+
+int strassen_timing_enable(int on) {
+  smx::g_last_error.clear();
+  smx::g_timing.store(on != 0);
+  return 0;
+}
+
+int strassen_timing_collect(int kind, double* ms_total, int* launches) {
+  smx::g_last_error.clear();
+  if (!ms_total || !launches) return smx::fail(-2, "NULL output");
+  std::vector<smx::TimedLaunch> mine;
+  {
+    std::lock_guard<std::mutex> lk(smx::g_tm_mu);
+    std::vector<smx::TimedLaunch> rest;
+    for (const auto& t : smx::g_tm_log) (t.kind == kind ? mine : rest).push_back(t);
+    smx::g_tm_log.swap(rest);
+  }
+  double total = 0.0;
+  int rc = 0;
+  for (const auto& t : mine) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t.e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.e0, t.e1);
+    if (e != hipSuccess && rc == 0) rc = smx::hip_fail(e, "timing events");
+    total += ms;
+  }
+  {
+    std::lock_guard<std::mutex> lk(smx::g_tm_mu);
+    for (const auto& t : mine) {
+      smx::g_tm_pool.push_back(t.e0);
+      smx::g_tm_pool.push_back(t.e1);
+    }
+  }
+  *ms_total = total;
+  *launches = (int)mine.size();
+  return rc;
 }
 
 int strassen_set_tile_config(int cfg) {

@@ -117,6 +117,40 @@ __global__ __launch_bounds__(256) void sum_kernel(const SumArgs args) {
   args.dst[(int64_t)slot * args.dst_stride + i + j * args.rows_q] = v;
 }
 
+// Staged outer sums: a workgroup covers kOuterSumRows rows of kOuterSumCols consecutive columns
+// of one slot, each lane a row pair (16-byte loads and stores), all loads of a lane issued
+// before its first store.  x0 + s1 x1 is rounded once (the pair rule of signed_sum with a first
+// sign of +1, as the all-products kernel forms the same sum).
+constexpr int kOuterSumRows = 512, kOuterSumCols = 4;
+
+__global__ __launch_bounds__(256) void outer_sum_kernel(const OuterSumArgs args) {
+  const int slot = blockIdx.y;
+  const int64_t i = (int64_t)(blockIdx.x % args.chunks_r) * kOuterSumRows + 2 * threadIdx.x;
+  const int64_t j0 = (int64_t)(blockIdx.x / args.chunks_r) * kOuterSumCols;
+  if (i >= args.rows) return;
+  const double* x0 = args.src + args.off0[slot] + i;
+  const double* x1 = args.src + args.off1[slot] + i;
+  double* d = args.dst + slot * args.dst_stride + i;
+  const double s1 = args.sg1[slot];
+  d2_t a[kOuterSumCols], b[kOuterSumCols];
+#pragma unroll
+  for (int c = 0; c < kOuterSumCols; ++c) {
+    if (j0 + c < args.cols) {
+      a[c] = *reinterpret_cast<const d2_t*>(x0 + (j0 + c) * args.ld);
+      b[c] = *reinterpret_cast<const d2_t*>(x1 + (j0 + c) * args.ld);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kOuterSumCols; ++c) {
+    if (j0 + c < args.cols) {
+      d2_t v;
+      v.x = __builtin_fma(s1, b[c].x, a[c].x);
+      v.y = __builtin_fma(s1, b[c].y, a[c].y);
+      *reinterpret_cast<d2_t*>(d + (j0 + c) * args.rows) = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void scale_kernel(const ScaleArgs args, int chunks_m) {
   const int64_t j = blockIdx.x / chunks_m;
   const int64_t i = (int64_t)(blockIdx.x % chunks_m) * 256 + threadIdx.x;
@@ -173,6 +207,15 @@ hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s) {
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s) {
   const int64_t gx = (int64_t)a.chunks_r * a.cols_q;
   hipLaunchKernelGGL(sum_kernel, dim3((unsigned)gx, nslots), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_sums(const OuterSumArgs& a, int nslots, hipStream_t s) {
+  OuterSumArgs b = a;
+  b.chunks_r = (int32_t)((a.rows + kOuterSumRows - 1) / kOuterSumRows);
+  const int64_t gx = (int64_t)b.chunks_r * ((a.cols + kOuterSumCols - 1) / kOuterSumCols);
+  if (nslots < 1 || nslots > kMaxOuterSlots || gx >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(outer_sum_kernel, dim3((unsigned)gx, nslots), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 

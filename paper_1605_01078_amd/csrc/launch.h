@@ -13,7 +13,8 @@ enum TileCfg : int {
   kCfg128k8 = 2,   // 128 x 128, BK 8, two workgroups per CU
   kCfg128w1 = 3,   // 128 x 128, BK 16, one workgroup per CU (512 registers per lane)
   kCfgAll = 4,     // ABC with levels >= 1: the all-products kernel (where its layout applies)
-  kNumCfgs = 5
+  kCfgAllStaged = 5,   // as 4; at two levels the outer operand sums are staged in a workspace
+  kNumCfgs = 6
 };
 inline int cfg_bm(int cfg) { return cfg == kCfg64 ? 64 : 128; }
 inline int cfg_bn(int cfg) { return cfg == kCfg64 ? 64 : 128; }
@@ -49,6 +50,7 @@ hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v,
                            float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
+hipError_t launch_outer_sums(const OuterSumArgs& a, int nslots, hipStream_t s);
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 
 }  // namespace smx

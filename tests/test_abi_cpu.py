@@ -89,7 +89,8 @@ def test_workspace_sizes(m, n, k):
     for levels in (1, 2):
         q = 2 ** levels
         mq, nq, kq = _cdiv(m, q), _cdiv(n, q), _cdiv(k, q)
-        assert sx.workspace_size(m, n, k, levels, "abc") == 0
+        if levels == 1 or m < 4096:   # two-level staging: test_two_level_abc_staging_workspace
+            assert sx.workspace_size(m, n, k, levels, "abc") == 0
         ab = sx.workspace_size(m, n, k, levels, "ab")
         nprod = 7 ** levels
         # one M_r per product, leading dimension rounded to 8 doubles, slot to 32
@@ -101,6 +102,19 @@ def test_workspace_sizes(m, n, k):
         nb = sum(1 for _, b, _ in tab if len(b) > 1 or b[0][1] < 0)
         assert (na, nb) == ((5, 5) if levels == 1 else (45, 45))
         assert nv == ab + 8 * (na * _cdiv(mq * kq, 32) * 32 + nb * _cdiv(kq * nq, 32) * 32)
+
+
+def test_two_level_abc_staging_workspace():
+    """Two-level ABC reports the staging buffers of its outer operand sums (five A sums of
+    m/2 x k/2 and five B sums of k/2 x n/2, slots rounded to 32 doubles) where staging applies:
+    n a multiple of 4, outer C blocks of at least 2048 x 2048 and k >= 2048."""
+    r32 = lambda x: _cdiv(x, 32) * 32
+    for m, n, k in [(16384, 16384, 16384), (4096, 4096, 4096), (8192, 12288, 2048)]:
+        want = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
+        assert sx.workspace_size(m, n, k, 2, "abc") == want
+        assert sx.workspace_size(m, n, k, 1, "abc") == 0
+    for m, n, k in [(8192, 8190, 8192), (2048, 4096, 4096), (8192, 8192, 1024)]:
+        assert sx.workspace_size(m, n, k, 2, "abc") == 0
 
 
 def test_workspace_size_errors():

@@ -235,3 +235,97 @@ def test_all_products_kernel(shape, levels):
         assert np.array_equal(out, run(Ar, Br, Cn, 1.0, 0.0, levels, "naive"))
     finally:
         sx.set_tile_config(-1)
+
+
+STAGED_SHAPES = [(512, 512, 512), (1032, 1028, 1048), (2048, 2056, 1024)]
+
+
+@pytest.mark.parametrize("shape", STAGED_SHAPES)
+def test_two_level_staged_outer_sums(shape):
+    """Two-level ABC with the outer operand sums staged (tile configuration 5): exact on
+    integers, within the Strassen tolerance on reals, bitwise equal to the unstaged all-products
+    path and to Naive, and C write-only when beta = 0."""
+    m, n, k = shape
+    print(f"case staged {shape}", flush=True)
+    A, B, C = W.problem(31, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    Ar, Br, Cr = W.problem(32, m, n, k, "uniform")
+    refr = oracle_dgemm(Ar, Br, Cr.copy(order="F"), 0.75, -1.5)
+    try:
+        sx.set_tile_config(4)
+        unstaged = run(Ar, Br, Cr, 0.75, -1.5, 2, "abc")
+        sx.set_tile_config(5)
+        assert np.array_equal(run(A, B, C, 1.0, 1.0, 2, "abc"), ref)
+        staged = run(Ar, Br, Cr, 0.75, -1.5, 2, "abc")
+        assert rel_fro(staged, refr) <= TOL[2]
+        assert np.array_equal(staged, unstaged)
+        assert np.array_equal(staged, run(Ar, Br, Cr, 0.75, -1.5, 2, "naive"))
+        Cn = np.full_like(Cr, np.nan)
+        out = run(Ar, Br, Cn, 1.0, 0.0, 2, "abc")
+        assert np.isfinite(out).all()
+        sx.set_tile_config(4)
+        assert np.array_equal(out, run(Ar, Br, Cn, 1.0, 0.0, 2, "abc"))
+    finally:
+        sx.set_tile_config(-1)
+
+
+def test_two_level_staging_default_and_small_caller_workspace():
+    """At 8192 the default two-level ABC stages the outer sums (workspace reported), bitwise
+    as the unstaged path; a caller workspace too small for the staging buffers makes it form the
+    sums in the load instead (same bits, no error)."""
+    import torch
+    n = 8192
+    print("case staging default 8192", flush=True)
+    need = sx.workspace_size(n, n, n, 2, "abc")
+    assert need >= 10 * (n // 2) ** 2 * 8
+    A = W.device_uniform(41, n, n)
+    B = W.device_uniform(42, n, n)
+    C0 = W.device_uniform(43, n, n)
+    outs = {}
+    try:
+        for name, cfg, ws in (("default", -1, None), ("unstaged", 4, None),
+                              ("small_ws", -1, torch.empty(1 << 20, dtype=torch.float64,
+                                                           device="cuda"))):
+            sx.set_tile_config(cfg)
+            sx.set_workspace(ws)
+            C = C0.clone()
+            sx.dgemm(A, B, C, 1.0, 1.0, 2, "abc")
+            torch.cuda.synchronize()
+            outs[name] = C
+            sx.set_workspace(None)
+    finally:
+        sx.set_workspace(None)
+        sx.set_tile_config(-1)
+    assert torch.equal(outs["default"], outs["unstaged"])
+    assert torch.equal(outs["small_ws"], outs["unstaged"])
+    # spot check against the oracle on a few columns
+    cols = [0, 4097, 8191]
+    Ah = np.asfortranarray(A.cpu().numpy())
+    Bc = np.asfortranarray(B[:, cols].cpu().numpy())
+    ref = oracle_dgemm(Ah, Bc, np.asfortranarray(C0[:, cols].cpu().numpy()), 1.0, 1.0)
+    assert rel_fro(outs["default"][:, cols].cpu().numpy(), ref) <= TOL[2]
+
+
+def test_kernel_timing_hooks():
+    """The library's event pairs: one all-products launch at one level, seven plus two staged
+    outer-sum passes at two levels (m = n = k = 4096), one tile-kernel launch for classical."""
+    import torch
+    n = 4096
+    print("case timing hooks", flush=True)
+    A, B, C = (W.device_uniform(s, n, n) for s in (51, 52, 53))
+    for kind in sx.KERNEL_KINDS:
+        sx.timing_collect(kind)
+    sx.timing_enable(True)
+    try:
+        sx.dgemm(A, B, C, 1.0, 1.0, 1, "abc")
+        sx.dgemm(A, B, C, 1.0, 1.0, 2, "abc")
+        sx.dgemm(A, B, C, 1.0, 1.0, 0, "abc")
+        torch.cuda.synchronize()
+    finally:
+        sx.timing_enable(False)
+    ms_ap, n_ap = sx.timing_collect("all_products")
+    ms_os, n_os = sx.timing_collect("outer_sums")
+    ms_t, n_t = sx.timing_collect("tile")
+    assert (n_ap, n_os, n_t) == (8, 2, 1)
+    assert ms_ap > 0 and ms_os > 0 and ms_t > 0
+    assert sx.timing_collect("all_products") == (0.0, 0)
