@@ -60,7 +60,11 @@ __device__ __forceinline__ d2_t fma2(double s, d2_t x, d2_t y) {
   return (d2_t){__builtin_fma(s, x.x, y.x), __builtin_fma(s, x.y, y.y)};
 }
 
-template <int NA, int NB, int BK, int NS>
+// FULL: every tile is whole (sub-block extents multiples of the tile, every B column present),
+// so the loads need no per-lane range masks; the registers this frees keep the main loop free of
+// spill reloads, whose wait on the vector-memory counter would also wait for the tile loads just
+// issued and stall the pipeline.
+template <int NA, int NB, int BK, int NS, bool FULL>
 struct AllProducts {
   static constexpr int T = 64;                    // tile edge inside one inner sub-block
   static constexpr int NT = 512;
@@ -120,6 +124,7 @@ struct AllProducts {
         b_cols |= (uint32_t)(b_col_in & ((args.b_cb[s] + (q & 1)) * nq + j0 + b_j < args.n))
                   << (4 * s + q);
 
+    const int nk = (int)((kq + BK - 1) / BK);
     auto issue_loads = [&](int stage, int kt) {
       const int64_t kb = (int64_t)kt * BK;
       double* sbase = lds + stage * STAGE_D;
@@ -131,11 +136,13 @@ struct AllProducts {
         const int t = u / IPT;
         double* dst = sbase + t * TILE_D + v * 128;
         if (8 * j < 4 * NA * IPT) {           // an A tile (compile-time split, see static_assert)
-          dma16(make_rsrc(a_tile(t >> 2, t & 3) + kb * lda), dst, a_ok ? a_off : kOOB);
+          dma16(make_rsrc(a_tile(t >> 2, t & 3) + kb * lda), dst,
+                FULL ? (kt < nk ? a_off : kOOB) : (a_ok ? a_off : kOOB));
         } else {
           const int tb = t - 4 * NA;
           const bool ok = ((b_cols >> tb) & 1u) & b_k_ok;
-          dma16(make_rsrc(b_tile(tb >> 2, tb & 3) + kb), dst, ok ? b_off : kOOB);
+          dma16(make_rsrc(b_tile(tb >> 2, tb & 3) + kb), dst,
+                FULL ? (kt < nk ? b_off : kOOB) : (ok ? b_off : kOOB));
         }
       }
     };
@@ -225,7 +232,6 @@ struct AllProducts {
     // the current group run (they do not depend on those reads); the instruction order is
     // pinned so the reads alternate with the first MFMAs.  Loads past the last step are out of
     // range (zeros, no memory access) and land in a stage nobody reads.
-    const int nk = (int)((kq + BK - 1) / BK);
     constexpr int kReads = 8 * NA + 4 * NB;   // 16-byte LDS reads per wave and group
     auto interleave = [&]() {
 #pragma unroll
@@ -335,9 +341,9 @@ struct AllProducts {
   }
 };
 
-template <int NA, int NB, int BK, int NS>
+template <int NA, int NB, int BK, int NS, bool FULL>
 __global__ __launch_bounds__(512, 1) void all_products_kernel(const FusedArgs args) {
-  using K = AllProducts<NA, NB, BK, NS>;
+  using K = AllProducts<NA, NB, BK, NS, FULL>;
   __shared__ __attribute__((aligned(16))) double lds[K::LDS_D];
   K::run(args, lds);
 }
@@ -346,14 +352,22 @@ __global__ __launch_bounds__(512, 1) void all_products_kernel(const FusedArgs ar
 
 hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(512);
-  if (na == 1 && nb == 1)
-    hipLaunchKernelGGL((all_products_kernel<1, 1, 16, 2>), grid, block, 0, s, a);
+  // whole tiles: sub-block extents multiples of 64 (m, n) and of the k step, and the B columns
+  // of the highest column block used present
+  int64_t cb_max = 0;
+  for (int t = 0; t < nb; ++t) cb_max = cb_max > a.b_cb[t] ? cb_max : a.b_cb[t];
+  const bool full = a.mq % 64 == 0 && a.nq % 64 == 0 && a.kq % 16 == 0 && (cb_max + 2) * a.nq <= a.n;
+  if (na == 1 && nb == 1 && full)
+    hipLaunchKernelGGL((all_products_kernel<1, 1, 16, 2, true>), grid, block, 0, s, a);
+  else if (na == 1 && nb == 1)
+    hipLaunchKernelGGL((all_products_kernel<1, 1, 16, 2, false>), grid, block, 0, s, a);
+  // (the whole-tile form of the two-level kernels measured slower: they keep the masked loads)
   else if (na == 2 && nb == 2)
-    hipLaunchKernelGGL((all_products_kernel<2, 2, 8, 2>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((all_products_kernel<2, 2, 8, 2, false>), grid, block, 0, s, a);
   else if (na == 2 && nb == 1)
-    hipLaunchKernelGGL((all_products_kernel<2, 1, 8, 3>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((all_products_kernel<2, 1, 8, 3, false>), grid, block, 0, s, a);
   else if (na == 1 && nb == 2)
-    hipLaunchKernelGGL((all_products_kernel<1, 2, 8, 3>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((all_products_kernel<1, 2, 8, 3, false>), grid, block, 0, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
