@@ -271,7 +271,9 @@ int strassen_set_tile_config(int cfg);
 enum strassen_kernel_kind {
     STRASSEN_KERNEL_ALL_PRODUCTS = 0,  /* the fused ABC kernel (one level; each two-level outer product) */
     STRASSEN_KERNEL_OUTER_SUMS = 1,    /* the staged outer-sum pass of two-level ABC            */
-    STRASSEN_KERNEL_TILE = 2           /* the general FP64 tile kernel (classical, AB, Naive, ABC fallback) */
+    STRASSEN_KERNEL_TILE = 2,          /* the general FP64 tile kernel (classical, AB, Naive, ABC fallback) */
+    STRASSEN_KERNEL_BF16 = 3,          /* the reduced-precision product kernel (strassen_gemm_ex) */
+    STRASSEN_KERNEL_CAST = 4           /* its operand pass (sums rounded to bf16 hi / lo)       */
 };
 int strassen_timing_enable(int on);
 int strassen_timing_collect(int kind, double *ms_total, int *launches);

@@ -247,7 +247,7 @@ def set_tile_config(cfg):
     check(lib().strassen_set_tile_config(int(cfg)))
 
 
-KERNEL_KINDS = {"all_products": 0, "outer_sums": 1, "tile": 2}
+KERNEL_KINDS = {"all_products": 0, "outer_sums": 1, "tile": 2, "bf16": 3, "cast": 4}
 
 
 def timing_enable(on=True):
@@ -256,8 +256,8 @@ def timing_enable(on=True):
 
 
 def timing_collect(kind):
-    """(total milliseconds, launches) of the recorded launches of one kernel kind ("all_products",
-    "outer_sums", "tile"), which are then forgotten; waits for them."""
+    """(total milliseconds, launches) of the recorded launches of one kernel kind (a key of
+    KERNEL_KINDS), which are then forgotten; waits for them."""
     ms, cnt = ctypes.c_double(), ctypes.c_int()
     check(lib().strassen_timing_collect(KERNEL_KINDS[kind], ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value

@@ -700,7 +700,7 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   ca.tab = tab;
   ca.side = 0;
   ca.sum_f64 = sum_prec == STRASSEN_PREC_F64;
-  SMX_HIP(launch_cast(ca, (int)p.nslots, stream));
+  SMX_LAUNCH(STRASSEN_KERNEL_CAST, stream, launch_cast(ca, (int)p.nslots, stream));
   CastArgs cb = ca;
   cb.src = B;
   cb.hi = TBh;
@@ -713,7 +713,7 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   cb.outer_pad = p.np;
   cb.slot_stride = p.slot_b;
   cb.side = 1;
-  SMX_HIP(launch_cast(cb, (int)p.nslots, stream));
+  SMX_LAUNCH(STRASSEN_KERNEL_CAST, stream, launch_cast(cb, (int)p.nslots, stream));
 
   Bf16Args g;
   std::memset(&g, 0, sizeof g);
@@ -737,7 +737,7 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   g.tiles_n = (int32_t)(p.np / 128);
   g.x3 = p.x3;
   g.c_f64 = c_prec == STRASSEN_PREC_F64;
-  SMX_HIP(launch_bf16_gemm(g, stream));
+  SMX_LAUNCH(STRASSEN_KERNEL_BF16, stream, launch_bf16_gemm(g, stream));
   return 0;
 }
 

@@ -14,9 +14,9 @@
 //   bf16_gemm_kernel  owns one 128 x 128 tile position in every C sub-block and runs every
 //                   product on it in table order (ABC epilogue: each product is added to each of
 //                   its destination C sub-blocks, beta at the first update).  BF16 operands go
-//                   HBM -> LDS by direct-to-LDS buffer loads, four stages deep, streamed across
-//                   the product boundary; bf16x3 runs hi*hi + hi*lo + lo*hi into the same FP32
-//                   accumulator.
+//                   HBM -> LDS by direct-to-LDS buffer loads in two stages (k step 64, 32 for
+//                   bf16x3), streamed across the product boundary, two workgroups per CU; bf16x3
+//                   runs hi*hi + hi*lo + lo*hi into the same FP32 accumulator.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -167,17 +167,23 @@ __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args) {
 // ---------------------------------------------------------------------------------------------
 // BF16 product kernel.
 // ---------------------------------------------------------------------------------------------
-template <bool X3>
+// Tiles: BM x BN = 128 x 128, 4 waves of 64 x 64 (4 x 4 blocks of 16 x 16 MFMA), k step BK
+// (bf16 elements).  Stage s holds the tiles of stream position s: A hi, B hi (, A lo, B lo),
+// each BM rows of BK values, 16-byte chunks XOR-swizzled by row pair.
+template <bool X3, int BK, int NS>
 struct Bf16Gemm {
-  static constexpr int BM = 128, BN = 128, BK = 64;   // BK in bf16 elements (128 bytes a row)
-  static constexpr int NS = X3 ? 2 : 4;               // LDS stages
-  static constexpr int TILE_B = BM * BK * 2;          // bytes of one 128 x 64 bf16 tile (16 KB)
-  static constexpr int NTL = X3 ? 4 : 2;              // tiles per stage: A hi, B hi (, A lo, B lo)
+  static constexpr int BM = 128, BN = 128;
+  static constexpr int CPR = BK / 8;                  // 16-byte chunks per tile row
+  static constexpr int TILE_B = BM * BK * 2;          // bytes of one tile
+  static constexpr int NTL = X3 ? 4 : 2;              // tiles per stage
   static constexpr int STAGE_B = NTL * TILE_B;
-  static constexpr int IPT = TILE_B / 1024;           // 64-lane x 16-byte loads per tile (16)
-  static constexpr int IPW = NTL * IPT / 4;           // per wave and step (4 waves)
+  static constexpr int IPT = TILE_B / 1024;           // 64-lane x 16-byte loads per tile
+  static constexpr int LPW = IPT / 4;                 // loads per tile and wave
+  static constexpr int IPW = NTL * LPW;               // loads per wave and step
+  static constexpr int KK = BK / 32;                  // MFMA k sub-steps per step
   static constexpr int LDS_B = NS * STAGE_B;
   static_assert(LDS_B <= 160 * 1024, "LDS");
+  static_assert(BK == 32 || BK == 64, "k step");
 
   __device__ static void run(const Bf16Args& args, char* lds) {
     const TableDev& tab = g_tables_bf16[args.tab];
@@ -190,40 +196,53 @@ struct Bf16Gemm {
     const int64_t row0 = (int64_t)ti * BM, col0 = (int64_t)tj * BN;
     const int nk = (int)(args.kpad / BK);
     const int nprod = tab.nprod;
-    const int total = nprod * nk;
 
-    // Loads: tile position p = 64 u + lane of a 128 x 8-chunk tile: row p / 8, stored chunk p % 8
-    // holds logical k-chunk (p % 8) ^ ((row / 2) % 8).  The swizzle keeps the sixteen lanes of a
-    // fragment read (16 rows, one chunk) on distinct banks.
-    auto issue = [&](int s, int stage) {
-      const bool live = s < total;
-      const int r = live ? s / nk : 0, kt = live ? s - r * nk : 0;
+    // Lane byte offsets inside a product slot for load jj of a tile (part wave + 4 jj):
+    // position p = 64 part + lane is row p / CPR, stored chunk p % CPR = logical chunk ^ swizzle.
+    uint32_t off_a[LPW], off_b[LPW];
+#pragma unroll
+    for (int jj = 0; jj < LPW; ++jj) {
+      const int p = (wave + 4 * jj) * 64 + lane;
+      const int row = p / CPR, pc = p % CPR, c = pc ^ ((row >> 1) & (CPR - 1));
+      off_a[jj] = (uint32_t)(2 * ((row0 + row) * args.kpad + c * 8));
+      off_b[jj] = (uint32_t)(2 * ((col0 + row) * args.kpad + c * 8));
+    }
+    // the load stream: product ri, k step ki, and the slot bases of product ri (uniform)
+    int ri = 0, ki = 0;
+    const uint16_t* base[NTL];
+    auto set_bases = [&](int r) {
+      base[0] = args.TAh + (int64_t)r * args.stride_a;
+      base[1] = args.TBh + (int64_t)r * args.stride_b;
+      if (X3) {
+        base[NTL > 2 ? 2 : 0] = args.TAl + (int64_t)r * args.stride_a;
+        base[NTL > 2 ? 3 : 1] = args.TBl + (int64_t)r * args.stride_b;
+      }
+    };
+    set_bases(0);
+    auto issue = [&](int stage) {
+      const bool live = ri < nprod;
+      const uint32_t kofs = (uint32_t)(2 * BK * ki);
       char* sb = lds + stage * STAGE_B;
 #pragma unroll
       for (int j = 0; j < IPW; ++j) {
-        const int u = wave + 4 * j;            // load index over the stage
-        const int tl = u / IPT, part = u % IPT;
-        const int p = part * 64 + lane;
-        const int row = p >> 3, pc = p & 7, c = pc ^ ((row >> 1) & 7);
-        const bool is_a = (tl & 1) == 0, is_lo = tl >= 2;
-        // the buffer starts at product r's slot (uniform); offsets inside one slot are below
-        // 2^31 (host-checked); steps past the last one load nothing
-        const uint16_t* base = (is_a ? (is_lo ? args.TAl : args.TAh) : (is_lo ? args.TBl : args.TBh)) +
-                               (int64_t)r * (is_a ? args.stride_a : args.stride_b);
-        const int64_t rc0 = is_a ? row0 : col0;
-        const int64_t off = 2 * ((rc0 + row) * args.kpad + (int64_t)kt * BK + c * 8);
+        const int tl = j / LPW, jj = j % LPW;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<uint16_t*>(base), (short)0, 0x7fffffff, 0x00020000);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(sb + tl * TILE_B + part * 1024),
-                                                 16, live ? (uint32_t)off : kOOB, 0, 0, 0);
+            const_cast<uint16_t*>(base[tl]), (short)0, 0x7fffffff, 0x00020000);
+        const uint32_t o = ((tl & 1) == 0 ? off_a[jj] : off_b[jj]) + kofs;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(sb + tl * TILE_B + (wave + 4 * jj) * 1024),
+                                                 16, live ? o : kOOB, 0, 0, 0);
+      }
+      if (++ki == nk) {
+        ki = 0;
+        if (++ri < nprod) set_bases(ri);
       }
     };
 
-    // fragment reads: rows (A) / columns (B) 16 f + lane % 16 of the wave's 64, k-chunk 4 kk + g
+    // fragment reads: rows (A) / columns (B) 16 f + lane % 16 of the wave's 64, chunk 4 kk + g
     const int g = lane >> 4, li = lane & 15;
     auto frag = [&](const char* tile, int rr, int chunk) {
-      const int pc = chunk ^ ((rr >> 1) & 7);
-      return *reinterpret_cast<const bf8_t*>(tile + rr * 128 + pc * 16);
+      const int pc = chunk ^ ((rr >> 1) & (CPR - 1));
+      return *reinterpret_cast<const bf8_t*>(tile + rr * (2 * BK) + pc * 16);
     };
 
     f4_t acc[4][4];
@@ -235,29 +254,30 @@ struct Bf16Gemm {
     };
     auto compute = [&](int stage) {
       const char* sb = lds + stage * STAGE_B;
+      bf8_t ah[KK][4], bh[KK][4], al[KK][4], bl[KK][4];
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        bf8_t ah[4], bh[4], al[4], bl[4];
+      for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          ah[f] = frag(sb, wm * 64 + 16 * f + li, 4 * kk + g);
-          bh[f] = frag(sb + TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
+          ah[kk][f] = frag(sb, wm * 64 + 16 * f + li, 4 * kk + g);
+          bh[kk][f] = frag(sb + TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
           if (X3) {
-            al[f] = frag(sb + 2 * TILE_B, wm * 64 + 16 * f + li, 4 * kk + g);
-            bl[f] = frag(sb + 3 * TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
+            al[kk][f] = frag(sb + 2 * TILE_B, wm * 64 + 16 * f + li, 4 * kk + g);
+            bl[kk][f] = frag(sb + 3 * TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
           }
         }
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
         for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
           for (int fn = 0; fn < 4; ++fn) {
-            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fm], bh[fn], acc[fm][fn], 0, 0, 0);
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kk][fm], bh[kk][fn], acc[fm][fn], 0, 0, 0);
             if (X3) {
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fm], bl[fn], acc[fm][fn], 0, 0, 0);
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[fm], bh[fn], acc[fm][fn], 0, 0, 0);
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kk][fm], bl[kk][fn], acc[fm][fn], 0, 0, 0);
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[kk][fm], bh[kk][fn], acc[fm][fn], 0, 0, 0);
             }
           }
-      }
     };
 
     // Epilogue of product r: lane l, element e of block (fm, fn) is tile row
@@ -276,7 +296,7 @@ struct Bf16Gemm {
         const __amdgpu_buffer_rsrc_t rs =
             make_rsrc(args.C + (ci * args.mq + row0) + (cj * args.nq + col0) * ldc);
 #pragma unroll
-        for (int fm = 0; fm < 4; ++fm)
+        for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
           for (int fn = 0; fn < 4; ++fn) {
             const int cl = wn * 64 + 16 * fn + li;
@@ -301,35 +321,35 @@ struct Bf16Gemm {
               __builtin_amdgcn_raw_buffer_store_b64(as_u2(out), rs, ok ? off : kOOB, 0, 0);
             }
           }
+          __builtin_amdgcn_sched_barrier(0);   // keep the C traffic of one row block together
+        }
       }
     };
 
-    // Step s = (product s / nk, k step s % nk) lives in stage s % NS.  Iteration s: with step s
-    // landed (the NS - 2 newest batches may still fly) the barrier publishes it and has every
-    // read of step s - 1 done, so the loads of step s + NS - 1 go into that step's stage.
+    // Stream position s lives in stage s % NS.  At each step: with the step landed (the NS - 2
+    // newest batches may still fly) the barrier publishes it and has every read of the previous
+    // step done, so the next position's loads go into that step's stage.
 #pragma unroll
-    for (int s = 0; s < NS - 1; ++s) issue(s, s);
-    zero();
+    for (int s = 0; s < NS - 1; ++s) issue(s);
     int stage = 0;
-    for (int s = 0; s < total; ++s) {
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IPW * (NS - 2)) : "memory");
-      __syncthreads();
-      issue(s + NS - 1, stage == 0 ? NS - 1 : stage - 1);
-      compute(stage);
-      stage = stage + 1 == NS ? 0 : stage + 1;
-      const int r = s / nk;
-      if (s - r * nk == nk - 1) {
-        epilogue(r);
-        zero();
+    for (int r = 0; r < nprod; ++r) {
+      zero();
+      for (int kt = 0; kt < nk; ++kt) {
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IPW * (NS - 2)) : "memory");
+        __syncthreads();
+        issue(stage == 0 ? NS - 1 : stage - 1);
+        compute(stage);
+        stage = stage + 1 == NS ? 0 : stage + 1;
       }
+      epilogue(r);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
 };
 
-template <bool X3>
-__global__ __launch_bounds__(256, 1) void bf16_gemm_kernel(const Bf16Args args) {
-  using K = Bf16Gemm<X3>;
+template <bool X3, int BK, int NS, int WPC>
+__global__ __launch_bounds__(256, WPC) void bf16_gemm_kernel(const Bf16Args args) {
+  using K = Bf16Gemm<X3, BK, NS>;
   __shared__ __attribute__((aligned(16))) char lds[K::LDS_B];
   K::run(args, lds);
 }
@@ -345,8 +365,9 @@ hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
 
 hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(256);
-  if (a.x3) hipLaunchKernelGGL(bf16_gemm_kernel<true>, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(bf16_gemm_kernel<false>, grid, block, 0, s, a);
+  // two workgroups per CU (64 KB of LDS each): one hides the other's LDS latency and barriers
+  if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
