@@ -70,44 +70,80 @@ static double launch_seconds(double items, double fi, double slots, double rate)
   return std::ceil(items / slots) * fi / share;
 }
 
+// The kernel each member runs for these sizes follows the library's own dispatch: ABC uses the
+// all-products kernel where m and k are multiples of 2^(L+1) (whole tiles or masked), at two
+// levels with the staged outer sums where they apply, else the general tile kernel.  Rates and
+// efficiencies were fitted to this library's timings of the selector's 20000 training shapes
+// (coordinate search on the regret of the model's choice, efficiencies capped at 1, keeping the
+// measured order at m = n = k = 16384: two-level ABC, one-level ABC, classical).
+namespace {
+struct ModelCoef {
+  double R = 66.0e12;        // classical FP64 MFMA rate of the tile kernel
+  double e_full = 0.99;      // all-products kernel, whole tiles (relative to R)
+  double e_masked = 0.966;   // all-products kernel, masked loads
+  double e_unstaged = 0.80;  // two levels, outer sums in the load
+  double e_tile1 = 0.60, e_tile2 = 0.50;   // ABC on the general tile kernel
+  double e_ab1 = 0.918, e_ab2 = 0.562, e_naive1 = 0.997, e_naive2 = 0.483;
+  double bw = 7.81e12;       // HBM bytes/s of the element-wise passes (fitted)
+  double t_launch = 20.0e-6; // per launch (latency and tail)
+  double R_bf16 = 900.0e12;  // BF16 product kernel
+  double bw_cast = 4.0e12;   // its operand pass
+};
+const ModelCoef kCoef;
+}  // namespace
+
 double model_seconds(int64_t m, int64_t n, int64_t k, int dtype, int c) {
   if (!member_available(dtype, c)) return std::numeric_limits<double>::infinity();
+  const ModelCoef& K = kCoef;
   const int L = kMemberLevels[c], var = kMemberVariant[c];
   const int64_t q = int64_t(1) << L;
-  const double mq = (double)cdiv(m, q), nq = (double)cdiv(n, q), kq = (double)cdiv(k, q);
+  const int64_t mqi = cdiv(m, q), nqi = cdiv(n, q), kqi = cdiv(k, q);
+  const double mq = (double)mqi, nq = (double)nqi, kq = (double)kqi;
   const double p7 = L == 0 ? 1.0 : (L == 1 ? 7.0 : 49.0);
   // operand terms and C updates of the tables (Sec. 3.1, Sec. 3.5): 12^L each
   const double terms = L == 0 ? 1.0 : (L == 1 ? 12.0 : 144.0);
-  const double bw = 5.0e12;    // sustained HBM bytes/s
-  const double t_launch = 8.0e-6;
   auto tiles = [](double a, double b, double t) { return std::ceil(a / t) * std::ceil(b / t); };
+  auto ap_launch = [&](double e) {   // one all-products launch: 7 products per 64 x 64 item
+    return launch_seconds(tiles(mq, nq, 64.0), 7.0 * 2.0 * 64 * 64 * kq, 256.0, K.R * e) + K.t_launch;
+  };
+  const bool whole = mqi % 64 == 0 && nqi % 64 == 0 && kqi % 16 == 0 && q * nqi <= n;
   double t = 0.0;
   if (dtype == 0) {
-    const double R = 66.0e12;   // this library's classical FP64 MFMA rate
     if (L == 0) {
-      t = launch_seconds(tiles(mq, nq, 128.0), 2.0 * 128 * 128 * kq, 512.0, R) + t_launch;
-    } else if (var == STRASSEN_ABC) {
-      // all-products kernel: 7 products per 64 x 64 item, 7^(L-1) launches
-      const double e = L == 1 ? 0.96 : 0.78;
-      const double launches = L == 1 ? 1.0 : 7.0;
-      t = launches * (launch_seconds(tiles(mq, nq, 64.0), 7.0 * 2.0 * 64 * 64 * kq, 256.0, R * e) +
-                      t_launch);
-    } else {
-      // calibrated on m = n = k = 16384 (products kernel efficiency relative to classical)
-      const double e = var == STRASSEN_AB ? (L == 1 ? 0.92 : 0.78) : (L == 1 ? 0.95 : 0.92);
-      t = launch_seconds(p7 * tiles(mq, nq, 128.0), 2.0 * 128 * 128 * kq, 512.0, R * e) +
-          (var == STRASSEN_AB ? 2.0 : 4.0) * t_launch;
-      // M_r written once and read by the assembly once per destination; C read and written
-      t += (8.0 * mq * nq * (p7 + terms) + 16.0 * (double)m * (double)n) / bw;
-      if (var == STRASSEN_NAIVE)   // operand sums: terms read, one temporary per product written
-        t += 8.0 * (terms + p7) * (mq * kq + kq * nq) / bw;
+      const double t128 = tiles(mq, nq, 128.0);
+      if (t128 < 512.0)
+        return launch_seconds(tiles(mq, nq, 64.0), 2.0 * 64 * 64 * kq, 1024.0, K.R * 0.85) + K.t_launch;
+      return launch_seconds(t128, 2.0 * 128 * 128 * kq, 512.0, K.R) + K.t_launch;
     }
-  } else {
-    // BF16 products kernel: all 7^L products per 128 x 128 item; operand pass first
-    const double R = 400.0e12;
-    t = launch_seconds(tiles(mq, nq, 128.0), p7 * 2.0 * 128 * 128 * kq, 256.0, R) + 3.0 * t_launch;
-    t += (8.0 * terms + 2.0 * p7) * (mq * kq + kq * nq) / bw;
+    if (var == STRASSEN_ABC) {
+      const int64_t unit = int64_t(2) << L;
+      if (m % unit == 0 && k % unit == 0) {
+        if (L == 1) return ap_launch(whole ? K.e_full : K.e_masked);
+        const bool staged = n % 4 == 0 && (m / 2) * (n / 2) >= int64_t(2048) * 2048 && k >= 2048;
+        if (!staged) return 7.0 * ap_launch(K.e_unstaged);
+        // ten outer sums (two blocks read, one written each), then seven one-level launches
+        return 7.0 * ap_launch(whole ? K.e_full : K.e_masked) +
+               8.0 * 15.0 * (4.0 * mq * kq + 4.0 * kq * nq) / K.bw + 2.0 * K.t_launch;
+      }
+      const double e = L == 1 ? K.e_tile1 : K.e_tile2;
+      return launch_seconds(tiles(mq, nq, 128.0), p7 * 2.0 * 128 * 128 * kq, 512.0, K.R * e) +
+             K.t_launch;
+    }
+    const double e = var == STRASSEN_AB ? (L == 1 ? K.e_ab1 : K.e_ab2) : (L == 1 ? K.e_naive1 : K.e_naive2);
+    t = launch_seconds(p7 * tiles(mq, nq, 128.0), 2.0 * 128 * 128 * kq, 512.0, K.R * e) +
+        (var == STRASSEN_AB ? 2.0 : 4.0) * K.t_launch;
+    // M_r written once and read by the assembly once per destination; C read and written
+    t += (8.0 * mq * nq * (p7 + terms) + 16.0 * (double)m * (double)n) / K.bw;
+    if (var == STRASSEN_NAIVE)   // operand sums: terms read, one temporary per product written
+      t += 8.0 * (terms + p7) * (mq * kq + kq * nq) / K.bw;
+    return t;
   }
+  // BF16: all 7^L products per 128 x 128 item (two workgroups per CU); the operand pass reads
+  // every term once in FP64 and writes the padded bf16 slots
+  t = launch_seconds(tiles(mq, nq, 128.0), p7 * 2.0 * 128 * 128 * kq, 512.0, K.R_bf16) + 3.0 * K.t_launch;
+  const double mp = std::ceil(mq / 128.0) * 128.0, np_ = std::ceil(nq / 128.0) * 128.0,
+               kp = std::ceil(kq / 64.0) * 64.0;
+  t += (8.0 * terms * (mq * kq + kq * nq) + 2.0 * p7 * (mp * kp + kp * np_)) / K.bw_cast;
   return t;
 }
 

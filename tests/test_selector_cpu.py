@@ -32,9 +32,11 @@ def test_model_choice_valid_and_strassen_at_large_sizes():
         for d in (0, 1):
             lv, var = S.select(*shape, d)
             assert lv in (0, 1, 2) and (d == 0 or var == "abc")
-    # at 16384 the measured order (one-level ABC ahead of classical) is reproduced
+    # at 16384 the measured order (two-level ABC, one-level ABC, classical) is reproduced
     t = _model(16384, 16384, 16384, 0)
-    assert t[1] < t[0] and S.select(16384, 16384, 16384, 0) == (1, "abc")
+    assert t[4] < t[1] < t[0] and S.select(16384, 16384, 16384, 0) == (2, "abc")
+    # where the all-products layout does not apply, ABC runs on the slower general kernel
+    assert _model(16383, 16384, 16383, 0)[1] > _model(16384, 16384, 16384, 0)[1]
     assert S.select(20000, 20000, 20000, 1)[1] == "abc"
 
 
