@@ -283,8 +283,7 @@ def batched_suite(args):
     choices = tuned.choices()
     hist = {}
     for lv, cf in choices:
-        key = f"L{lv}_" + ["tile128", "tile64", "all_products"][cf]
-        hist[key] = hist.get(key, 0) + 1
+        hist[f"L{lv}_{'128' if cf == 0 else '64'}"] = hist.get(f"L{lv}_{'128' if cf == 0 else '64'}", 0) + 1
     log(f"autotune: {tune_s:.1f} s, choices {hist}")
     # timed step: the captured graph
     tuned.capture(As, Bs, Cs, 1.0, 1.0, stream)

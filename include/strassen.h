@@ -156,26 +156,20 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
 
 /*
  * Batched mode — many independent FP64 GEMMs  C_p := alpha*A_p*B_p + beta*C_p  (p < count) in
- * persistent kernel launches.  The paper chooses the member of the family per problem size
- * (Sec. 5); here every problem gets its own Strassen level (0, 1, 2; the ABC variant) and kernel
- * / tile shape cfg (0: tile kernel on 128 x 128 tiles, 1: on 64 x 64 tiles, 2: one level on the
- * all-products kernel, whole 64 x 64 tiles: m and n multiples of 128, k of 32, 16-byte aligned
- * operands with even leading dimensions — otherwise such a problem runs on cfg 0).  A work item
- * is one tile position of one problem, on which one workgroup runs all the problem's products;
- * items are handed out longest first through a device counter, cfg 2 items by a persistent
- * all-products kernel launched first, the others by the persistent tile kernel.  Per problem
- * the result is bitwise that of strassen_dgemm at the same level (every FP64 kernel performs
- * the same operations per element).
+ * one persistent kernel launch.  The paper chooses "the right member of the family" per problem
+ * size (Sec. 5); here every problem gets its own Strassen level (0, 1, 2; the ABC variant) and
+ * tile shape (0: 128 x 128, 1: 64 x 64).  A work item is one tile position of one problem, on
+ * which one workgroup runs all the problem's products; items are handed out longest first
+ * through a device counter.  Per problem the result is bitwise that of strassen_dgemm with the
+ * same level and tile shape (strassen_set_tile_config 0 / 1).
  *
  * strassen_batched_plan(count, m, n, k, levels, cfg, plan): problem sizes (host arrays of
  *   `count`).  levels / cfg (host, may be NULL = all -1): -1 lets the library choose by its rule
- *   (cfg 2 at one level from a min(m, n, k) threshold where the sizes allow, else the level
- *   from min(m, n, k) thresholds and 64 x 64 tiles when the 128 x 128 grid of a sub-block is
- *   small); cfg 2 with an automatic level sets level 1; the chosen values are written back.
- *   *plan receives an opaque handle (host memory).  Returns 0, -1 count < 0, -2 NULL or
- *   negative sizes, -5 / -6 a level / cfg out of range (cfg 2 with a level other than 1),
+ *   (level from min(m, n, k) thresholds, 64 x 64 tiles when the 128 x 128 grid of a sub-block is
+ *   small); the chosen values are written back.  *plan receives an opaque handle (host memory).
+ *   Returns 0, -1 count < 0, -2 NULL or negative sizes, -5 / -6 a level / cfg out of range,
  *   -7 plan NULL.  Needs no device.
- * strassen_batched_autotune(plan, sample, seed, stream): times the persistent kernels on `sample`
+ * strassen_batched_autotune(plan, sample, seed, stream): times the persistent kernel on `sample`
  *   problems of the plan (seeded choice; 0 = all) under candidate rule thresholds, on zeroed
  *   library-owned buffers of the same shapes, and re-chooses every -1 entry with the fastest
  *   rule.  Synchronises `stream`.  Returns 0, -1, -2, or a positive error.
@@ -187,7 +181,7 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
  *   scale C.  Returns 0, -1 plan NULL, -2 NULL arrays, -3 a bad problem (message names it), or
  *   a positive error.
  * strassen_batched_capture(...same arguments...): prepares the work list for these operands
- *   and records the launches (counter clear + persistent kernels) as a HIP graph in the plan,
+ *   and records the launch (counter clear + persistent kernel) as a HIP graph in the plan,
  *   without running it.  alpha == 0 / k == 0 problems are refused (STRASSEN_ERR_UNSUPPORTED).
  * strassen_batched_replay(plan, stream): launches the recorded graph on `stream`; every replay
  *   recomputes C from the operands recorded at capture.  A later run or capture on the plan

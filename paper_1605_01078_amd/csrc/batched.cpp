@@ -1,17 +1,12 @@
 // Batched mode host side: plans, the per-problem choice rule and its autotuner, the work list,
 // eager launches and graph capture / replay.
 //
-// Every problem gets a Strassen level and a kernel / tile shape (cfg): 0 = the tile kernel on
-// 128 x 128 tiles, 1 = on 64 x 64 tiles, 2 = one level on the all-products kernel (whole
-// 64 x 64 tiles: m and n multiples of 128, k of 32).  Entries given as -1 follow a rule,
-//   level 1, cfg 2           if min(m, n, k) >= t_ap and the sizes allow whole tiles, else
+// Every problem gets a Strassen level and a tile shape.  Entries given as -1 follow a rule,
 //   level = 2 if min(m, n, k) >= t2, else 1 if min(m, n, k) >= t1, else 0;
-//   cfg   = 1 if the 128 x 128 grid of one sub-block has fewer than `small` tiles, else 0;
-// whose thresholds the autotuner picks by timing the persistent kernels themselves on a sample
-// of the batch (the quantity that matters is the batch's time, not one problem's latency).
-// cfg 2 problems run in a persistent all-products kernel launched before the tile kernel's;
-// every FP64 kernel of the library performs the same operations per element, so each problem's
-// result is bitwise that of a single strassen_dgemm call at its level.
+//   tile  = 64 x 64 if the 128 x 128 grid of one sub-block has fewer than `small` tiles,
+//           else 128 x 128;
+// whose thresholds the autotuner picks by timing the persistent kernel itself on a sample of
+// the batch (the quantity that matters is the batch's time, not one problem's latency).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,13 +27,7 @@ struct Rule {
   int64_t t1 = std::numeric_limits<int64_t>::max();   // min dimension for one level
   int64_t t2 = std::numeric_limits<int64_t>::max();   // for two levels
   int64_t small = 0;                                  // 128-tile count below which tiles are 64
-  int64_t t_ap = std::numeric_limits<int64_t>::max(); // for one level on the all-products kernel
 };
-
-// Sizes for which one level runs on whole 64 x 64 tiles of the all-products kernel.
-static bool ap_sizes(int64_t m, int64_t n, int64_t k) {
-  return m > 0 && n > 0 && k > 0 && m % 128 == 0 && n % 128 == 0 && k % 32 == 0;
-}
 
 struct BatchedPlan {
   int count = 0;
@@ -50,14 +39,11 @@ struct BatchedPlan {
   int dev = -1;
   BatchProblem* d_probs = nullptr;
   BatchItem* d_items = nullptr;
-  FusedArgs* d_ap_probs = nullptr;
-  BatchItem* d_ap_items = nullptr;
-  unsigned* d_counter = nullptr;   // [0]: tile kernel, [kApCounter]: all-products kernel
-  unsigned* d_ap_counter = nullptr;   // d_counter + kApCounter (a graph node argument)
-  size_t cap_probs = 0, cap_items = 0, cap_ap_probs = 0, cap_ap_items = 0;
-  int n_items = 0, n_ap_items = 0;
+  unsigned* d_counter = nullptr;
+  size_t cap_probs = 0, cap_items = 0;
+  int n_items = 0;
   bool vec = true;
-  int grid = 0, grid_ap = 0;
+  int grid = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -65,15 +51,6 @@ struct BatchedPlan {
 static void apply_rule(const Rule& r, int64_t m, int64_t n, int64_t k, int* level, int* cfg,
                        bool set_level, bool set_cfg) {
   const int64_t mn = std::min(m, std::min(n, k));
-  if (!set_cfg && *cfg == 2) {   // the all-products kernel was asked for: one level
-    if (set_level) *level = 1;
-    return;
-  }
-  if (set_cfg && (!set_level ? *level == 1 : true) && mn >= r.t_ap && ap_sizes(m, n, k)) {
-    if (set_level) *level = 1;
-    *cfg = 2;
-    return;
-  }
   if (set_level) *level = mn >= r.t2 ? 2 : (mn >= r.t1 ? 1 : 0);
   if (set_cfg) {
     const int64_t q = int64_t(1) << *level;
@@ -94,91 +71,27 @@ static void free_device(BatchedPlan* p) {
   if (p->d_probs) (void)hipFree(p->d_probs);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);
-  if (p->d_ap_probs) (void)hipFree(p->d_ap_probs);
-  if (p->d_ap_items) (void)hipFree(p->d_ap_items);
   p->d_probs = nullptr;
   p->d_items = nullptr;
   p->d_counter = nullptr;
-  p->d_ap_counter = nullptr;
-  p->d_ap_probs = nullptr;
-  p->d_ap_items = nullptr;
-  p->cap_probs = p->cap_items = p->cap_ap_probs = p->cap_ap_items = 0;
+  p->cap_probs = p->cap_items = 0;
 }
 
 // Problems (GemmArgs per problem) and the cost-ordered work list for the given operands.
-struct Work {
-  std::vector<BatchProblem> probs;
-  std::vector<BatchItem> items;
-  std::vector<FusedArgs> ap_probs;
-  std::vector<BatchItem> ap_items;
-  bool vec = true;
-};
-
-// Longest items first (stable: ties keep problem order).
-static void sort_items(std::vector<BatchItem>* items, const std::vector<double>& cost) {
-  std::vector<int> order(items->size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  std::vector<BatchItem> sorted(items->size());
-  for (size_t i = 0; i < order.size(); ++i) sorted[i] = (*items)[order[i]];
-  items->swap(sorted);
-}
-
-// A cfg 2 problem as all-products kernel arguments, if its operands allow the kernel's 16-byte
-// layout (else it runs on the tile kernel at the same level, with the same bits).
-static bool ap_args(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
-                    const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
-                    double beta, FusedArgs* f) {
-  const bool al16 = ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0 && ((uintptr_t)C & 15) == 0;
-  if (!ap_sizes(m, n, k) || !al16 || lda % 2 || ldb % 2 || ldc % 2) return false;
-  const int64_t lim = int64_t(1) << 31;
-  if (8 * 16 * lda >= lim || 8 * 64 * ldb >= lim || 8 * 64 * ldc >= lim) return false;
-  std::memset(f, 0, sizeof *f);
-  f->A = A;
-  f->B = B;
-  f->C = C;
-  f->lda = lda;
-  f->ldb = ldb;
-  f->ldc = ldc;
-  f->n = n;
-  f->mq = m / 2;
-  f->nq = n / 2;
-  f->kq = k / 2;
-  f->alpha = alpha;
-  f->beta = beta;
-  f->tiles_m = (int32_t)(f->mq / 64);
-  f->tiles_n = (int32_t)(f->nq / 64);
-  f->nc = 1;
-  f->c_first = 1;
-  f->a_sg[0] = f->b_sg[0] = f->c_sg[0] = 1.0;
-  return all_products_whole_tiles(*f);
-}
-
 static int build_work(const BatchedPlan& p, const double* const* A, const int64_t* lda,
                       const double* const* B, const int64_t* ldb, double* const* C,
-                      const int64_t* ldc, double alpha, double beta, Work* w) {
+                      const int64_t* ldc, double alpha, double beta,
+                      std::vector<BatchProblem>* probs, std::vector<BatchItem>* items,
+                      bool* vec) {
   const TableDev* tabs = host_tables();
-  std::vector<BatchProblem>* probs = &w->probs;
-  std::vector<BatchItem>* items = &w->items;
-  *w = Work();
-  bool* vec = &w->vec;
-  std::vector<double> cost, ap_cost;
+  probs->clear();
+  items->clear();
+  *vec = true;
+  std::vector<double> cost;
   for (int i = 0; i < p.count; ++i) {
     const int64_t m = p.m[i], n = p.n[i], k = p.k[i];
     if (m == 0 || n == 0 || k == 0 || alpha == 0.0) continue;   // handled by the caller
     const int L = p.level[i];
-    FusedArgs f;
-    if (p.cfg[i] == 2 && L == 1 &&
-        ap_args(m, n, k, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], alpha, beta, &f)) {
-      const int pid = (int)w->ap_probs.size();
-      w->ap_probs.push_back(f);
-      const double c = 7.0 * 64 * 64 * (double)f.kq;
-      for (int t = 0; t < f.tiles_m * f.tiles_n; ++t) {
-        w->ap_items.push_back({pid, t});
-        ap_cost.push_back(c);
-      }
-      continue;
-    }
     const int64_t q = int64_t(1) << L;
     BatchProblem bp;
     std::memset(&bp, 0, sizeof bp);
@@ -199,7 +112,7 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
     g.beta = beta;
     g.tab = table_id(L, false);
     g.mode = kModeABC;
-    bp.cfg = p.cfg[i] == 1 ? 1 : 0;
+    bp.cfg = p.cfg[i];
     const int64_t bm = bp.cfg == 0 ? 128 : 64;
     g.tiles_m = (int32_t)cdiv(g.mq, bm);
     g.tiles_n = (int32_t)cdiv(g.nq, bm);
@@ -214,10 +127,14 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
       cost.push_back(c);
     }
   }
-  sort_items(items, cost);
-  sort_items(&w->ap_items, ap_cost);
-  if (items->size() >= (size_t)std::numeric_limits<int32_t>::max() ||
-      w->ap_items.size() >= (size_t)std::numeric_limits<int32_t>::max())
+  // longest items first (stable: ties keep problem order)
+  std::vector<int> order(items->size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<BatchItem> sorted(items->size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = (*items)[order[i]];
+  items->swap(sorted);
+  if (items->size() >= (size_t)std::numeric_limits<int32_t>::max())
     return fail(STRASSEN_ERR_UNSUPPORTED, "batched: too many work items");
   return 0;
 }
@@ -241,21 +158,8 @@ static int validate_operands(const BatchedPlan& p, const double* const* A, const
 }
 
 // Device copies of the problems and the work list (grown on demand).
-template <class T>
-static int grow_copy(T** d, size_t* cap, const std::vector<T>& h, hipStream_t s) {
-  if (*cap < h.size()) {
-    if (*d) SMX_HIP(hipFree(*d));
-    *d = nullptr;
-    SMX_HIP(hipMalloc(d, std::max<size_t>(1, h.size()) * sizeof(T)));
-    *cap = h.size();
-  }
-  if (!h.empty()) SMX_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  return 0;
-}
-
-static int upload(BatchedPlan* p, const Work& w, hipStream_t s) {
-  const std::vector<BatchProblem>& probs = w.probs;
-  const std::vector<BatchItem>& items = w.items;
+static int upload(BatchedPlan* p, const std::vector<BatchProblem>& probs,
+                  const std::vector<BatchItem>& items, hipStream_t s) {
   int dev = 0;
   SMX_HIP(hipGetDevice(&dev));
   if (p->dev != dev) {
@@ -263,32 +167,31 @@ static int upload(BatchedPlan* p, const Work& w, hipStream_t s) {
     p->dev = dev;
   }
   if (!p->d_counter) SMX_HIP(hipMalloc(&p->d_counter, 256));
-  p->d_ap_counter = p->d_counter + kApCounter;
-  if (int rc = grow_copy(&p->d_probs, &p->cap_probs, probs, s)) return rc;
-  if (int rc = grow_copy(&p->d_items, &p->cap_items, items, s)) return rc;
-  if (int rc = grow_copy(&p->d_ap_probs, &p->cap_ap_probs, w.ap_probs, s)) return rc;
-  if (int rc = grow_copy(&p->d_ap_items, &p->cap_ap_items, w.ap_items, s)) return rc;
+  if (p->cap_probs < probs.size()) {
+    if (p->d_probs) SMX_HIP(hipFree(p->d_probs));
+    p->d_probs = nullptr;
+    SMX_HIP(hipMalloc(&p->d_probs, std::max<size_t>(1, probs.size()) * sizeof(BatchProblem)));
+    p->cap_probs = probs.size();
+  }
+  if (p->cap_items < items.size()) {
+    if (p->d_items) SMX_HIP(hipFree(p->d_items));
+    p->d_items = nullptr;
+    SMX_HIP(hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(BatchItem)));
+    p->cap_items = items.size();
+  }
+  if (!probs.empty())
+    SMX_HIP(hipMemcpyAsync(p->d_probs, probs.data(), probs.size() * sizeof(BatchProblem),
+                           hipMemcpyHostToDevice, s));
+  if (!items.empty())
+    SMX_HIP(hipMemcpyAsync(p->d_items, items.data(), items.size() * sizeof(BatchItem),
+                           hipMemcpyHostToDevice, s));
   // the host vectors go out of scope after this call: finish the copies first
   SMX_HIP(hipStreamSynchronize(s));
   p->n_items = (int)items.size();
-  p->n_ap_items = (int)w.ap_items.size();
-  p->vec = w.vec;
   hipDeviceProp_t prop;
   SMX_HIP(hipGetDeviceProperties(&prop, dev));
   p->grid = 2 * prop.multiProcessorCount;   // two 256-thread workgroups per CU
-  p->grid_ap = prop.multiProcessorCount;    // one 512-thread workgroup (128 KB of LDS) per CU
   return 0;
-}
-
-// The launches of one run: clear both counters, the all-products items, the tile items.
-static hipError_t launch_plan(const BatchedPlan& p, hipStream_t s) {
-  hipError_t e = launch_clear_counters(p.d_counter, s);
-  if (e == hipSuccess && p.n_ap_items > 0)
-    e = launch_batched_ap(p.d_ap_probs, p.d_ap_items, p.n_ap_items, p.d_counter + kApCounter,
-                          p.grid_ap, s);
-  if (e == hipSuccess && p.n_items > 0)
-    e = launch_batched(p.d_probs, p.d_items, p.n_items, p.d_counter, p.vec, p.grid, s);
-  return e;
 }
 
 // Problems with alpha == 0 or k == 0 only scale C (outside the persistent kernel).
@@ -314,13 +217,16 @@ static int run_plan(BatchedPlan* p, const double* const* A, const int64_t* lda,
   if (int rc = validate_operands(*p, A, lda, B, ldb, C, ldc)) return rc;
   int dev = 0;
   if (int rc = device_ready(&dev)) return rc;
-  Work w;
-  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &w)) return rc;
+  std::vector<BatchProblem> probs;
+  std::vector<BatchItem> items;
+  bool vec = true;
+  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &vec)) return rc;
   if (int rc = scale_only(*p, C, ldc, alpha, beta, s)) return rc;
   drop_graph(p);   // the buffers a recorded graph reads are about to change
-  if (int rc = upload(p, w, s)) return rc;
-  if (p->n_items == 0 && p->n_ap_items == 0) return 0;
-  SMX_HIP(launch_plan(*p, s));
+  if (int rc = upload(p, probs, items, s)) return rc;
+  p->vec = vec;
+  if (p->n_items == 0) return 0;
+  SMX_HIP(launch_batched(p->d_probs, p->d_items, p->n_items, p->d_counter, vec, p->grid, s));
   return 0;
 }
 
@@ -376,11 +282,9 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
   const int64_t t1s[] = {inf, 3072, 2048, 1536, 1024};
   const int64_t t2s[] = {inf, 4096, 3072, 2048};
   const int64_t smalls[] = {0, 4, 16};
-  const int64_t taps[] = {inf, 2048, 1024, 512};
   Rule best = p->rule;
   float best_ms = std::numeric_limits<float>::max();
   int rc = 0;
-  for (int64_t tap : taps)
   for (int64_t t1 : t1s) {
     for (int64_t t2 : t2s) {
       if (t2 != inf && t2 <= t1 && t1 != inf) continue;
@@ -391,7 +295,6 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
         r.t1 = t1;
         r.t2 = t2;
         r.small = sm;
-        r.t_ap = tap;
         for (int i = 0; i < sp.count; ++i)
           apply_rule(r, sp.m[i], sp.n[i], sp.k[i], &sp.level[i], &sp.cfg[i], true, true);
         // one warm call, then the median of three timed calls
@@ -400,7 +303,8 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
                       0.0, s);
         for (int rep = 0; rep < 3 && rc == 0 && e == hipSuccess; ++rep) {
           e = hipEventRecord(e0, s);
-          if (e == hipSuccess) e = launch_plan(sp, s);
+          if (e == hipSuccess && sp.n_items > 0)
+            e = launch_batched(sp.d_probs, sp.d_items, sp.n_items, sp.d_counter, sp.vec, sp.grid, s);
           if (e == hipSuccess) e = hipEventRecord(e1, s);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           if (e == hipSuccess) e = hipEventElapsedTime(&ts[rep], e0, e1);
@@ -442,14 +346,15 @@ static int capture(BatchedPlan* p, const double* const* A, const int64_t* lda,
     if ((alpha == 0.0 || p->k[i] == 0) && p->m[i] > 0 && p->n[i] > 0 && beta != 1.0)
       return fail(STRASSEN_ERR_UNSUPPORTED,
                   "batched capture: alpha == 0 or k == 0 (problem %d) is only run eagerly", i);
-  Work w;
-  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &w)) return rc;
+  std::vector<BatchProblem> probs;
+  std::vector<BatchItem> items;
+  bool vec = true;
+  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &vec)) return rc;
   drop_graph(p);
-  if (int rc = upload(p, w, s)) return rc;
-  const bool vec = p->vec;
+  if (int rc = upload(p, probs, items, s)) return rc;
+  p->vec = vec;
   SMX_HIP(hipGraphCreate(&p->graph, 0));
-  hipGraphNode_t clear_node, run_node, ap_node;
-  hipGraphNode_t last = nullptr;
+  hipGraphNode_t clear_node, run_node;
   void* clear_args[] = {&p->d_counter};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof kp);
@@ -458,18 +363,6 @@ static int capture(BatchedPlan* p, const double* const* A, const int64_t* lda,
   kp.blockDim = dim3(64);
   kp.kernelParams = clear_args;
   SMX_HIP(hipGraphAddKernelNode(&clear_node, p->graph, nullptr, 0, &kp));
-  last = clear_node;
-  if (p->n_ap_items > 0) {
-    void* ap_args_[] = {&p->d_ap_probs, &p->d_ap_items, &p->n_ap_items, &p->d_ap_counter};
-    hipKernelNodeParams ap;
-    std::memset(&ap, 0, sizeof ap);
-    ap.func = const_cast<void*>(batched_ap_kernel_fn());
-    ap.gridDim = dim3(p->grid_ap);
-    ap.blockDim = dim3(512);
-    ap.kernelParams = ap_args_;
-    SMX_HIP(hipGraphAddKernelNode(&ap_node, p->graph, &last, 1, &ap));
-    last = ap_node;
-  }
   if (p->n_items > 0) {
     void* run_args[] = {&p->d_probs, &p->d_items, &p->n_items, &p->d_counter};
     hipKernelNodeParams rp;
@@ -478,7 +371,7 @@ static int capture(BatchedPlan* p, const double* const* A, const int64_t* lda,
     rp.gridDim = dim3(p->grid);
     rp.blockDim = dim3(256);
     rp.kernelParams = run_args;
-    SMX_HIP(hipGraphAddKernelNode(&run_node, p->graph, &last, 1, &rp));
+    SMX_HIP(hipGraphAddKernelNode(&run_node, p->graph, &clear_node, 1, &rp));
   }
   SMX_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
   return 0;
@@ -503,9 +396,7 @@ int strassen_batched_plan(int count, const int64_t* m, const int64_t* n, const i
     if (levels[i] < -1 || levels[i] > smx::kMaxLevels)
       return smx::fail(-5, "problem %d: level %d not in -1..%d", i, levels[i], smx::kMaxLevels);
   for (int i = 0; cfg && i < count; ++i)
-    if (cfg[i] < -1 || cfg[i] > 2 ||
-        (cfg[i] == 2 && levels && levels[i] >= 0 && levels[i] != 1))
-      return smx::fail(-6, "problem %d: cfg %d not in -1..2 (2 needs level 1)", i, cfg[i]);
+    if (cfg[i] < -1 || cfg[i] > 1) return smx::fail(-6, "problem %d: tile %d not in -1..1", i, cfg[i]);
   auto* p = new smx::BatchedPlan;
   p->count = count;
   p->m.assign(m, m + count);

@@ -84,20 +84,13 @@ struct AllProducts {
 
   typedef d4_t Acc[7][2];
 
-  // One launch: workgroup b takes the tile position of logical id xcd_remap(b).
   __device__ static void run(const FusedArgs& args, double* lds) {
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    int ti, tj;
-    tile_coords(logical, args.tiles_m, args.tiles_n, ti, tj);
-    run_tile(args, ti, tj, lds);
-  }
-
-  // Tile position (ti, tj) of every sub-block: all products, then the C epilogue.  Ends with no
-  // tile load in flight; the caller synchronises the workgroup before reusing `lds`.
-  __device__ static void run_tile(const FusedArgs& args, int ti, int tj, double* lds) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar addressing
     const int wm = wave & 1, wn = wave >> 1;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    int ti, tj;
+    tile_coords(logical, args.tiles_m, args.tiles_n, ti, tj);
     const int64_t i0 = (int64_t)ti * T, j0 = (int64_t)tj * T;
     const int64_t lda = args.lda, ldb = args.ldb, mq = args.mq, nq = args.nq, kq = args.kq;
 
@@ -355,43 +348,7 @@ __global__ __launch_bounds__(512, 1) void all_products_kernel(const FusedArgs ar
   K::run(args, lds);
 }
 
-// Batched mode: a persistent kernel over (problem, tile) items of one-level ABC problems whose
-// tiles are all whole; item it of the list runs the whole-tile kernel above on problem
-// probs[items[it].problem] at tile items[it].tile = ti + tiles_m * tj.  Items come through an
-// atomic counter (cleared by the batched mode's clear kernel), longest first.
-__global__ __launch_bounds__(512, 1) void batched_ap_kernel(const FusedArgs* probs,
-                                                            const BatchItem* items, int n_items,
-                                                            unsigned* counter) {
-  using K = AllProducts<1, 1, 16, 2, true>;
-  __shared__ __attribute__((aligned(16))) double lds[K::LDS_D];
-  __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0)
-      s_item = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();   // also: every wave is done with the previous item's tiles in LDS
-    const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar problem loads
-    __syncthreads();   // s_item is rewritten by the next round
-    if (it >= n_items) break;   // every workgroup ends once the list is exhausted
-    const BatchItem w = items[it];
-    const FusedArgs& f = probs[w.problem];
-    K::run_tile(f, w.tile % f.tiles_m, w.tile / f.tiles_m, lds);
-  }
-}
-
 }  // namespace
-
-hipError_t launch_batched_ap(const FusedArgs* probs, const BatchItem* items, int n_items,
-                             unsigned* counter, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(batched_ap_kernel, dim3(grid), dim3(512), 0, s, probs, items, n_items, counter);
-  return hipGetLastError();
-}
-
-const void* batched_ap_kernel_fn() { return reinterpret_cast<const void*>(&batched_ap_kernel); }
-
-// The whole-tile condition of the one-level kernel (see launch_all_products).
-bool all_products_whole_tiles(const FusedArgs& a) {
-  return a.mq % 64 == 0 && a.nq % 64 == 0 && a.kq % 16 == 0 && 2 * a.nq <= a.n;
-}
 
 hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(512);

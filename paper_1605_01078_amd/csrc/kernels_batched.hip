@@ -24,13 +24,8 @@ hipError_t upload_tables_batched(const TableDev* tabs) {
 
 namespace {
 
-// Clears the work counters of both persistent kernels (tile kernel: counter[0]; all-products
-// kernel: counter[kApCounter], on its own cache line).
 __global__ void clear_counter_kernel(unsigned* counter) {
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(counter + kApCounter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class Tile>
@@ -59,7 +54,7 @@ __global__ __launch_bounds__(256, 2) void batched_kernel(const BatchProblem* pro
     if (threadIdx.x == 0)
       s_item = (int)__hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar problem loads
+    const int it = s_item;
     __syncthreads();   // s_item is rewritten by the next round
     if (it >= n_items) break;   // every workgroup ends once the list is exhausted
     const BatchItem w = items[it];
@@ -71,13 +66,9 @@ __global__ __launch_bounds__(256, 2) void batched_kernel(const BatchProblem* pro
 
 }  // namespace
 
-hipError_t launch_clear_counters(unsigned* counter, hipStream_t s) {
-  hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(64), 0, s, counter);
-  return hipGetLastError();
-}
-
 hipError_t launch_batched(const BatchProblem* probs, const BatchItem* items, int n_items,
                           unsigned* counter, bool vec, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(64), 0, s, counter);
   if (vec) hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(256), 0, s, probs, items, n_items, counter);
   else hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(256), 0, s, probs, items, n_items, counter);
   return hipGetLastError();

@@ -36,14 +36,6 @@ hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s);
 hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s);
 // Batched mode: clear the item counter, then the persistent kernel over `grid` workgroups.
 hipError_t upload_tables_batched(const TableDev* tabs);
-// Batched mode, one-level problems on the all-products kernel (whole 64 x 64 tiles): a
-// persistent kernel of `grid` 512-thread workgroups over `items` (tile = ti + tiles_m * tj).
-hipError_t launch_batched_ap(const FusedArgs* probs, const BatchItem* items, int n_items,
-                             unsigned* counter, int grid, hipStream_t s);
-const void* batched_ap_kernel_fn();
-bool all_products_whole_tiles(const FusedArgs& a);
-constexpr int kApCounter = 32;   // the all-products kernel's counter: counter + kApCounter
-hipError_t launch_clear_counters(unsigned* counter, hipStream_t s);
 hipError_t launch_batched(const BatchProblem* probs, const BatchItem* items, int n_items,
                           unsigned* counter, bool vec, int grid, hipStream_t s);
 const void* batched_kernel_fn(bool vec);   // kernel symbols, for graph nodes

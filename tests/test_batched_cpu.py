@@ -17,10 +17,6 @@ def test_plan_explicit_and_default_choices():
     assert ch[1] == (0, 0) and ch[3] == (0, 0)
     b.close()
     b.close()   # idempotent
-    # the all-products kernel (cfg 2) runs one level: an automatic level becomes 1
-    b = sx.Batched([(512, 512, 512), (512, 512, 512)], levels=[-1, 1], cfg=[2, 2])
-    assert b.choices() == [(1, 2), (1, 2)]
-    b.close()
 
 
 def test_plan_workload_c4_shapes():
@@ -42,8 +38,7 @@ def test_plan_argument_errors():
     assert L.strassen_batched_plan(2, None, n, k, None, None, ctypes.byref(plan)) == -2
     assert L.strassen_batched_plan(2, i64(4, -1), n, k, None, None, ctypes.byref(plan)) == -2
     assert L.strassen_batched_plan(2, m, n, k, ci(0, 3), None, ctypes.byref(plan)) == -5
-    assert L.strassen_batched_plan(2, m, n, k, None, ci(3, 0), ctypes.byref(plan)) == -6
-    assert L.strassen_batched_plan(2, m, n, k, ci(2, 0), ci(2, 0), ctypes.byref(plan)) == -6
+    assert L.strassen_batched_plan(2, m, n, k, None, ci(2, 0), ctypes.byref(plan)) == -6
     assert L.strassen_batched_plan(2, m, n, k, None, None, None) == -7
     assert L.strassen_batched_plan(2, m, n, k, None, None, ctypes.byref(plan)) == 0
     lv, cf = ctypes.c_int(), ctypes.c_int()
