@@ -388,21 +388,12 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
     ob.rows = ok;
     ob.cols = on;
     ob.dst_stride = sp.tb_stride;
-    for (int R = 0; R < 7; ++R) {
-      const QProduct& P = kOneLevel[R];
-      if (sp.slot_a[R] >= 0) {
-        oa.off0[sp.slot_a[R]] = a_block(P.a[0].q);
-        oa.off1[sp.slot_a[R]] = a_block(P.a[1].q);
-        oa.sg1[sp.slot_a[R]] = P.a[1].sign;
-      }
-      if (sp.slot_b[R] >= 0) {
-        ob.off0[sp.slot_b[R]] = b_block(P.b[0].q);
-        ob.off1[sp.slot_b[R]] = b_block(P.b[1].q);
-        ob.sg1[sp.slot_b[R]] = P.b[1].sign;
-      }
+    for (int q = 0; q < 4; ++q) {
+      oa.blk[q] = a_block(q);
+      ob.blk[q] = b_block(q);
     }
-    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, sp.na_slots, stream));
-    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, sp.nb_slots, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
   }
   bool touched[4] = {false, false, false, false};
   for (int R = 0; R < 7; ++R) {

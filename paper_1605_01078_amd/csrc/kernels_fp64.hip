@@ -117,37 +117,44 @@ __global__ __launch_bounds__(256) void sum_kernel(const SumArgs args) {
   args.dst[(int64_t)slot * args.dst_stride + i + j * args.rows_q] = v;
 }
 
-// Staged outer sums: a workgroup covers kOuterSumRows rows of kOuterSumCols consecutive columns
-// of one slot, each lane a row pair (16-byte loads and stores), all loads of a lane issued
-// before its first store.  x0 + s1 x1 is rounded once (the pair rule of signed_sum with a first
-// sign of +1, as the all-products kernel forms the same sum).
+// Staged outer sums: a workgroup covers kOuterSumRows rows of kOuterSumCols consecutive columns,
+// each lane a row pair (16-byte accesses): it reads the four outer blocks once and writes every
+// two-term sum of its side of the one-level table, x0 + s1 x1 rounded once (the pair rule of
+// signed_sum with a first sign of +1, as the all-products kernel forms the same sum).
 constexpr int kOuterSumRows = 512, kOuterSumCols = 4;
 
+template <int SIDE>
 __global__ __launch_bounds__(256) void outer_sum_kernel(const OuterSumArgs args) {
-  const int slot = blockIdx.y;
   const int64_t i = (int64_t)(blockIdx.x % args.chunks_r) * kOuterSumRows + 2 * threadIdx.x;
   const int64_t j0 = (int64_t)(blockIdx.x / args.chunks_r) * kOuterSumCols;
   if (i >= args.rows) return;
-  const double* x0 = args.src + args.off0[slot] + i;
-  const double* x1 = args.src + args.off1[slot] + i;
-  double* d = args.dst + slot * args.dst_stride + i;
-  const double s1 = args.sg1[slot];
-  d2_t a[kOuterSumCols], b[kOuterSumCols];
+  d2_t x[4][kOuterSumCols];
 #pragma unroll
   for (int c = 0; c < kOuterSumCols; ++c) {
     if (j0 + c < args.cols) {
-      a[c] = *reinterpret_cast<const d2_t*>(x0 + (j0 + c) * args.ld);
-      b[c] = *reinterpret_cast<const d2_t*>(x1 + (j0 + c) * args.ld);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        x[q][c] = *reinterpret_cast<const d2_t*>(args.src + args.blk[q] + i + (j0 + c) * args.ld);
     }
   }
+  int slot = 0;
 #pragma unroll
-  for (int c = 0; c < kOuterSumCols; ++c) {
-    if (j0 + c < args.cols) {
-      d2_t v;
-      v.x = __builtin_fma(s1, b[c].x, a[c].x);
-      v.y = __builtin_fma(s1, b[c].y, a[c].y);
-      *reinterpret_cast<d2_t*>(d + (j0 + c) * args.rows) = v;
+  for (int r = 0; r < 7; ++r) {
+    const QProduct& P = kOneLevel[r];
+    if ((SIDE == 0 ? P.na : P.nb) != 2) continue;
+    const QTerm t0 = SIDE == 0 ? P.a[0] : P.b[0], t1 = SIDE == 0 ? P.a[1] : P.b[1];
+    const double s1 = t1.sign;
+    double* d = args.dst + slot * args.dst_stride + i;
+#pragma unroll
+    for (int c = 0; c < kOuterSumCols; ++c) {
+      if (j0 + c < args.cols) {
+        d2_t v;
+        v.x = __builtin_fma(s1, x[t1.q][c].x, x[t0.q][c].x);
+        v.y = __builtin_fma(s1, x[t1.q][c].y, x[t0.q][c].y);
+        *reinterpret_cast<d2_t*>(d + (j0 + c) * args.rows) = v;
+      }
     }
+    ++slot;
   }
 }
 
@@ -210,12 +217,13 @@ hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_outer_sums(const OuterSumArgs& a, int nslots, hipStream_t s) {
+hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s) {
   OuterSumArgs b = a;
   b.chunks_r = (int32_t)((a.rows + kOuterSumRows - 1) / kOuterSumRows);
   const int64_t gx = (int64_t)b.chunks_r * ((a.cols + kOuterSumCols - 1) / kOuterSumCols);
-  if (nslots < 1 || nslots > kMaxOuterSlots || gx >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(outer_sum_kernel, dim3((unsigned)gx, nslots), dim3(256), 0, s, b);
+  if (gx >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  if (side == 0) hipLaunchKernelGGL(outer_sum_kernel<0>, dim3((unsigned)gx), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL(outer_sum_kernel<1>, dim3((unsigned)gx), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v,
                            float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
-hipError_t launch_outer_sums(const OuterSumArgs& a, int nslots, hipStream_t s);
+hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s);   // side 0 A, 1 B
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 
 }  // namespace smx

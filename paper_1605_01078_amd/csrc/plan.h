@@ -96,16 +96,16 @@ struct AssembleArgs {
   int32_t chunks_m;     // ceil(mq / rows per workgroup)
 };
 
-// Staged outer-level operand sums of two-level ABC: slot s := X[off0[s]] + sg1[s] * X[off1[s]],
-// two blocks of rows x cols (leading dimension ld) summed into a rows x cols slot (leading
-// dimension rows) at dst + s * dst_stride.  rows even, ld even, src and dst 16-byte aligned.
-constexpr int kMaxOuterSlots = 7;
+// Staged outer-level operand sums of two-level ABC, one side (A or B) per launch: the four outer
+// blocks of the operand (rows x cols each, leading dimension ld, at src + blk[q]) are read once
+// and every two-term sum of that side of the one-level table (in product order) is written as a
+// rows x cols slot (leading dimension rows) at dst + s * dst_stride.  rows even, ld even, src and
+// dst 16-byte aligned.
 struct OuterSumArgs {
   const double* src;
   double* dst;
   int64_t ld, rows, cols, dst_stride;
-  int64_t off0[kMaxOuterSlots], off1[kMaxOuterSlots];
-  double sg1[kMaxOuterSlots];
+  int64_t blk[4];
   int32_t chunks_r;     // row chunks per column group (set by the launcher)
 };
 
