@@ -121,9 +121,10 @@ double model_seconds(int64_t m, int64_t n, int64_t k, int dtype, int c) {
         if (L == 1) return ap_launch(whole ? K.e_full : K.e_masked);
         const bool staged = n % 4 == 0 && (m / 2) * (n / 2) >= int64_t(2048) * 2048 && k >= 2048;
         if (!staged) return 7.0 * ap_launch(K.e_unstaged);
-        // ten outer sums (two blocks read, one written each), then seven one-level launches
+        // the outer sums (per side four blocks read, five sums written), then seven one-level
+        // launches
         return 7.0 * ap_launch(whole ? K.e_full : K.e_masked) +
-               8.0 * 15.0 * (4.0 * mq * kq + 4.0 * kq * nq) / K.bw + 2.0 * K.t_launch;
+               8.0 * 9.0 * (4.0 * mq * kq + 4.0 * kq * nq) / K.bw + 2.0 * K.t_launch;
       }
       const double e = L == 1 ? K.e_tile1 : K.e_tile2;
       return launch_seconds(tiles(mq, nq, 128.0), p7 * 2.0 * 128 * 128 * kq, 512.0, K.R * e) +
