@@ -68,21 +68,20 @@ __device__ __forceinline__ float pair_rule_sum(const double* x, const double* sg
   return p01 + sf[2] * (xf[2] + (sf[2] * sf[3]) * xf[3]);
 }
 
-// Each thread sums 16 consecutive elements of one source column: A side, rows ob.. of column
-// kk (written through an LDS transpose, since the operand is stored k-contiguous); B side,
-// k values kc.. of column oo (already k-contiguous).  The term pointers and their valid extents
-// are set up once per thread; the element loop only loads and adds.
+// Each thread sums one source row of a 64 x 64 block across 16 consecutive columns: lane l of
+// wave w takes row l and columns 16 w .. 16 w + 15, so every load instruction of a wave reads 64
+// consecutive doubles of one column (coalesced).  The term pointers and their valid extents are
+// set up once per thread; the element loop only loads and adds.
 template <int NT, bool F64>
-__device__ __forceinline__ void cast_column(const CastArgs& args, const ProdDesc& pd, int64_t o0,
-                                            int64_t k0, int col_local, int row_local,
-                                            float* v) {
+__device__ __forceinline__ void cast_row(const CastArgs& args, const ProdDesc& pd, int64_t o0,
+                                         int64_t k0, int row_local, int col_base, float* v) {
   const uint8_t* codes = args.side == 0 ? pd.a : pd.b;
   // per term: a buffer over the workgroup's block of the term (uniform base), the lane's byte
-  // offset in it and how many of its 16 elements exist; missing ones get an offset past the
+  // offset in it and how many of its 16 columns exist; missing ones get an offset past the
   // buffer range and load as zero, without a branch
   __amdgpu_buffer_rsrc_t rs[NT];
   uint32_t off[NT];
-  int nrow[NT];
+  int ncol[NT];
   double sg[NT];
   const int64_t r_blk = args.side == 0 ? o0 : k0, c_blk = args.side == 0 ? k0 : o0;
 #pragma unroll
@@ -92,9 +91,9 @@ __device__ __forceinline__ void cast_column(const CastArgs& args, const ProdDesc
     const int64_t r_ext = min64(args.rq, args.rows - br * args.rq);   // valid rows of the block
     const int64_t c_ext = min64(args.cq, args.cols - bc * args.cq);
     rs[s] = make_rsrc(args.src + (br * args.rq + r_blk) + (bc * args.cq + c_blk) * args.ld);
-    const bool col_ok = c_blk + col_local < c_ext;
-    nrow[s] = col_ok ? (int)min64(16, max(int64_t(0), r_ext - r_blk - row_local)) : 0;
-    off[s] = (uint32_t)(8 * (row_local + (int64_t)col_local * args.ld));
+    const bool row_ok = r_blk + row_local < r_ext;
+    ncol[s] = row_ok ? (int)min64(16, max(int64_t(0), c_ext - c_blk - col_base)) : 0;
+    off[s] = (uint32_t)(8 * (row_local + (int64_t)col_base * args.ld));
     sg[s] = code_neg(c) ? -1.0 : 1.0;
   }
   double xs[NT][16];
@@ -103,7 +102,8 @@ __device__ __forceinline__ void cast_column(const CastArgs& args, const ProdDesc
 #pragma unroll
     for (int e = 0; e < 16; ++e)
       xs[s][e] = __builtin_bit_cast(
-          double, __builtin_amdgcn_raw_buffer_load_b64(rs[s], e < nrow[s] ? off[s] + 8 * e : kOOB, 0, 0));
+          double, __builtin_amdgcn_raw_buffer_load_b64(
+                      rs[s], e < ncol[s] ? off[s] + (uint32_t)(8 * e * args.ld) : kOOB, 0, 0));
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     double x[NT];
@@ -113,15 +113,19 @@ __device__ __forceinline__ void cast_column(const CastArgs& args, const ProdDesc
   }
 }
 
+// Workgroup b takes slot b % nslots of block position b / nslots (outer block fastest, then k
+// block): the slots of one block position run back to back, so the operand blocks they share
+// are read from HBM about once and then from L2.
 template <bool F64>
-__global__ __launch_bounds__(256) void cast_kernel(const CastArgs args) {
+__global__ __launch_bounds__(256) void cast_kernel(const CastArgs args, int nslots, int blocks_o) {
   __shared__ float tile[kCastT][kCastT + 1];
   const TableDev& tab = g_tables_bf16[args.tab];
-  const int slot = blockIdx.z;
+  const int slot = (int)(blockIdx.x % (unsigned)nslots);
+  const int pos = (int)(blockIdx.x / (unsigned)nslots);
   const ProdDesc& pd = tab.prod[slot];
   const int nt = args.side == 0 ? pd.na : pd.nb;
-  const int64_t o0 = (int64_t)blockIdx.x * kCastT;   // outer index (A: row, B: column)
-  const int64_t k0 = (int64_t)blockIdx.y * kCastT;
+  const int64_t o0 = (int64_t)(pos % blocks_o) * kCastT;   // outer index (A: row, B: column)
+  const int64_t k0 = (int64_t)(pos / blocks_o) * kCastT;
   const int t = threadIdx.x;
   const size_t slot_off = (size_t)slot * args.slot_stride;
   auto store16 = [&](int64_t o, int64_t kc, const float* v) {
@@ -145,22 +149,22 @@ __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args) {
       dl[1] = (u4_t){lw[4], lw[5], lw[6], lw[7]};
     }
   };
-  const int cl = t >> 2, rl = (t & 3) * 16;   // column within the block, first of 16 rows
+  const int rl = t & 63, cb = (t >> 6) * 16;   // row within the block, first of 16 columns
   float v[16];
-  if (nt == 1) cast_column<1, F64>(args, pd, o0, k0, cl, rl, v);
-  else if (nt == 2) cast_column<2, F64>(args, pd, o0, k0, cl, rl, v);
-  else cast_column<4, F64>(args, pd, o0, k0, cl, rl, v);
-  if (args.side == 1) {   // B: column cl is outer index o0 + cl, rows are k values k0 + rl..
-    store16(o0 + cl, k0 + rl, v);
+  if (nt == 1) cast_row<1, F64>(args, pd, o0, k0, rl, cb, v);
+  else if (nt == 2) cast_row<2, F64>(args, pd, o0, k0, rl, cb, v);
+  else cast_row<4, F64>(args, pd, o0, k0, rl, cb, v);
+  if (args.side == 0) {   // A: row rl is outer index o0 + rl, the columns are k values k0 + cb..
+    store16(o0 + rl, k0 + cb, v);
     return;
   }
-  // A: column cl is k value k0 + cl, rows are outer indices o0 + rl..; transpose through LDS
+  // B: row rl is k value k0 + rl, the columns are outer indices o0 + cb..; transpose via LDS
 #pragma unroll
-  for (int e = 0; e < 16; ++e) tile[cl][rl + e] = v[e];
+  for (int e = 0; e < 16; ++e) tile[cb + e][rl] = v[e];
   __syncthreads();
   const int oo = t >> 2, kc = (t & 3) * 16;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) v[e] = tile[kc + e][oo];
+  for (int e = 0; e < 16; ++e) v[e] = tile[oo][kc + e];
   store16(o0 + oo, k0 + kc, v);
 }
 
@@ -357,9 +361,13 @@ __global__ __launch_bounds__(256, WPC) void bf16_gemm_kernel(const Bf16Args args
 }  // namespace
 
 hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
-  const dim3 grid((unsigned)(a.outer_pad / kCastT), (unsigned)(a.kpad / kCastT), (unsigned)nslots);
-  if (a.sum_f64) hipLaunchKernelGGL(cast_kernel<true>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(cast_kernel<false>, grid, dim3(256), 0, s, a);
+  const int64_t blocks_o = a.outer_pad / kCastT, blocks_k = a.kpad / kCastT;
+  const int64_t grid = blocks_o * blocks_k * nslots;
+  if (nslots < 1 || grid >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  if (a.sum_f64)
+    hipLaunchKernelGGL(cast_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, a, nslots, (int)blocks_o);
+  else
+    hipLaunchKernelGGL(cast_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, a, nslots, (int)blocks_o);
   return hipGetLastError();
 }
 
