@@ -64,11 +64,12 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
-    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector"],
+    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
                         "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
                         "one persistent graph launch; selector: the committed network's choice "
-                        "against exhaustive timing on held-out shapes; each prints one JSON line")
+                        "against exhaustive timing on held-out shapes; sweep: every member on the "
+                        "square sizes 2048..16384 and the rank-k shapes; each prints one JSON line")
     p.add_argument("--shapes", type=int, default=200,
                    help="selector suite: held-out shapes timed exhaustively")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -392,6 +393,53 @@ def selector_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def sweep_suite(args):
+    """Every member (classical; one- and two-level ABC, AB, Naive) on the square sizes
+    m = n = k = 2048, 4096, ..., 16384 and the rank-k shapes m = n = 16384, k = 256 ... 8192,
+    entries uniform[-1, 1]: median of three event-timed calls each, effective TFLOPS and the
+    ratio to classical at the same shape."""
+    import torch
+    import paper_1605_01078_amd as sx
+    import workloads as W
+
+    stream = torch.cuda.current_stream()
+    shapes = [(s_, s_, s_) for s_ in range(2048, 16384 + 1, 2048)]
+    shapes += [(16384, 16384, k) for k in (256, 512, 1024, 2048, 4096, 8192)]
+    members = [(0, "abc")] + [(lv, v) for lv in (1, 2) for v in ("abc", "ab", "naive")]
+    rows = []
+    for m, n, k in shapes:
+        A = W.device_uniform(1, m, k)
+        B = W.device_uniform(2, k, n)
+        C = W.device_uniform(3, m, n)
+        row = {"m": m, "n": n, "k": k}
+        for lv, v in members:
+            f = lambda: sx.dgemm(A, B, C, 1.0, 1.0, lv, v, stream)
+            f()
+            ms, _ = timed(f, 3, stream)
+            row[f"L{lv}_{v}"] = round(ms, 3)
+        base = row["L0_abc"]
+        row["speedup"] = {key: round(base / t, 4) for key, t in row.items()
+                          if key.startswith("L") and key != "L0_abc"}
+        best = min((key for key in row if key.startswith("L")), key=lambda key: row[key])
+        row["best"] = best
+        log(f"  {m}x{n}x{k}: classical {base:.3f} ms, best {best} {row[best]:.3f} ms")
+        rows.append(row)
+        del A, B, C
+        sx.release_workspace()
+        torch.cuda.empty_cache()
+    sq = [r for r in rows if r["m"] == r["k"]]
+    top = max(sq, key=lambda r: r["m"])
+    out = {"metric": "effective TFLOPS (2mnk/t) of the fastest member at m=n=k=16384 over the sweep",
+           "value": round(2.0 * top["m"] ** 3 / (top[top["best"]] * 1e-3) * 1e-12, 3),
+           "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": top[top["best"]], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "FP64 Strassen sweep: square 2048..16384 step 2048 and rank-k "
+                                  "m=n=16384, k=256..8192; all members; entries uniform[-1,1]"},
+           "table_ms": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -414,6 +462,9 @@ def main():
         return
     if args.suite == "selector":
         selector_suite(args)
+        return
+    if args.suite == "sweep":
+        sweep_suite(args)
         return
     if args.copy_calibration:
         copy_calibration()
