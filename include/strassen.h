@@ -254,7 +254,8 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
  *   5: as 4, with the two-level outer operand sums staged wherever n % 4 == 0 (the workspace,
  *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise).
  * The default (-1) uses the all-products kernel wherever it applies and stages as described
- * at strassen_dgemm.
+ * at strassen_dgemm.  For strassen_gemm_ex, 0 / 1 force the BF16 product kernel's 128 x 128 /
+ * 128 x 64 workgroup tiles (default: 128 x 64 where 128 x 128 tiles would number fewer than 512).
  * Results do not depend on the configuration (bitwise).  The environment variable
  * STRASSEN_TILE_CFG sets the initial value.  Returns 0 or -1 (cfg out of range).
  */

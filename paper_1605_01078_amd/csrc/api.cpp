@@ -728,6 +728,14 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   g.tiles_n = (int32_t)(p.np / 128);
   g.x3 = p.x3;
   g.c_f64 = c_prec == STRASSEN_PREC_F64;
+  // 128 x 64 workgroup tiles where 128 x 128 ones would not give every CU two workgroups
+  // (tile configuration 0 / 1 force 128 x 128 / 128 x 64)
+  {
+    const int forced = g_forced_cfg.load(std::memory_order_relaxed);
+    const bool narrow = forced == kCfg64 || (forced != kCfg128 && (int64_t)g.tiles_m * g.tiles_n < 512);
+    g.bn = narrow ? 64 : 128;
+    if (narrow) g.tiles_n = (int32_t)(p.np / 64);
+  }
   SMX_LAUNCH(STRASSEN_KERNEL_BF16, stream, launch_bf16_gemm(g, stream));
   return 0;
 }

@@ -171,23 +171,28 @@ __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args, int nslo
 // ---------------------------------------------------------------------------------------------
 // BF16 product kernel.
 // ---------------------------------------------------------------------------------------------
-// Tiles: BM x BN = 128 x 128, 4 waves of 64 x 64 (4 x 4 blocks of 16 x 16 MFMA), k step BK
-// (bf16 elements).  Stage s holds the tiles of stream position s: A hi, B hi (, A lo, B lo),
-// each BM rows of BK values, 16-byte chunks XOR-swizzled by row pair.
-template <bool X3, int BK, int NS>
+// Tiles: BM x BN = 128 x BN (BN 128 or 64), 4 waves of 64 x BN/2 (4 x BN/32 blocks of 16 x 16
+// MFMA), k step BK (bf16 elements).  Stage s holds the tiles of stream position s: A hi, B hi
+// (, A lo, B lo), A tiles BM rows and B tiles BN rows of BK values, 16-byte chunks XOR-swizzled
+// by row pair.  The 128 x 64 form doubles the workgroups where 128 x 128 tiles would leave CUs
+// with one workgroup (the two-level products), at 1.5 times the LDS reads per MFMA.
+template <bool X3, int BK, int NS, int BN>
 struct Bf16Gemm {
-  static constexpr int BM = 128, BN = 128;
+  static constexpr int BM = 128;
   static constexpr int CPR = BK / 8;                  // 16-byte chunks per tile row
-  static constexpr int TILE_B = BM * BK * 2;          // bytes of one tile
-  static constexpr int NTL = X3 ? 4 : 2;              // tiles per stage
-  static constexpr int STAGE_B = NTL * TILE_B;
-  static constexpr int IPT = TILE_B / 1024;           // 64-lane x 16-byte loads per tile
-  static constexpr int LPW = IPT / 4;                 // loads per tile and wave
-  static constexpr int IPW = NTL * LPW;               // loads per wave and step
+  static constexpr int TILE_A = BM * BK * 2;          // bytes of one A tile
+  static constexpr int TILE_B = BN * BK * 2;          // bytes of one B tile
+  static constexpr int PAIR = TILE_A + TILE_B;         // one A and one B tile
+  static constexpr int STAGE_B = (X3 ? 2 : 1) * PAIR;
+  static constexpr int LPA = TILE_A / 4096;           // 64-lane x 16-byte loads per wave, A tile
+  static constexpr int LPB = TILE_B / 4096;           // B tile
+  static constexpr int IPW = (X3 ? 2 : 1) * (LPA + LPB);   // loads per wave and step
+  static constexpr int NFB = BN / 32;                 // 16-column blocks per wave
   static constexpr int KK = BK / 32;                  // MFMA k sub-steps per step
   static constexpr int LDS_B = NS * STAGE_B;
   static_assert(LDS_B <= 160 * 1024, "LDS");
   static_assert(BK == 32 || BK == 64, "k step");
+  static_assert((BN == 128 || BN == 64) && LPB >= 1, "tile columns");
 
   __device__ static void run(const Bf16Args& args, char* lds) {
     const TableDev& tab = g_tables_bf16[args.tab];
@@ -203,23 +208,25 @@ struct Bf16Gemm {
 
     // Lane byte offsets inside a product slot for load jj of a tile (part wave + 4 jj):
     // position p = 64 part + lane is row p / CPR, stored chunk p % CPR = logical chunk ^ swizzle.
-    uint32_t off_a[LPW], off_b[LPW];
-#pragma unroll
-    for (int jj = 0; jj < LPW; ++jj) {
+    auto lane_off = [&](int jj, int64_t rc0) {
       const int p = (wave + 4 * jj) * 64 + lane;
       const int row = p / CPR, pc = p % CPR, c = pc ^ ((row >> 1) & (CPR - 1));
-      off_a[jj] = (uint32_t)(2 * ((row0 + row) * args.kpad + c * 8));
-      off_b[jj] = (uint32_t)(2 * ((col0 + row) * args.kpad + c * 8));
-    }
+      return (uint32_t)(2 * ((rc0 + row) * args.kpad + c * 8));
+    };
+    uint32_t off_a[LPA], off_b[LPB];
+#pragma unroll
+    for (int jj = 0; jj < LPA; ++jj) off_a[jj] = lane_off(jj, row0);
+#pragma unroll
+    for (int jj = 0; jj < LPB; ++jj) off_b[jj] = lane_off(jj, col0);
     // the load stream: product ri, k step ki, and the slot bases of product ri (uniform)
     int ri = 0, ki = 0;
-    const uint16_t* base[NTL];
+    const uint16_t* base[4];   // A hi, B hi, A lo, B lo of product ri
     auto set_bases = [&](int r) {
       base[0] = args.TAh + (int64_t)r * args.stride_a;
       base[1] = args.TBh + (int64_t)r * args.stride_b;
       if (X3) {
-        base[NTL > 2 ? 2 : 0] = args.TAl + (int64_t)r * args.stride_a;
-        base[NTL > 2 ? 3 : 1] = args.TBl + (int64_t)r * args.stride_b;
+        base[2] = args.TAl + (int64_t)r * args.stride_a;
+        base[3] = args.TBl + (int64_t)r * args.stride_b;
       }
     };
     set_bases(0);
@@ -227,14 +234,19 @@ struct Bf16Gemm {
       const bool live = ri < nprod;
       const uint32_t kofs = (uint32_t)(2 * BK * ki);
       char* sb = lds + stage * STAGE_B;
-#pragma unroll
-      for (int j = 0; j < IPW; ++j) {
-        const int tl = j / LPW, jj = j % LPW;
+      auto load = [&](int tl, char* dst, uint32_t o) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<uint16_t*>(base[tl]), (short)0, 0x7fffffff, 0x00020000);
-        const uint32_t o = ((tl & 1) == 0 ? off_a[jj] : off_b[jj]) + kofs;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(sb + tl * TILE_B + (wave + 4 * jj) * 1024),
-                                                 16, live ? o : kOOB, 0, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)dst, 16, live ? o + kofs : kOOB, 0, 0, 0);
+      };
+#pragma unroll
+      for (int h = 0; h < (X3 ? 2 : 1); ++h) {   // hi tiles, then lo tiles
+#pragma unroll
+        for (int jj = 0; jj < LPA; ++jj)
+          load(2 * h, sb + h * PAIR + (wave + 4 * jj) * 1024, off_a[jj]);
+#pragma unroll
+        for (int jj = 0; jj < LPB; ++jj)
+          load(2 * h + 1, sb + h * PAIR + TILE_A + (wave + 4 * jj) * 1024, off_b[jj]);
       }
       if (++ki == nk) {
         ki = 0;
@@ -249,33 +261,35 @@ struct Bf16Gemm {
       return *reinterpret_cast<const bf8_t*>(tile + rr * (2 * BK) + pc * 16);
     };
 
-    f4_t acc[4][4];
+    f4_t acc[4][NFB];
     auto zero = [&]() {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (f4_t){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NFB; ++b) acc[a][b] = (f4_t){0.f, 0.f, 0.f, 0.f};
     };
     auto compute = [&](int stage) {
       const char* sb = lds + stage * STAGE_B;
-      bf8_t ah[KK][4], bh[KK][4], al[KK][4], bl[KK][4];
+      bf8_t ah[KK][4], bh[KK][NFB], al[KK][4], bl[KK][NFB];
 #pragma unroll
-      for (int kk = 0; kk < KK; ++kk)
+      for (int kk = 0; kk < KK; ++kk) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           ah[kk][f] = frag(sb, wm * 64 + 16 * f + li, 4 * kk + g);
-          bh[kk][f] = frag(sb + TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
-          if (X3) {
-            al[kk][f] = frag(sb + 2 * TILE_B, wm * 64 + 16 * f + li, 4 * kk + g);
-            bl[kk][f] = frag(sb + 3 * TILE_B, wn * 64 + 16 * f + li, 4 * kk + g);
-          }
+          if (X3) al[kk][f] = frag(sb + PAIR, wm * 64 + 16 * f + li, 4 * kk + g);
         }
+#pragma unroll
+        for (int f = 0; f < NFB; ++f) {
+          bh[kk][f] = frag(sb + TILE_A, wn * (BN / 2) + 16 * f + li, 4 * kk + g);
+          if (X3) bl[kk][f] = frag(sb + PAIR + TILE_A, wn * (BN / 2) + 16 * f + li, 4 * kk + g);
+        }
+      }
 #pragma unroll
       for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
         for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
-          for (int fn = 0; fn < 4; ++fn) {
+          for (int fn = 0; fn < NFB; ++fn) {
             acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kk][fm], bh[kk][fn], acc[fm][fn], 0, 0, 0);
             if (X3) {
               acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kk][fm], bl[kk][fn], acc[fm][fn], 0, 0, 0);
@@ -285,7 +299,7 @@ struct Bf16Gemm {
     };
 
     // Epilogue of product r: lane l, element e of block (fm, fn) is tile row
-    // 64 wm + 16 fm + 4 (l / 16) + e, column 64 wn + 16 fn + l % 16.
+    // 64 wm + 16 fm + 4 (l / 16) + e, column (BN / 2) wn + 16 fn + l % 16.
     auto epilogue = [&](int r) {
       const ProdDesc& pd = tab.prod[r];
       const int64_t ldc = args.ldc;
@@ -302,8 +316,8 @@ struct Bf16Gemm {
 #pragma unroll
         for (int fm = 0; fm < 4; ++fm) {
 #pragma unroll
-          for (int fn = 0; fn < 4; ++fn) {
-            const int cl = wn * 64 + 16 * fn + li;
+          for (int fn = 0; fn < NFB; ++fn) {
+            const int cl = wn * (BN / 2) + 16 * fn + li;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const int rl = wm * 64 + 16 * fm + 4 * g + e;
@@ -351,9 +365,9 @@ struct Bf16Gemm {
   }
 };
 
-template <bool X3, int BK, int NS, int WPC>
+template <bool X3, int BK, int NS, int WPC, int BN>
 __global__ __launch_bounds__(256, WPC) void bf16_gemm_kernel(const Bf16Args args) {
-  using K = Bf16Gemm<X3, BK, NS>;
+  using K = Bf16Gemm<X3, BK, NS, BN>;
   __shared__ __attribute__((aligned(16))) char lds[K::LDS_B];
   K::run(args, lds);
 }
@@ -373,9 +387,15 @@ hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
 
 hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(256);
-  // two workgroups per CU (64 KB of LDS each): one hides the other's LDS latency and barriers
-  if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2>), grid, block, 0, s, a);
+  // two workgroups per CU (at most 64 KB of LDS each): one hides the other's LDS latency and
+  // barriers
+  if (a.bn == 64) {
+    if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 64>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 64>), grid, block, 0, s, a);
+  } else {
+    if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

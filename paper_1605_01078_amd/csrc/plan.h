@@ -148,6 +148,8 @@ struct Bf16Args {
   int32_t tab, tiles_m, tiles_n;
   int32_t x3;                   // 1: bf16x3 (hi*hi + hi*lo + lo*hi)
   int32_t c_f64;                // 1: C update in FP64, 0: in FP32
+  int32_t bn;                   // workgroup tile columns: 128 or 64 (tiles_n counts these)
+  int32_t pad;
 };
 
 // Batched mode: one problem (its tile-kernel arguments and tile shape) and one work item.

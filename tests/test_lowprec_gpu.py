@@ -88,3 +88,24 @@ def test_two_level_operands_larger_than_2gib():
                        np.zeros((m, len(cols)), order="F"), 1.0, 0.0)
     got = C[:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
+def test_product_tile_widths_bitwise(levels, compute):
+    """128 x 128 and 128 x 64 workgroup tiles of the product kernel (tile configuration 0 / 1)
+    give the same bits: every C element sums the same k steps in the same order."""
+    m, n, k = 520, 650, 390
+    print(f"case tile widths L={levels} {compute}", flush=True)
+    A, B, C = W.problem(91, m, n, k, "uniform")
+    outs = []
+    try:
+        for cfg in (0, 1):
+            sx.set_tile_config(cfg)
+            dC = sx.to_device(C)
+            sx.gemm_ex(sx.to_device(A), sx.to_device(B), dC, 0.75, -0.5, levels, compute, "f64", "f32")
+            torch.cuda.synchronize()
+            outs.append(sx.to_host(dC))
+    finally:
+        sx.set_tile_config(-1)
+    assert np.array_equal(outs[0], outs[1])
