@@ -545,7 +545,7 @@ def main():
         f"(wall {wall:.2f} s)")
 
     # ---- classical and every variant (same inputs, outside the timed steps) --------------------
-    variants = {}
+    variants, vendor = {}, None
     if not args.no_compare:
         Cw = C0.clone()
         pairs = [(0, "abc")] + [(lv, v) for lv in (1, 2) for v in ("abc", "ab", "naive")]
@@ -569,6 +569,16 @@ def main():
         variants["L2_abc_unstaged"] = {"ms": round(ms, 3),
                                        "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
         log(f"  L=2 abc, outer sums in the load: {ms:8.3f} ms")
+        # context only: the vendor BLAS FP64 GEMM through torch (not this library's code)
+        Ac, Bc = A.contiguous(), B.contiguous()   # plain row-major operands (same values)
+        Cv = torch.empty(n, n, dtype=torch.float64, device=A.device)
+        f = lambda: torch.matmul(Ac, Bc, out=Cv)
+        f()
+        torch.cuda.synchronize()
+        ms, _ = timed(f, 3, stream)
+        vendor = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
+        log(f"  vendor BLAS FP64 GEMM (torch.matmul), context: {ms:8.3f} ms")
+        del Cv, Ac, Bc
         base = variants["L0_abc"]["tflops"]
         for key, v in variants.items():
             v["speedup_vs_classical"] = round(v["tflops"] / base, 4)
@@ -660,6 +670,7 @@ def main():
     if variants:
         out["classical_tflops"] = variants["L0_abc"]["tflops"]
         out["speedup_vs_classical"] = round(value / variants["L0_abc"]["tflops"], 4)
+        out["context_vendor_blas_fp64"] = dict(vendor, speedup_of_value=round(value / vendor["tflops"], 4))
     print(json.dumps(out), flush=True)
 
 
