@@ -164,15 +164,21 @@ class Trainer:
         return self.p.cpu().numpy()
 
 
-def train(X, y, epochs=300, batch=2048, lr=3e-3, seed=0, log=None):
-    """Minibatch Adam on (X, y) with the library's kernels; samples shuffled once per epoch on
-    the host (the device copy is reordered)."""
+def train(X, y, epochs=300, batch=2048, lr=3e-3, seed=0, log=None, weights=None):
+    """Minibatch Adam on (X, y) with the library's kernels.  Each epoch the host draws the
+    sample order (the device copy is reordered): a permutation, or with `weights` (e.g. each
+    shape's best time, so that the loss counts shapes as the regret does) a draw with
+    replacement proportional to them."""
     import torch
     g = np.random.default_rng(seed)
     tr = Trainer(X, y, init_params(seed))
     Xh, yh = np.asarray(X, dtype=np.float32), np.asarray(y, dtype=np.int32)
+    pw = None
+    if weights is not None:
+        pw = np.asarray(weights, dtype=np.float64)
+        pw = pw / pw.sum()
     for ep in range(epochs):
-        perm = g.permutation(len(yh))
+        perm = g.permutation(len(yh)) if pw is None else g.choice(len(yh), len(yh), p=pw)
         tr.X.copy_(torch.as_tensor(Xh[perm]))
         tr.y.copy_(torch.as_tensor(yh[perm]))
         rate = lr * (0.5 * (1 + math.cos(math.pi * ep / epochs)))
@@ -340,7 +346,8 @@ def main(argv=None):
     X = features(*np.array(shapes).T, dtypes)
     y = times.argmin(axis=1)
     n = a.train
-    params = train(X[:n], y[:n], epochs=a.epochs, log=say)
+    # shapes weighted by their best time: the regret is a ratio of summed times
+    params = train(X[:n], y[:n], epochs=a.epochs, log=say, weights=times[:n].min(axis=1))
     res_test = evaluate(params, shapes[n:], dtypes[n:], times[n:])
     res_train = evaluate(params, shapes[:n], dtypes[:n], times[:n])
     say(json.dumps({"held_out": res_test, "train": res_train}))
