@@ -333,6 +333,11 @@ def batched_suite(args):
                                   "[256, 4096], entries uniform[-1,1], autotuned level and tile "
                                   "per problem, one hipGraph replay", "problems": len(shapes),
                       "total_flops": flops},
+           "roofline": {"bound": "mfma", "achieved": tf(ms_graph), "peak": PEAK_F64_MFMA,
+                        "unit": "TFLOP/s", "frac": round(tf(ms_graph) / PEAK_F64_MFMA, 4),
+                        "traffic": None, "kernel": "batched_kernel (persistent)",
+                        "achieved_note": "all 512 problems' 2mnk flops (classical choices: "
+                                         "executed = effective) over the graph replay"},
            "choices": hist, "autotune_seconds": round(tune_s, 2),
            "compare": {"graph_replay_ms": round(ms_graph, 3), "eager_run_ms": round(ms_eager, 3),
                        "batched_all_classical_ms": round(ms_classical, 3),
