@@ -132,8 +132,10 @@ struct AllProducts {
       const bool b_k_ok = kb + 2 * b_c < kq;
 #pragma unroll
       for (int j = 0; j < IPW; ++j) {
-        const int u = wave + 8 * j;
-        const int t = u / IPT;
+        // Tile of load u = wave + 8 j.  With one term per side every tile's block offsets are
+        // then compile-time indices into the arguments, loaded once instead of in every step
+        // (with two terms the extra registers this takes cost more than the loads).
+        const int t = (NA == 1 && NB == 1) ? (8 * j) / IPT + (wave & 7) / IPT : (wave + 8 * j) / IPT;
         double* dst = sbase + t * TILE_D + v * 128;
         if (8 * j < 4 * NA * IPT) {           // an A tile (compile-time split, see static_assert)
           dma16(make_rsrc(a_tile(t >> 2, t & 3) + kb * lda), dst,
@@ -241,17 +243,35 @@ struct AllProducts {
       }
       __builtin_amdgcn_sched_group_barrier(0x008, 28 - kReads, 0);
     };
+    // Second half of a k step: the LDS reads of the next group among the first MFMAs, the DMA
+    // of the step after next spread over the later ones, so that waves leaving the barrier
+    // together keep MFMAs queued while they issue it.
+    auto interleave_dma = [&]() {
+#pragma unroll
+      for (int i = 0; i < 28; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        if (i < kReads) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+        if (i >= 6 && (i - 6) % 2 == 0 && (i - 6) / 2 < IPW)
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // one DMA
+      }
+    };
+    // End of a stage: this wave's DMA of the step to be read next has landed (the NS - 2 newest
+    // batches may still fly) and its LDS reads are done; then the barrier.  The waits are
+    // explicit because a workgroup fence (as in __syncthreads) would also wait for every DMA in
+    // flight, which serialises the deeper pipelines.
     auto sync_stage = [&]() {
-      if (NS == 2) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(%0)" ::"n"(IPW * (NS - 2)) : "memory");
-      __syncthreads();
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(IPW * (NS - 2)) : "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
     };
     Frag f0, f1;
     if (NPAIR == 2) {
       // Two groups per stage, two stages.  Iteration kt: read group 1 of step kt during the
       // MFMAs of group 0; the barrier then has step kt + 1 landed and every read of step kt
       // done, so the DMA of step kt + 2 goes into its stage; read group 0 of step kt + 1
-      // during the MFMAs of group 1.  Each DMA has one full step to land.
+      // during the MFMAs of group 1.  Each DMA has one full step to land.  (The reads come
+      // before the DMA in program order: the compiler cannot tell the stages apart and keeps
+      // LDS reads after an earlier DMA into LDS.)
       issue_loads(0, 0);
       issue_loads(1, 1);
       sync_stage();
@@ -262,10 +282,10 @@ struct AllProducts {
         mfma_frag(f0);
         interleave();
         sync_stage();
-        issue_loads(cur, kt + 2);
         load_frag(cur ^ 1, 0, f0);
+        issue_loads(cur, kt + 2);
         mfma_frag(f1);
-        interleave();
+        interleave_dma();
       }
     } else {
       // One group per stage, NS stages; step kt lives in stage kt % NS.  Iteration kt issues
