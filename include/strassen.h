@@ -158,19 +158,25 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
  * Batched mode — many independent FP64 GEMMs  C_p := alpha*A_p*B_p + beta*C_p  (p < count) in
  * one persistent kernel launch.  The paper chooses "the right member of the family" per problem
  * size (Sec. 5); here every problem gets its own Strassen level (0, 1, 2; the ABC variant) and
- * tile shape (0: 128 x 128, 1: 64 x 64).  A work item is one tile position of one problem, on
- * which one workgroup runs all the problem's products; items are handed out longest first
- * through a device counter.  Per problem the result is bitwise that of strassen_dgemm with the
- * same level and tile shape (strassen_set_tile_config 0 / 1).
+ * tile choice (0: 128 x 128, 1: 64 x 64 in the persistent kernel; 2: the problem runs as its own
+ * all-products launch(es), one at one level, seven at two with the outer sums in the load,
+ * after the persistent kernel, where that kernel's layout applies (strassen_dgemm's conditions),
+ * else in the persistent kernel with the tiles a single call would use).  A work item of the
+ * persistent kernel is one tile position of one problem, on which one workgroup runs all the
+ * problem's products; items are handed out longest first through a device counter.  Per problem
+ * the result is bitwise that of strassen_dgemm with the same level (every FP64 kernel rounds the
+ * same operations in the same order).
  *
  * strassen_batched_plan(count, m, n, k, levels, cfg, plan): problem sizes (host arrays of
  *   `count`).  levels / cfg (host, may be NULL = all -1): -1 lets the library choose by its rule
- *   (level from min(m, n, k) thresholds, 64 x 64 tiles when the 128 x 128 grid of a sub-block is
- *   small); the chosen values are written back.  *plan receives an opaque handle (host memory).
+ *   (level from min(m, n, k) thresholds; one-level problems above a size threshold as their own
+ *   all-products launch, else 64 x 64 tiles when the 128 x 128 grid of a sub-block is small);
+ *   the chosen values are written back.  *plan receives an opaque handle (host memory).
  *   Returns 0, -1 count < 0, -2 NULL or negative sizes, -5 / -6 a level / cfg out of range,
  *   -7 plan NULL.  Needs no device.
- * strassen_batched_autotune(plan, sample, seed, stream): times the persistent kernel on `sample`
- *   problems of the plan (seeded choice; 0 = all) under candidate rule thresholds, on zeroed
+ * strassen_batched_autotune(plan, sample, seed, stream): times the batch (persistent kernel and
+ *   all-products launches) on `sample` problems of the plan (seeded choice; 0 = all) under
+ *   candidate rule thresholds, on zeroed
  *   library-owned buffers of the same shapes, and re-chooses every -1 entry with the fastest
  *   rule.  Synchronises `stream`.  Returns 0, -1, -2, or a positive error.
  * strassen_batched_choice(plan, i, level, cfg): the current choice for problem i.
@@ -181,7 +187,8 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
  *   scale C.  Returns 0, -1 plan NULL, -2 NULL arrays, -3 a bad problem (message names it), or
  *   a positive error.
  * strassen_batched_capture(...same arguments...): prepares the work list for these operands
- *   and records the launch (counter clear + persistent kernel) as a HIP graph in the plan,
+ *   and records the launches (counter clear, persistent kernel, then the all-products launches
+ *   in problem order) as a HIP graph in the plan,
  *   without running it.  alpha == 0 / k == 0 problems are refused (STRASSEN_ERR_UNSUPPORTED).
  * strassen_batched_replay(plan, stream): launches the recorded graph on `stream`; every replay
  *   recomputes C from the operands recorded at capture.  A later run or capture on the plan

@@ -298,7 +298,8 @@ class Batched:
     """A batch of independent FP64 GEMMs run by one persistent kernel (see strassen.h).
 
     shapes: list of (m, n, k); levels / cfg: per-problem lists with -1 = library choice
-    (None = all -1)."""
+    (None = all -1); cfg 0 / 1: 128 x 128 / 64 x 64 tiles of the persistent kernel, 2: the
+    problem's own all-products launch(es)."""
 
     def __init__(self, shapes, levels=None, cfg=None):
         self.count = len(shapes)

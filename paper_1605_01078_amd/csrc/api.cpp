@@ -332,12 +332,13 @@ static bool user_workspace_below(size_t bytes) {
   return g_user_ws != nullptr && g_user_ws_bytes < bytes;
 }
 
-// ABC through the all-products kernel: one launch at one level, seven (one per outer product
-// of the one-level table, in order) at two; `stage` (two levels only, may be null) holds the
-// staged outer sums.
-static int run_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
-                            int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
-                            double beta, double* stage, hipStream_t stream) {
+// The all-products launches of ABC: one at one level; at two, one per outer product of the
+// one-level table, in order.  `stage` (two levels only, may be null) holds the staged outer
+// sums as laid out by make_stage_plan.
+static int build_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
+                              int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
+                              double beta, const double* stage, std::vector<ApLaunch>* out) {
+  out->clear();
   FusedArgs f;
   std::memset(&f, 0, sizeof f);
   f.A = A;
@@ -360,7 +361,7 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
     f.nc = 1;
     f.c_first = 1;
     f.a_sg[0] = f.b_sg[0] = f.c_sg[0] = 1.0;
-    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, 1, 1, stream));
+    out->push_back({f, 1, 1});
     return 0;
   }
   // two levels: outer blocks are 2 x 2 inner sub-blocks
@@ -371,30 +372,7 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
     if (kOneLevel[R].a[0].sign != 1 || kOneLevel[R].b[0].sign != 1)
       return fail(STRASSEN_ERR_UNSUPPORTED, "outer product %d: first term negative", R);
   StagePlan sp;
-  if (stage) {
-    sp = make_stage_plan(p);
-    OuterSumArgs oa, ob;
-    std::memset(&oa, 0, sizeof oa);
-    std::memset(&ob, 0, sizeof ob);
-    oa.src = A;
-    oa.dst = stage;
-    oa.ld = lda;
-    oa.rows = om;
-    oa.cols = ok;
-    oa.dst_stride = sp.ta_stride;
-    ob.src = B;
-    ob.dst = stage + sp.na_slots * sp.ta_stride;
-    ob.ld = ldb;
-    ob.rows = ok;
-    ob.cols = on;
-    ob.dst_stride = sp.tb_stride;
-    for (int q = 0; q < 4; ++q) {
-      oa.blk[q] = a_block(q);
-      ob.blk[q] = b_block(q);
-    }
-    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
-    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
-  }
+  if (stage) sp = make_stage_plan(p);
   bool touched[4] = {false, false, false, false};
   for (int R = 0; R < 7; ++R) {
     const QProduct& P = kOneLevel[R];
@@ -440,9 +418,62 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
       if (!touched[q]) f.c_first |= 1 << d;
       touched[q] = true;
     }
-    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, na, nb, stream));
+    out->push_back({f, na, nb});
   }
   return 0;
+}
+
+// ABC through the all-products kernel; at two levels with `stage` (may be null) the outer
+// operand sums are first formed into it by two streaming launches.
+static int run_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
+                            double beta, double* stage, hipStream_t stream) {
+  std::vector<ApLaunch> launches;
+  if (int rc = build_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta,
+                                  p.levels == 2 ? stage : nullptr, &launches))
+    return rc;
+  if (p.levels == 2 && stage) {
+    const StagePlan sp = make_stage_plan(p);
+    const int64_t om = 2 * p.mq, on = 2 * p.nq, ok = 2 * p.kq;
+    OuterSumArgs oa, ob;
+    std::memset(&oa, 0, sizeof oa);
+    std::memset(&ob, 0, sizeof ob);
+    oa.src = A;
+    oa.dst = stage;
+    oa.ld = lda;
+    oa.rows = om;
+    oa.cols = ok;
+    oa.dst_stride = sp.ta_stride;
+    ob.src = B;
+    ob.dst = stage + sp.na_slots * sp.ta_stride;
+    ob.ld = ldb;
+    ob.rows = ok;
+    ob.cols = on;
+    ob.dst_stride = sp.tb_stride;
+    for (int q = 0; q < 4; ++q) {
+      oa.blk[q] = (q >> 1) * om + (q & 1) * ok * lda;
+      ob.blk[q] = (q >> 1) * ok + (q & 1) * on * ldb;
+    }
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
+  }
+  for (const ApLaunch& l : launches)
+    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(l.f, l.na, l.nb, stream));
+  return 0;
+}
+
+bool all_products_ok(int64_t m, int64_t k, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, const double* C, int64_t ldc, int levels) {
+  return all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels);
+}
+
+int all_products_plan(int64_t m, int64_t n, int64_t k, int levels, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
+                      double beta, std::vector<ApLaunch>* out) {
+  if (!all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "all-products layout does not apply");
+  return build_all_products(make_plan(m, n, k, levels, STRASSEN_ABC), A, lda, B, ldb, C, ldc, n,
+                            alpha, beta, nullptr, out);
 }
 
 static int validate(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,

@@ -3,10 +3,12 @@
 //
 // Every problem gets a Strassen level and a tile shape.  Entries given as -1 follow a rule,
 //   level = 2 if min(m, n, k) >= t2, else 1 if min(m, n, k) >= t1, else 0;
-//   tile  = 64 x 64 if the 128 x 128 grid of one sub-block has fewer than `small` tiles,
+//   tile  = its own all-products launch (one level, min(m, n, k) >= t_ap), else
+//           64 x 64 if the 128 x 128 grid of one sub-block has fewer than `small` tiles,
 //           else 128 x 128;
-// whose thresholds the autotuner picks by timing the persistent kernel itself on a sample of
-// the batch (the quantity that matters is the batch's time, not one problem's latency).
+// whose thresholds the autotuner picks by timing the batch itself (persistent kernel and
+// all-products launches) on a sample of its problems: the quantity that matters is the batch's
+// time, not one problem's latency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,7 +29,10 @@ struct Rule {
   int64_t t1 = std::numeric_limits<int64_t>::max();   // min dimension for one level
   int64_t t2 = std::numeric_limits<int64_t>::max();   // for two levels
   int64_t small = 0;                                  // 128-tile count below which tiles are 64
+  int64_t t_ap = std::numeric_limits<int64_t>::max(); // min dimension for an all-products launch
 };
+
+constexpr int kBatchAllProducts = 2;   // problem tile choice: its own all-products launch(es)
 
 struct BatchedPlan {
   int count = 0;
@@ -42,6 +47,7 @@ struct BatchedPlan {
   unsigned* d_counter = nullptr;
   size_t cap_probs = 0, cap_items = 0;
   int n_items = 0;
+  std::vector<ApLaunch> ap;   // all-products launches of the problems that have them, in order
   bool vec = true;
   int grid = 0;
   hipGraph_t graph = nullptr;
@@ -55,7 +61,7 @@ static void apply_rule(const Rule& r, int64_t m, int64_t n, int64_t k, int* leve
   if (set_cfg) {
     const int64_t q = int64_t(1) << *level;
     const int64_t tiles128 = cdiv(cdiv(m, q), 128) * cdiv(cdiv(n, q), 128);
-    *cfg = tiles128 < r.small ? 1 : 0;
+    *cfg = *level == 1 && mn >= r.t_ap ? kBatchAllProducts : (tiles128 < r.small ? 1 : 0);
   }
 }
 
@@ -77,15 +83,17 @@ static void free_device(BatchedPlan* p) {
   p->cap_probs = p->cap_items = 0;
 }
 
-// Problems (GemmArgs per problem) and the cost-ordered work list for the given operands.
+// Problems (GemmArgs per problem) and the cost-ordered work list of the persistent kernel for
+// the given operands, and the all-products launches of the problems that run on their own.
 static int build_work(const BatchedPlan& p, const double* const* A, const int64_t* lda,
                       const double* const* B, const int64_t* ldb, double* const* C,
                       const int64_t* ldc, double alpha, double beta,
                       std::vector<BatchProblem>* probs, std::vector<BatchItem>* items,
-                      bool* vec) {
+                      std::vector<ApLaunch>* ap, bool* vec) {
   const TableDev* tabs = host_tables();
   probs->clear();
   items->clear();
+  ap->clear();
   *vec = true;
   std::vector<double> cost;
   for (int i = 0; i < p.count; ++i) {
@@ -93,6 +101,19 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
     if (m == 0 || n == 0 || k == 0 || alpha == 0.0) continue;   // handled by the caller
     const int L = p.level[i];
     const int64_t q = int64_t(1) << L;
+    int cfg = p.cfg[i];
+    if (cfg == kBatchAllProducts) {
+      if (all_products_ok(m, k, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], L)) {
+        std::vector<ApLaunch> mine;
+        if (int rc = all_products_plan(m, n, k, L, A[i], lda[i], B[i], ldb[i], C[i], ldc[i],
+                                       alpha, beta, &mine))
+          return rc;
+        ap->insert(ap->end(), mine.begin(), mine.end());
+        continue;
+      }
+      // layout does not apply: the persistent kernel, tiles as a single call would pick them
+      cfg = cdiv(cdiv(m, q), 128) * cdiv(cdiv(n, q), 128) < 512 ? 1 : 0;
+    }
     BatchProblem bp;
     std::memset(&bp, 0, sizeof bp);
     GemmArgs& g = bp.g;
@@ -112,7 +133,7 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
     g.beta = beta;
     g.tab = table_id(L, false);
     g.mode = kModeABC;
-    bp.cfg = p.cfg[i];
+    bp.cfg = cfg;
     const int64_t bm = bp.cfg == 0 ? 128 : 64;
     g.tiles_m = (int32_t)cdiv(g.mq, bm);
     g.tiles_n = (int32_t)cdiv(g.nq, bm);
@@ -211,6 +232,21 @@ static int scale_only(const BatchedPlan& p, double* const* C, const int64_t* ldc
   return 0;
 }
 
+// The batch's launches for the uploaded work: the persistent kernel over the items (after its
+// counter clear), then the all-products launches in problem order.
+static hipError_t launch_work(const BatchedPlan& p, hipStream_t s) {
+  if (p.n_items > 0) {
+    const hipError_t e =
+        launch_batched(p.d_probs, p.d_items, p.n_items, p.d_counter, p.vec, p.grid, s);
+    if (e != hipSuccess) return e;
+  }
+  for (const ApLaunch& l : p.ap) {
+    const hipError_t e = launch_all_products(l.f, l.na, l.nb, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 static int run_plan(BatchedPlan* p, const double* const* A, const int64_t* lda,
                     const double* const* B, const int64_t* ldb, double* const* C,
                     const int64_t* ldc, double alpha, double beta, hipStream_t s) {
@@ -219,14 +255,16 @@ static int run_plan(BatchedPlan* p, const double* const* A, const int64_t* lda,
   if (int rc = device_ready(&dev)) return rc;
   std::vector<BatchProblem> probs;
   std::vector<BatchItem> items;
+  std::vector<ApLaunch> ap;
   bool vec = true;
-  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &vec)) return rc;
+  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &ap, &vec))
+    return rc;
   if (int rc = scale_only(*p, C, ldc, alpha, beta, s)) return rc;
   drop_graph(p);   // the buffers a recorded graph reads are about to change
   if (int rc = upload(p, probs, items, s)) return rc;
   p->vec = vec;
-  if (p->n_items == 0) return 0;
-  SMX_HIP(launch_batched(p->d_probs, p->d_items, p->n_items, p->d_counter, vec, p->grid, s));
+  p->ap = std::move(ap);
+  SMX_HIP(launch_work(*p, s));
   return 0;
 }
 
@@ -282,42 +320,57 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
   const int64_t t1s[] = {inf, 3072, 2048, 1536, 1024};
   const int64_t t2s[] = {inf, 4096, 3072, 2048};
   const int64_t smalls[] = {0, 4, 16};
+  const int64_t t_aps[] = {3072, 2048, 1536, 1024};
   Rule best = p->rule;
   float best_ms = std::numeric_limits<float>::max();
   int rc = 0;
-  for (int64_t t1 : t1s) {
+  auto try_rule = [&](const Rule& r) {
+    if (e != hipSuccess || rc != 0) return;
+    for (int i = 0; i < sp.count; ++i)
+      apply_rule(r, sp.m[i], sp.n[i], sp.k[i], &sp.level[i], &sp.cfg[i], true, true);
+    // one warm call, then the median of three timed calls
+    float ts[3];
+    rc = run_plan(&sp, A.data(), lda.data(), B.data(), ldb.data(), C.data(), ldc.data(), 1.0, 0.0,
+                  s);
+    for (int rep = 0; rep < 3 && rc == 0 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = launch_work(sp, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ts[rep], e0, e1);
+    }
+    if (rc != 0 || e != hipSuccess) return;
+    std::sort(ts, ts + 3);
+    if (ts[1] < best_ms) {
+      best_ms = ts[1];
+      best = r;
+    }
+  };
+  // the persistent kernel alone: level thresholds and tile shapes
+  for (int64_t t1 : t1s)
     for (int64_t t2 : t2s) {
       if (t2 != inf && t2 <= t1 && t1 != inf) continue;
       if (t1 == inf && t2 != inf) continue;
       for (int64_t sm : smalls) {
-        if (e != hipSuccess || rc != 0) break;
         Rule r;
         r.t1 = t1;
         r.t2 = t2;
         r.small = sm;
-        for (int i = 0; i < sp.count; ++i)
-          apply_rule(r, sp.m[i], sp.n[i], sp.k[i], &sp.level[i], &sp.cfg[i], true, true);
-        // one warm call, then the median of three timed calls
-        float ts[3];
-        rc = run_plan(&sp, A.data(), lda.data(), B.data(), ldb.data(), C.data(), ldc.data(), 1.0,
-                      0.0, s);
-        for (int rep = 0; rep < 3 && rc == 0 && e == hipSuccess; ++rep) {
-          e = hipEventRecord(e0, s);
-          if (e == hipSuccess && sp.n_items > 0)
-            e = launch_batched(sp.d_probs, sp.d_items, sp.n_items, sp.d_counter, sp.vec, sp.grid, s);
-          if (e == hipSuccess) e = hipEventRecord(e1, s);
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          if (e == hipSuccess) e = hipEventElapsedTime(&ts[rep], e0, e1);
-        }
-        if (rc != 0 || e != hipSuccess) break;
-        std::sort(ts, ts + 3);
-        if (ts[1] < best_ms) {
-          best_ms = ts[1];
-          best = r;
-        }
+        try_rule(r);
       }
     }
-  }
+  // then one-level problems from t_ap up as their own all-products launches, with the best
+  // two-level threshold and tile rule kept
+  const Rule base = best;
+  for (int64_t t1 : t1s)
+    for (int64_t ta : t_aps) {
+      if (t1 == inf || ta < t1) continue;
+      if (base.t2 != inf && base.t2 <= t1) continue;
+      Rule r = base;
+      r.t1 = t1;
+      r.t_ap = ta;
+      try_rule(r);
+    }
   free_device(&sp);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -348,13 +401,16 @@ static int capture(BatchedPlan* p, const double* const* A, const int64_t* lda,
                   "batched capture: alpha == 0 or k == 0 (problem %d) is only run eagerly", i);
   std::vector<BatchProblem> probs;
   std::vector<BatchItem> items;
+  std::vector<ApLaunch> ap;
   bool vec = true;
-  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &vec)) return rc;
+  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &ap, &vec))
+    return rc;
   drop_graph(p);
   if (int rc = upload(p, probs, items, s)) return rc;
   p->vec = vec;
+  p->ap = std::move(ap);
   SMX_HIP(hipGraphCreate(&p->graph, 0));
-  hipGraphNode_t clear_node, run_node;
+  hipGraphNode_t clear_node = nullptr, run_node = nullptr;
   void* clear_args[] = {&p->d_counter};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof kp);
@@ -372,6 +428,21 @@ static int capture(BatchedPlan* p, const double* const* A, const int64_t* lda,
     rp.blockDim = dim3(256);
     rp.kernelParams = run_args;
     SMX_HIP(hipGraphAddKernelNode(&run_node, p->graph, &clear_node, 1, &rp));
+  }
+  // the all-products launches, chained after the persistent kernel (the eager order)
+  hipGraphNode_t prev = p->n_items > 0 ? run_node : clear_node;
+  for (ApLaunch& l : p->ap) {
+    void* ap_args[] = {&l.f};
+    hipKernelNodeParams ak;
+    std::memset(&ak, 0, sizeof ak);
+    ak.func = const_cast<void*>(all_products_fn(l.f, l.na, l.nb));
+    if (!ak.func) return fail(STRASSEN_ERR_UNSUPPORTED, "batched capture: no all-products kernel");
+    ak.gridDim = dim3((unsigned)((int64_t)l.f.tiles_m * l.f.tiles_n));
+    ak.blockDim = dim3(512);
+    ak.kernelParams = ap_args;
+    hipGraphNode_t node;
+    SMX_HIP(hipGraphAddKernelNode(&node, p->graph, &prev, 1, &ak));
+    prev = node;
   }
   SMX_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
   return 0;
@@ -396,7 +467,8 @@ int strassen_batched_plan(int count, const int64_t* m, const int64_t* n, const i
     if (levels[i] < -1 || levels[i] > smx::kMaxLevels)
       return smx::fail(-5, "problem %d: level %d not in -1..%d", i, levels[i], smx::kMaxLevels);
   for (int i = 0; cfg && i < count; ++i)
-    if (cfg[i] < -1 || cfg[i] > 1) return smx::fail(-6, "problem %d: tile %d not in -1..1", i, cfg[i]);
+    if (cfg[i] < -1 || cfg[i] > smx::kBatchAllProducts)
+      return smx::fail(-6, "problem %d: tile %d not in -1..%d", i, cfg[i], smx::kBatchAllProducts);
   auto* p = new smx::BatchedPlan;
   p->count = count;
   p->m.assign(m, m + count);

@@ -370,27 +370,27 @@ __global__ __launch_bounds__(512, 1) void all_products_kernel(const FusedArgs ar
 
 }  // namespace
 
-hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s) {
-  const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(512);
+const void* all_products_fn(const FusedArgs& a, int na, int nb) {
   // whole tiles: sub-block extents multiples of 64 (m, n) and of the k step, and the B columns
   // of the highest column block used present
   int64_t cb_max = 0;
   for (int t = 0; t < nb; ++t) cb_max = cb_max > a.b_cb[t] ? cb_max : a.b_cb[t];
   const bool full = a.mq % 64 == 0 && a.nq % 64 == 0 && a.kq % 16 == 0 && (cb_max + 2) * a.nq <= a.n;
-  if (na == 1 && nb == 1 && full)
-    hipLaunchKernelGGL((all_products_kernel<1, 1, 16, 2, true>), grid, block, 0, s, a);
-  else if (na == 1 && nb == 1)
-    hipLaunchKernelGGL((all_products_kernel<1, 1, 16, 2, false>), grid, block, 0, s, a);
+  if (na == 1 && nb == 1 && full) return (const void*)all_products_kernel<1, 1, 16, 2, true>;
+  if (na == 1 && nb == 1) return (const void*)all_products_kernel<1, 1, 16, 2, false>;
   // (the whole-tile form of the two-level kernels measured slower: they keep the masked loads)
-  else if (na == 2 && nb == 2)
-    hipLaunchKernelGGL((all_products_kernel<2, 2, 8, 2, false>), grid, block, 0, s, a);
-  else if (na == 2 && nb == 1)
-    hipLaunchKernelGGL((all_products_kernel<2, 1, 8, 3, false>), grid, block, 0, s, a);
-  else if (na == 1 && nb == 2)
-    hipLaunchKernelGGL((all_products_kernel<1, 2, 8, 3, false>), grid, block, 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (na == 2 && nb == 2) return (const void*)all_products_kernel<2, 2, 8, 2, false>;
+  if (na == 2 && nb == 1) return (const void*)all_products_kernel<2, 1, 8, 3, false>;
+  if (na == 1 && nb == 2) return (const void*)all_products_kernel<1, 2, 8, 3, false>;
+  return nullptr;
+}
+
+hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s) {
+  const void* fn = all_products_fn(a, na, nb);
+  if (!fn) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(512);
+  void* args[] = {const_cast<FusedArgs*>(&a)};
+  return hipLaunchKernel(fn, grid, block, args, 0, s);
 }
 
 }  // namespace smx

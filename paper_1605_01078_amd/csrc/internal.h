@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "plan.h"
 
@@ -23,6 +24,20 @@ void clear_error();
 const TableDev* host_tables();
 // Current device checked (gfx950) and its constant tables uploaded; returns 0 or an error code.
 int device_ready(int* dev_out);
+
+// One launch of the all-products kernel (operand terms per side: na, nb).
+struct ApLaunch {
+  FusedArgs f;
+  int na, nb;
+};
+// Whether ABC at `levels` can run on the all-products kernel for these operands, and its
+// launches with the outer sums formed in the load (one at one level, seven at two; stream order
+// gives every C element its updates in product order).  Returns 0 or an error code.
+bool all_products_ok(int64_t m, int64_t k, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, const double* C, int64_t ldc, int levels);
+int all_products_plan(int64_t m, int64_t n, int64_t k, int levels, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* C, int64_t ldc, double alpha,
+                      double beta, std::vector<ApLaunch>* out);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }

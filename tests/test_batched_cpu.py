@@ -38,8 +38,14 @@ def test_plan_argument_errors():
     assert L.strassen_batched_plan(2, None, n, k, None, None, ctypes.byref(plan)) == -2
     assert L.strassen_batched_plan(2, i64(4, -1), n, k, None, None, ctypes.byref(plan)) == -2
     assert L.strassen_batched_plan(2, m, n, k, ci(0, 3), None, ctypes.byref(plan)) == -5
-    assert L.strassen_batched_plan(2, m, n, k, None, ci(2, 0), ctypes.byref(plan)) == -6
+    assert L.strassen_batched_plan(2, m, n, k, None, ci(3, 0), ctypes.byref(plan)) == -6
+    assert L.strassen_batched_plan(2, m, n, k, None, ci(0, -2), ctypes.byref(plan)) == -6
     assert L.strassen_batched_plan(2, m, n, k, None, None, None) == -7
+    assert L.strassen_batched_plan(2, m, n, k, ci(1, 0), ci(2, 2), ctypes.byref(plan)) == 0
+    lv, cf = ctypes.c_int(), ctypes.c_int()
+    assert L.strassen_batched_choice(plan, 0, ctypes.byref(lv), ctypes.byref(cf)) == 0
+    assert (lv.value, cf.value) == (1, 2)
+    assert L.strassen_batched_destroy(plan) == 0
     assert L.strassen_batched_plan(2, m, n, k, None, None, ctypes.byref(plan)) == 0
     lv, cf = ctypes.c_int(), ctypes.c_int()
     assert L.strassen_batched_choice(plan, 2, ctypes.byref(lv), ctypes.byref(cf)) == -2

@@ -1,6 +1,7 @@
-"""Batched mode on the GPU: every problem of a persistent-kernel launch equals (bitwise) the
-single call with the same level and tile shape; graph replays equal the eager run; the
-autotuner's choices are valid and run correctly; scale-only problems."""
+"""Batched mode on the GPU: every problem of a batch (persistent-kernel tiles or its own
+all-products launches) equals (bitwise) the single call with the same level and tile choice;
+graph replays equal the eager run; the autotuner's choices are valid and run correctly;
+scale-only problems."""
 import numpy as np
 import pytest
 
@@ -22,7 +23,7 @@ def _mixed_batch(seed, count):
         m, n, k = (int(64 * g.integers(1, 11)) for _ in range(3))
         shapes.append((m, n, k))
         levels.append(int(g.integers(0, 3)))
-        cfg.append(int(g.integers(0, 2)))
+        cfg.append(int(g.integers(0, 3)))
     # ragged problems (odd sizes: the general load path)
     shapes += [(130, 70, 200), (301, 259, 271)]
     levels += [2, 1]
@@ -39,7 +40,8 @@ def _operands(shapes, seed):
 
 
 def _single(A, B, C, alpha, beta, level, cfg):
-    sx.set_tile_config(cfg)
+    # batched tile choice 2 (own all-products launches) = tile configuration 4 of a single call
+    sx.set_tile_config(4 if cfg == 2 else cfg)
     try:
         dC = sx.to_device(C)
         sx.dgemm(sx.to_device(A), sx.to_device(B), dC, alpha, beta, level, "abc")
@@ -107,7 +109,8 @@ def test_batched_autotune():
     b = sx.Batched(shapes)
     b.autotune(sample=0, seed=3)
     ch = b.choices()
-    assert all(lv in (0, 1, 2) and cf in (0, 1) for lv, cf in ch)
+    assert all(lv in (0, 1, 2) and cf in (0, 1, 2) for lv, cf in ch)
+    assert all(cf != 2 or lv == 1 for lv, cf in ch)     # the rule gives own launches to L1 only
     dA = [sx.to_device(A) for A, _, _ in ops]
     dB = [sx.to_device(B) for _, B, _ in ops]
     dC = [sx.to_device(C) for _, _, C in ops]
@@ -133,4 +136,40 @@ def test_batched_scale_only():
         assert np.array_equal(sx.to_host(dC[i]), 0.5 * C)
     with pytest.raises(sx.StrassenError):
         b.capture(dA, dB, dC, 0.0, 0.5)
+    b.close()
+
+
+def test_batched_all_products_launches():
+    """Problems on their own all-products launches (whole-tile and masked one-level kernels, the
+    seven in-load two-level launches, a level-0 problem whose choice falls back to the persistent
+    kernel) beside persistent-kernel problems: eager run and graph replays equal single calls."""
+    shapes = [(1024, 1024, 1024), (1024, 704, 512), (960, 1088, 768), (512, 512, 1024),
+              (768, 640, 512), (260, 300, 200), (640, 640, 640)]
+    levels = [1, 1, 1, 2, 0, 1, 0]
+    cfg = [2, 2, 2, 2, 2, 2, 0]
+    print(f"case batched all-products {shapes}", flush=True)
+    ops = _operands(shapes, 800)
+    b = sx.Batched(shapes, levels, cfg)
+    assert b.choices() == list(zip(levels, cfg))
+    dA = [sx.to_device(A) for A, _, _ in ops]
+    dB = [sx.to_device(B) for _, B, _ in ops]
+    C0 = [sx.to_device(C) for _, _, C in ops]
+    dC = [c.clone() for c in C0]
+    b.run(dA, dB, dC, 0.75, -1.25)
+    torch.cuda.synchronize()
+    want = [_single(A, B, C, 0.75, -1.25, lv, cf) for (A, B, C), lv, cf in zip(ops, levels, cfg)]
+    for i, c in enumerate(dC):
+        assert np.array_equal(sx.to_host(c), want[i]), (i, shapes[i])
+        A, B, C = ops[i]
+        ref = oracle_dgemm(A, B, C.copy(order="F"), 0.75, -1.25)
+        assert rel_fro(want[i], ref) <= TOL[levels[i]]
+    b.capture(dA, dB, dC, 0.75, -1.25)
+    for rep in range(3):
+        for c, c0 in zip(dC, C0):      # eager work between replays: reset C
+            c.copy_(c0)
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        for i, c in enumerate(dC):
+            assert np.array_equal(sx.to_host(c), want[i]), (rep, i)
     b.close()
