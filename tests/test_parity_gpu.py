@@ -202,8 +202,10 @@ def test_every_tile_config_bitwise_and_exact(cfg, levels):
 
 
 # Shapes on which ABC runs the all-products kernel (m and k multiples of 2^(L+1)): full tiles,
-# tile fringes inside the sub-blocks (m/4 = 194 = 3*64 + 2) and ragged n at both levels.
-ALL_PRODUCTS_SHAPES = [(512, 512, 512), (1024, 1030, 1032), (776, 333, 1048), (64, 9, 8)]
+# tile fringes inside the sub-blocks (m/4 = 194 = 3*64 + 2) and ragged n at both levels, and
+# sub-blocks of whole k steps with ragged m and n (1000 x 1096 x 1024).
+ALL_PRODUCTS_SHAPES = [(512, 512, 512), (1024, 1030, 1032), (776, 333, 1048), (64, 9, 8),
+                       (1000, 1096, 1024)]
 
 
 @pytest.mark.parametrize("shape", ALL_PRODUCTS_SHAPES)
@@ -237,7 +239,7 @@ def test_all_products_kernel(shape, levels):
         sx.set_tile_config(-1)
 
 
-STAGED_SHAPES = [(512, 512, 512), (1032, 1028, 1048), (2048, 2056, 1024)]
+STAGED_SHAPES = [(512, 512, 512), (1032, 1028, 1048), (2048, 2056, 1024), (1000, 1096, 1024)]
 
 
 @pytest.mark.parametrize("shape", STAGED_SHAPES)
