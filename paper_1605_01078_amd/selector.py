@@ -321,6 +321,8 @@ def main(argv=None):
     t.add_argument("inputs", nargs="+", help="timings .npz parts (or one merged file)")
     t.add_argument("--train", type=int, default=20000)
     t.add_argument("--epochs", type=int, default=300)
+    t.add_argument("--lr", type=float, default=3e-3, help="peak Adam step (cosine schedule)")
+    t.add_argument("--seed", type=int, default=0, help="initial weights and sample order")
     t.add_argument("--weights", default=WEIGHTS)
     t.add_argument("--merged", default=TIMINGS)
     a = ap.parse_args(argv)
@@ -347,12 +349,14 @@ def main(argv=None):
     y = times.argmin(axis=1)
     n = a.train
     # shapes weighted by their best time: the regret is a ratio of summed times
-    params = train(X[:n], y[:n], epochs=a.epochs, log=say, weights=times[:n].min(axis=1))
+    params = train(X[:n], y[:n], epochs=a.epochs, lr=a.lr, seed=a.seed, log=say,
+                   weights=times[:n].min(axis=1))
     res_test = evaluate(params, shapes[n:], dtypes[n:], times[n:])
     res_train = evaluate(params, shapes[:n], dtypes[:n], times[:n])
     say(json.dumps({"held_out": res_test, "train": res_train}))
     save(params, a.weights, meta={"held_out": res_test, "train": res_train,
-                                  "epochs": a.epochs, "train_shapes": n,
+                                  "epochs": a.epochs, "lr": a.lr, "seed": a.seed,
+                                  "train_shapes": n,
                                   "held_out_shapes": len(shapes) - n})
 
 
