@@ -86,8 +86,15 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * may use one to stage its outer-level operand sums (the ten two-term sums of the one-level
  * table over the 2 x 2 outer blocks, formed once by a streaming pass; the seven outer products
  * then run the one-level fused kernel on them and update C in place, bitwise as without
- * staging): by default where n % 4 == 0, (m/2)(n/2) >= 2048^2 and k >= 2048 and a library-owned
- * or large enough caller workspace is available; otherwise the sums are formed in the load.
+ * staging): by default where (m/2)(n/2) >= 2048^2 and k >= 2048 and a library-owned or large
+ * enough caller workspace is available; otherwise the sums are formed in the load.
+ * ABC at levels >= 1 runs on block-padded copies of the operands that do not fit the fused
+ * kernel's layout (m or k not a multiple of 2^(L+1), an operand not 16-byte aligned or with an
+ * odd leading dimension; B and C also where staging needs n % 4 == 0): every sub-block of the
+ * partition is stored with an even extent, the extra rows and columns zero, and C is copied
+ * back.  The result is bitwise that of the unpadded computation; the copies take workspace
+ * (reported by strassen_workspace_size for aligned operands with even leading dimensions) and
+ * are skipped, with the same result, when a caller workspace is too small for them.
  * Argument positions for -i: m=1 n=2 k=3 alpha=4 A=5 lda=6 B=7 ldb=8 beta=9 C=10 ldc=11
  * levels=12 variant=13.
  */
@@ -98,10 +105,15 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
 
 /*
  * strassen_workspace_size — bytes of device workspace strassen_dgemm needs for these sizes
- * (0 for levels 0 and one-level ABC).  AB: one M_r temporary per product (7^L of
- * ceil(m/2^L) x ceil(n/2^L) doubles); NAIVE adds the operand-sum temporaries.  Two-level ABC:
- * the staging buffers of its outer operand sums where staging is the default (five m/2 x k/2
- * and five k/2 x n/2 slots, each rounded up to 32 doubles), else 0; less only turns staging off.
+ * (0 for levels 0).  AB: one M_r temporary per product (7^L of ceil(m/2^L) x ceil(n/2^L)
+ * doubles); NAIVE adds the operand-sum temporaries.  ABC, for 16-byte aligned operands with
+ * even leading dimensions: where m, k are multiples of 2^(L+1) (and, for two levels, n of 4 or
+ * no staging), 0 at one level and at two the staging buffers of its outer operand sums where
+ * staging is the default (five m/2 x k/2 and five k/2 x n/2 slots, each rounded up to 32
+ * doubles); otherwise the block-padded copies (A as mp x kp, B as kp x n', C as mp x n' where
+ * it is copied; mp = 2^L * (ceil(m/2^L) rounded up to even), kp likewise, n' = n rounded up to
+ * 4 where staging needs it; each rounded up to 32 doubles) plus the staging buffers of the
+ * padded problem.  A smaller caller workspace only turns staging or the copies off.
  * Returns 0 or -i as strassen_dgemm does for the same argument (m=1 n=2 k=3 levels=4
  * variant=5 bytes=6).
  */
@@ -112,7 +124,10 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
  * strassen_set_workspace — use caller-owned device memory [ptr, ptr+bytes) as workspace
  * instead of the library's own (ptr must stay valid while calls that use it are in
  * flight; 256-byte alignment required).  ptr == NULL returns to library-owned workspace.
- * A call needing more than `bytes` fails with STRASSEN_ERR_ALLOC without touching C.
+ * A call needing more than `bytes` fails with STRASSEN_ERR_ALLOC without touching C (ABC only
+ * drops its staging or padded copies instead).  The workspace, the caller's or the library's,
+ * is shared by every call on the device: calls that use it (AB, NAIVE; ABC where it stages or
+ * pads) must not run at the same time on different streams.
  * Returns 0, -1 (misaligned ptr) or -2 (ptr != NULL with bytes == 0).
  */
 int strassen_set_workspace(void *ptr, size_t bytes);
@@ -281,7 +296,8 @@ enum strassen_kernel_kind {
     STRASSEN_KERNEL_OUTER_SUMS = 1,    /* the staged outer-sum pass of two-level ABC            */
     STRASSEN_KERNEL_TILE = 2,          /* the general FP64 tile kernel (classical, AB, Naive, ABC fallback) */
     STRASSEN_KERNEL_BF16 = 3,          /* the reduced-precision product kernel (strassen_gemm_ex) */
-    STRASSEN_KERNEL_CAST = 4           /* its operand pass (sums rounded to bf16 hi / lo)       */
+    STRASSEN_KERNEL_CAST = 4,          /* its operand pass (sums rounded to bf16 hi / lo)       */
+    STRASSEN_KERNEL_PAD = 5            /* block-padded operand copies of ABC (and the copy back) */
 };
 int strassen_timing_enable(int on);
 int strassen_timing_collect(int kind, double *ms_total, int *launches);

@@ -462,6 +462,121 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
   return 0;
 }
 
+// Block padding (the zero padding of Sec. 3.3 made physical).  Where the all-products layout
+// does not apply to the operands as given (m or k not a multiple of 2^(L+1), operands not
+// 16-byte aligned, odd leading dimensions) or two-level staging needs n % 4 == 0, ABC runs on
+// copies in which every row (column) block of the 2^L x 2^L partition is stored with an even
+// extent, the extra rows and columns zero.  Every real element keeps its sub-block, its
+// position in it and the k positions it meets in the MFMA; the padding only feeds exact zeros
+// to the positions the unpadded kernels mask to zero, so the result is bitwise that of the
+// unpadded path.  Operands that already fit are used in place.
+struct PadPlan {
+  int64_t mq, kq, nq, mq_e, kq_e;   // sub-block extents, plain and padded (even)
+  int64_t mp, kp, np;               // padded problem
+  bool pa, pb, pc;                  // which operands are copied
+  bool stage;                       // two-level staged outer sums on the padded problem
+  bool ok;                          // the padded layout fits the kernel's 32-bit lane offsets
+  int64_t a_off, b_off, c_off, s_off, total;   // workspace layout (doubles)
+};
+
+static PadPlan make_pad_plan(int64_t m, int64_t n, int64_t k, int levels, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, const double* C,
+                             int64_t ldc, int forced) {
+  PadPlan pp;
+  const int64_t q = int64_t(1) << levels, unit = 2 * q;
+  pp.mq = cdiv(m, q);
+  pp.kq = cdiv(k, q);
+  pp.nq = cdiv(n, q);
+  pp.mq_e = round_up(pp.mq, 2);
+  pp.kq_e = round_up(pp.kq, 2);
+  pp.mp = q * pp.mq_e;
+  pp.kp = q * pp.kq_e;
+  const int64_t n4 = round_up(n, 4);
+  pp.stage = levels == 2 && (forced == kCfgAllStaged ||
+                             (forced == -1 && staging_applies(pp.mp, n4, pp.kp, levels)));
+  const bool need_n = pp.stage && n % 4 != 0;
+  pp.np = need_n ? 4 * pp.nq : n;
+  const bool need_m = m % unit != 0, need_k = k % unit != 0;
+  const int64_t lim = int64_t(1) << 31;
+  pp.pa = need_m || need_k || !aligned16(A) || lda % 2 != 0 || 8 * 16 * lda >= lim;
+  pp.pb = need_k || need_n || !aligned16(B) || ldb % 2 != 0 || 8 * 64 * ldb >= lim;
+  pp.pc = need_m || need_n || !aligned16(C) || ldc % 2 != 0 || 8 * 64 * ldc >= lim;
+  pp.ok = 8 * 16 * (pp.pa ? pp.mp : lda) < lim && 8 * 64 * (pp.pb ? pp.kp : ldb) < lim &&
+          8 * 64 * (pp.pc ? pp.mp : ldc) < lim;
+  int64_t off = 0;
+  auto take = [&](bool used, int64_t elems) {
+    const int64_t at = off;
+    if (used) off += round_up(elems, 32);
+    return at;
+  };
+  pp.a_off = take(pp.pa, pp.mp * pp.kp);
+  pp.b_off = take(pp.pb, pp.kp * pp.np);
+  pp.c_off = take(pp.pc, pp.mp * pp.np);
+  pp.s_off = off;
+  if (pp.stage) off += make_stage_plan(make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC)).total;
+  pp.total = off;
+  return pp;
+}
+
+static int run_padded(const PadPlan& pp, int levels, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double beta, double* C, int64_t ldc, double* ws, hipStream_t stream) {
+  auto copy = [&](const double* src, int64_t ld_s, int64_t rows, int64_t cols, int64_t rb,
+                  int64_t rb_e, int64_t cb, int64_t cb_e, double* dst, int64_t ld_d,
+                  int64_t dst_rows, int64_t dst_cols, int unpad) {
+    PadArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.src = src;
+    a.dst = dst;
+    a.ld_s = ld_s;
+    a.ld_d = ld_d;
+    a.rows = rows;
+    a.cols = cols;
+    a.rb = rb;
+    a.rb_e = rb_e;
+    a.cb = cb;
+    a.cb_e = cb_e;
+    a.dst_rows = dst_rows;
+    a.dst_cols = dst_cols;
+    a.unpad = unpad;
+    return launch_pad_copy(a, stream);
+  };
+  const double* Ap = A;
+  const double* Bp = B;
+  double* Cp = C;
+  int64_t lda_p = lda, ldb_p = ldb, ldc_p = ldc;
+  const int64_t whole_n = pp.np;   // columns are not blocked: one block spanning them all
+  if (pp.pa) {
+    double* d = ws + pp.a_off;
+    SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream,
+               copy(A, lda, m, k, pp.mq, pp.mq_e, pp.kq, pp.kq_e, d, pp.mp, pp.mp, pp.kp, 0));
+    Ap = d;
+    lda_p = pp.mp;
+  }
+  if (pp.pb) {
+    double* d = ws + pp.b_off;
+    SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream,
+               copy(B, ldb, k, n, pp.kq, pp.kq_e, whole_n, whole_n, d, pp.kp, pp.kp, pp.np, 0));
+    Bp = d;
+    ldb_p = pp.kp;
+  }
+  if (pp.pc) {
+    Cp = ws + pp.c_off;
+    ldc_p = pp.mp;
+    if (beta != 0.0)   // with beta = 0 no update reads C
+      SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream,
+                 copy(C, ldc, m, n, pp.mq, pp.mq_e, whole_n, whole_n, Cp, pp.mp, pp.mp, pp.np, 0));
+  }
+  const Plan p = make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC);
+  if (int rc = run_all_products(p, Ap, lda_p, Bp, ldb_p, Cp, ldc_p, pp.np, alpha, beta,
+                                pp.stage ? ws + pp.s_off : nullptr, stream))
+    return rc;
+  if (pp.pc)
+    SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream,
+               copy(Cp, pp.mp, m, n, pp.mq, pp.mq_e, whole_n, whole_n, C, ldc, pp.mp, pp.np, 1));
+  return 0;
+}
+
 bool all_products_ok(int64_t m, int64_t k, const double* A, int64_t lda, const double* B,
                      int64_t ldb, const double* C, int64_t ldc, int levels) {
   return all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels);
@@ -543,8 +658,19 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
 
   if (p.variant == STRASSEN_ABC) {
     const int forced = g_forced_cfg.load(std::memory_order_relaxed);
-    if ((forced == -1 || forced == kCfgAll || forced == kCfgAllStaged) &&
-        all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels)) {
+    const bool all_products = forced == -1 || forced == kCfgAll || forced == kCfgAllStaged;
+    if (all_products && levels >= 1) {
+      const PadPlan pp = make_pad_plan(m, n, k, levels, A, lda, B, ldb, C, ldc, forced);
+      const size_t bytes = (size_t)pp.total * sizeof(double);
+      // a caller workspace too small for the copies: the unpadded path below (same result)
+      if ((pp.pa || pp.pb || pp.pc) && pp.ok && !user_workspace_below(bytes)) {
+        void* ws = nullptr;
+        if (int rc = get_workspace(dev, bytes, &ws)) return rc;
+        return run_padded(pp, levels, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                          static_cast<double*>(ws), stream);
+      }
+    }
+    if (all_products && all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels)) {
       double* stage = nullptr;
       const bool want = levels == 2 && n % 4 == 0 &&
                         (forced == kCfgAllStaged ||
@@ -800,8 +926,16 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   }
   const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
   *bytes = (size_t)p.total * sizeof(double);
-  if (variant == STRASSEN_ABC && smx::staging_applies(m, n, k, levels))
-    *bytes = (size_t)smx::make_stage_plan(p).total * sizeof(double);
+  if (variant == STRASSEN_ABC && levels >= 1) {
+    // operands taken as 16-byte aligned with even leading dimensions
+    const smx::PadPlan pp = smx::make_pad_plan(m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2),
+                                               nullptr, 2 * smx::cdiv(k, 2), nullptr,
+                                               2 * smx::cdiv(m, 2), -1);
+    if ((pp.pa || pp.pb || pp.pc) && pp.ok)
+      *bytes = (size_t)pp.total * sizeof(double);
+    else if (smx::staging_applies(m, n, k, levels))
+      *bytes = (size_t)smx::make_stage_plan(p).total * sizeof(double);
+  }
   return 0;
 }
 

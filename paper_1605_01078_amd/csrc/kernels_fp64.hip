@@ -227,6 +227,57 @@ hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Block-padded copy (PadArgs): one workgroup per column of the iterated matrix (the padded
+// destination when padding, the plain destination when unpadding) and kPadRows consecutive rows
+// of it, four rows per lane at a stride of 256 so that every access instruction of a wave covers
+// contiguous addresses.  Extents fit 32 bits (checked by the launcher).
+constexpr int kPadRows = 1024;
+
+__global__ __launch_bounds__(256) void pad_copy_kernel(const PadArgs a) {
+  const uint32_t j = blockIdx.x;
+  const uint32_t i0 = blockIdx.y * kPadRows + threadIdx.x;
+  const uint32_t rb = (uint32_t)a.rb, rb_e = (uint32_t)a.rb_e;
+  if (!a.unpad) {
+    const uint32_t bj = j / (uint32_t)a.cb_e, lj = j - bj * (uint32_t)a.cb_e;
+    const int64_t js = (int64_t)bj * a.cb + lj;
+    const bool col_ok = lj < (uint32_t)a.cb && js < a.cols;
+    double* dcol = a.dst + (int64_t)j * a.ld_d;
+    const double* scol = a.src + js * a.ld_s;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + 256u * u;
+      if (i >= (uint32_t)a.dst_rows) break;
+      const uint32_t bi = i / rb_e, li = i - bi * rb_e;
+      const int64_t is = (int64_t)bi * rb + li;
+      dcol[i] = (col_ok && li < rb && is < a.rows) ? scol[is] : 0.0;
+    }
+  } else {
+    const uint32_t bj = j / (uint32_t)a.cb, lj = j - bj * (uint32_t)a.cb;
+    const double* scol = a.src + ((int64_t)bj * a.cb_e + lj) * a.ld_s;
+    double* dcol = a.dst + (int64_t)j * a.ld_d;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + 256u * u;
+      if (i >= (uint32_t)a.rows) break;
+      const uint32_t bi = i / rb, li = i - bi * rb;
+      dcol[i] = scol[(int64_t)bi * rb_e + li];
+    }
+  }
+}
+
+hipError_t launch_pad_copy(const PadArgs& a, hipStream_t s) {
+  const int64_t cols = a.unpad ? a.cols : a.dst_cols;
+  const int64_t rows = a.unpad ? a.rows : a.dst_rows;
+  const int64_t lim = int64_t(1) << 31;
+  if (cols <= 0 || rows <= 0) return hipSuccess;
+  if (cols >= lim || a.dst_rows >= lim || a.dst_cols >= lim || a.rb <= 0 || a.cb <= 0 ||
+      a.rb_e < a.rb || a.cb_e < a.cb || (rows + kPadRows - 1) / kPadRows > 65535)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)cols, (unsigned)((rows + kPadRows - 1) / kPadRows));
+  hipLaunchKernelGGL(pad_copy_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s) {
   const int chunks_m = (int)((a.m + 255) / 256);
   hipLaunchKernelGGL(scale_kernel, dim3((unsigned)(chunks_m * a.n)), dim3(256), 0, s, a, chunks_m);

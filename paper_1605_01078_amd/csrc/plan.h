@@ -109,6 +109,22 @@ struct OuterSumArgs {
   int32_t chunks_r;     // row chunks per column group (set by the launcher)
 };
 
+// Block-padded copy.  Pad (unpad = 0): dst (dst_rows x dst_cols, leading dimension ld_d) gets
+// src (rows x cols, ld_s) with source row block b (rows [b*rb, b*rb + rb)) placed at destination
+// rows [b*rb_e, b*rb_e + rb) and likewise for column blocks (cb, cb_e); every other destination
+// element is zero.  Unpad (unpad = 1): the reverse, writing only the rows x cols plain elements
+// of dst from the padded src.
+struct PadArgs {
+  const double* src;
+  double* dst;
+  int64_t ld_s, ld_d;
+  int64_t rows, cols;           // plain extents
+  int64_t rb, rb_e, cb, cb_e;   // plain and padded block extents (rows, columns)
+  int64_t dst_rows, dst_cols;   // padded extents (pad direction)
+  int32_t unpad;
+  int32_t pad;
+};
+
 // Naive operand sums: slot s := sum_t delta_t X_t over the zero-padded sub-block extent.
 struct SumArgs {
   const double* src;

@@ -90,7 +90,15 @@ def test_workspace_sizes(m, n, k):
         q = 2 ** levels
         mq, nq, kq = _cdiv(m, q), _cdiv(n, q), _cdiv(k, q)
         if levels == 1 or m < 4096:   # two-level staging: test_two_level_abc_staging_workspace
-            assert sx.workspace_size(m, n, k, levels, "abc") == 0
+            # block-padded copies where m or k is not a multiple of 2^(L+1): A as mp x kp and B
+            # as kp x n (C too if m needs it), every sub-block extent rounded up to even
+            u = 2 * q
+            mp, kp = q * 2 * _cdiv(mq, 2), q * 2 * _cdiv(kq, 2)
+            r32 = lambda x: _cdiv(x, 32) * 32
+            want = 0
+            if m % u or k % u:
+                want = 8 * (r32(mp * kp) + r32(kp * n) + (r32(mp * n) if m % u else 0))
+            assert sx.workspace_size(m, n, k, levels, "abc") == want
         ab = sx.workspace_size(m, n, k, levels, "ab")
         nprod = 7 ** levels
         # one M_r per product, leading dimension rounded to 8 doubles, slot to 32
@@ -113,8 +121,13 @@ def test_two_level_abc_staging_workspace():
         want = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
         assert sx.workspace_size(m, n, k, 2, "abc") == want
         assert sx.workspace_size(m, n, k, 1, "abc") == 0
-    for m, n, k in [(8192, 8190, 8192), (2048, 4096, 4096), (8192, 8192, 1024)]:
+    for m, n, k in [(2048, 4096, 4096), (8192, 8192, 1024)]:
         assert sx.workspace_size(m, n, k, 2, "abc") == 0
+    # n not a multiple of 4: B and C are copied with n rounded up to 4 columns, then staged
+    m, n, k = 8192, 8190, 8192
+    n4 = 4 * _cdiv(n, 4)
+    want = 8 * (r32(k * n4) + r32(m * n4) + 5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n4 // 2)))
+    assert sx.workspace_size(m, n, k, 2, "abc") == want
 
 
 def test_workspace_size_errors():

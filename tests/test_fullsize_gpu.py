@@ -1,7 +1,8 @@
 """Parity at the full benchmark sizes, in the configuration bench.py times (needs an MI355X).
 
-m = n = k = 16384 (square) and m = n = 16384, k = 1024 (rank-k), A, B, C uniform[-1, 1] drawn on
-the device from seeds, alpha = beta = 1:
+m = n = k = 16384 (square), m = n = 16384, k = 1024 (rank-k) and m = n = k = 16383 (every
+dimension odd: ABC on block-padded copies), A, B, C uniform[-1, 1] drawn on the device from
+seeds, alpha = beta = 1:
   * 64 randomly chosen columns of C from classical, one-level ABC and two-level ABC (default
     path: staged outer sums) against the plain-definition oracle on those columns — relative
     Frobenius error 1e-12 / 1e-11 for Strassen, the any-order rounding bound for classical;
@@ -42,7 +43,7 @@ def _call(A, B, C0, levels, variant, cfg=-1):
     return C
 
 
-@pytest.mark.parametrize("shape", [(16384, 16384, 16384), (16384, 16384, 1024)])
+@pytest.mark.parametrize("shape", [(16384, 16384, 16384), (16384, 16384, 1024), (16383, 16383, 16383)])
 def test_full_size_sampled_columns_and_projection(shape):
     m, n, k = shape
     print(f"case full size {shape}", flush=True)

@@ -331,3 +331,75 @@ def test_kernel_timing_hooks():
     assert (n_ap, n_os, n_t) == (8, 2, 1)
     assert ms_ap > 0 and ms_os > 0 and ms_t > 0
     assert sx.timing_collect("all_products") == (0.0, 0)
+
+
+# Block-padded ABC: shapes and layouts the all-products kernel cannot take as given (odd and
+# not-multiple-of-2^(L+1) m and k, odd leading dimensions, an operand one double off 16-byte
+# alignment, two-level staging with n not a multiple of 4).
+PADDED_CASES = [
+    # (m, n, k, levels, lda_extra, ldb_extra, ldc_extra, offset, tile config)
+    (301, 259, 271, 1, 0, 0, 0, 0, -1),
+    (301, 259, 271, 2, 0, 0, 0, 0, -1),
+    (1002, 998, 1030, 1, 0, 0, 0, 0, -1),      # m, k even, sub-block extents odd
+    (1002, 998, 1030, 2, 0, 0, 0, 0, -1),
+    (512, 512, 512, 1, 1, 3, 1, 0, -1),        # odd leading dimensions
+    (512, 520, 512, 2, 0, 0, 0, 1, -1),        # every operand one double off alignment
+    (1000, 1094, 1024, 2, 0, 0, 0, 0, 5),      # staged, n % 4 == 2
+    (1001, 1094, 1027, 2, 2, 0, 0, 1, 5),      # staged, everything ragged
+]
+
+
+@pytest.mark.parametrize("case", PADDED_CASES)
+def test_block_padded_abc(case):
+    """ABC on block-padded copies: the copies run (timing hooks), the result is bitwise that of
+    the unpadded path (the general tile kernel and Naive), exact on integers, within tolerance
+    on reals, C write-only with beta = 0, and a caller workspace too small for the copies gives
+    the same result without them."""
+    m, n, k, levels, ea, eb, ec, off, cfg = case
+    print(f"case padded {case}", flush=True)
+    lda, ldb, ldc = m + ea, k + eb, m + ec
+    A, B, C = W.problem(41, m, n, k, "integer")
+    ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+    Ar, Br, Cr = W.problem(42, m, n, k, "uniform")
+    refr = oracle_dgemm(Ar, Br, Cr.copy(order="F"), 0.5, -1.5)
+    try:
+        sx.set_tile_config(cfg)
+        for kind in sx.KERNEL_KINDS:
+            sx.timing_collect(kind)
+        sx.timing_enable(True)
+        try:
+            got = run(Ar, Br, Cr, 0.5, -1.5, levels, "abc", lda, ldb, ldc, off)
+        finally:
+            sx.timing_enable(False)
+        _, n_pad = sx.timing_collect("pad")
+        _, n_ap = sx.timing_collect("all_products")
+        assert n_pad >= 2 and n_ap >= 1, (n_pad, n_ap)
+        assert rel_fro(got, refr) <= TOL[levels]
+        assert np.array_equal(run(A, B, C, 1.0, 1.0, levels, "abc", lda, ldb, ldc, off), ref)
+        Cn = np.full_like(Cr, np.nan)
+        out0 = run(Ar, Br, Cn, 0.5, 0.0, levels, "abc", lda, ldb, ldc, off)
+        assert np.isfinite(out0).all()
+        sx.set_tile_config(0)   # the general tile kernel, unpadded
+        assert np.array_equal(run(Ar, Br, Cr, 0.5, -1.5, levels, "abc", lda, ldb, ldc, off), got)
+        assert np.array_equal(run(Ar, Br, Cn, 0.5, 0.0, levels, "abc", lda, ldb, ldc, off), out0)
+        sx.set_tile_config(-1)
+        assert np.array_equal(run(Ar, Br, Cr, 0.5, -1.5, levels, "naive", lda, ldb, ldc, off), got)
+    finally:
+        sx.set_tile_config(-1)
+    # a caller workspace too small for the copies: the unpadded path, the same result
+    tiny = torch.empty(32, dtype=torch.float64, device="cuda")
+    sx.set_workspace(tiny)
+    try:
+        sx.set_tile_config(cfg)
+        for kind in sx.KERNEL_KINDS:
+            sx.timing_collect(kind)
+        sx.timing_enable(True)
+        try:
+            again = run(Ar, Br, Cr, 0.5, -1.5, levels, "abc", lda, ldb, ldc, off)
+        finally:
+            sx.timing_enable(False)
+        assert sx.timing_collect("pad")[1] == 0
+        assert np.array_equal(again, got)
+    finally:
+        sx.set_tile_config(-1)
+        sx.set_workspace(None)
