@@ -70,9 +70,11 @@ static double launch_seconds(double items, double fi, double slots, double rate)
   return std::ceil(items / slots) * fi / share;
 }
 
-// The kernel each member runs for these sizes follows the library's own dispatch: ABC uses the
-// all-products kernel where m and k are multiples of 2^(L+1) (whole tiles or masked), at two
-// levels with the staged outer sums where they apply, else the general tile kernel.  Rates and
+// The kernel each member runs for these sizes follows the library's own dispatch: ABC runs the
+// all-products kernel (whole tiles or masked) on the operands as given where m and k are
+// multiples of 2^(L+1), else on block-padded copies (every sub-block extent rounded up to even;
+// the copies cost their HBM traffic), at two levels with the staged outer sums where they apply
+// (n rounded up to 4 by the copies).  Rates and
 // efficiencies were fitted to this library's timings of the selector's 20000 training shapes
 // (coordinate search on the regret of the model's choice, efficiencies capped at 1, keeping the
 // measured order at m = n = k = 16384: two-level ABC, one-level ABC, classical).
@@ -82,7 +84,6 @@ struct ModelCoef {
   double e_full = 0.99;      // all-products kernel, whole tiles (relative to R)
   double e_masked = 0.966;   // all-products kernel, masked loads
   double e_unstaged = 0.80;  // two levels, outer sums in the load
-  double e_tile1 = 0.60, e_tile2 = 0.50;   // ABC on the general tile kernel
   double e_ab1 = 0.918, e_ab2 = 0.562, e_naive1 = 0.997, e_naive2 = 0.483;
   double bw = 7.81e12;       // HBM bytes/s of the element-wise passes (fitted)
   double t_launch = 20.0e-6; // per launch (latency and tail)
@@ -103,10 +104,6 @@ double model_seconds(int64_t m, int64_t n, int64_t k, int dtype, int c) {
   // operand terms and C updates of the tables (Sec. 3.1, Sec. 3.5): 12^L each
   const double terms = L == 0 ? 1.0 : (L == 1 ? 12.0 : 144.0);
   auto tiles = [](double a, double b, double t) { return std::ceil(a / t) * std::ceil(b / t); };
-  auto ap_launch = [&](double e) {   // one all-products launch: 7 products per 64 x 64 item
-    return launch_seconds(tiles(mq, nq, 64.0), 7.0 * 2.0 * 64 * 64 * kq, 256.0, K.R * e) + K.t_launch;
-  };
-  const bool whole = mqi % 64 == 0 && nqi % 64 == 0 && kqi % 16 == 0 && q * nqi <= n;
   double t = 0.0;
   if (dtype == 0) {
     if (L == 0) {
@@ -117,18 +114,28 @@ double model_seconds(int64_t m, int64_t n, int64_t k, int dtype, int c) {
     }
     if (var == STRASSEN_ABC) {
       const int64_t unit = int64_t(2) << L;
-      if (m % unit == 0 && k % unit == 0) {
-        if (L == 1) return ap_launch(whole ? K.e_full : K.e_masked);
-        const bool staged = n % 4 == 0 && (m / 2) * (n / 2) >= int64_t(2048) * 2048 && k >= 2048;
-        if (!staged) return 7.0 * ap_launch(K.e_unstaged);
-        // the outer sums (per side four blocks read, five sums written), then seven one-level
-        // launches
-        return 7.0 * ap_launch(whole ? K.e_full : K.e_masked) +
-               8.0 * 9.0 * (4.0 * mq * kq + 4.0 * kq * nq) / K.bw + 2.0 * K.t_launch;
-      }
-      const double e = L == 1 ? K.e_tile1 : K.e_tile2;
-      return launch_seconds(tiles(mq, nq, 128.0), p7 * 2.0 * 128 * 128 * kq, 512.0, K.R * e) +
-             K.t_launch;
+      const int64_t mqe = round_up(mqi, 2), kqe = round_up(kqi, 2);
+      const int64_t mp = q * mqe, kp = q * kqe, n4 = round_up(n, 4);
+      const bool staged = L == 2 && (mp / 2) * (n4 / 2) >= int64_t(2048) * 2048 && kp >= 2048;
+      const bool pad_mk = m % unit != 0 || k % unit != 0;
+      const bool pad_n = staged && n % 4 != 0;
+      double copies = 0.0;   // block-padded copies: A and B (or B only), C in and out
+      const double dm = (double)m, dn = (double)n, dk = (double)k;
+      if (pad_mk) copies = 8.0 * (2.0 * dm * dk + 2.0 * dk * dn + 4.0 * dm * dn) / K.bw + 4.0 * K.t_launch;
+      else if (pad_n) copies = 8.0 * (2.0 * dk * dn + 4.0 * dm * dn) / K.bw + 3.0 * K.t_launch;
+      const double mqp = (double)mqe, kqp = (double)kqe;
+      const bool whole_p = mqe % 64 == 0 && nqi % 64 == 0 && kqe % 16 == 0 &&
+                           q * nqi <= (pad_n ? n4 : n);
+      auto ap = [&](double e) {   // one all-products launch: 7 products per 64 x 64 item
+        return launch_seconds(tiles(mqp, nq, 64.0), 7.0 * 2.0 * 64 * 64 * kqp, 256.0, K.R * e) +
+               K.t_launch;
+      };
+      if (L == 1) return copies + ap(whole_p ? K.e_full : K.e_masked);
+      if (!staged) return copies + 7.0 * ap(K.e_unstaged);
+      // the outer sums (per side four blocks read, five sums written), then seven one-level
+      // launches
+      return copies + 7.0 * ap(whole_p ? K.e_full : K.e_masked) +
+             8.0 * 9.0 * (4.0 * mqp * kqp + 4.0 * kqp * nq) / K.bw + 2.0 * K.t_launch;
     }
     const double e = var == STRASSEN_AB ? (L == 1 ? K.e_ab1 : K.e_ab2) : (L == 1 ? K.e_naive1 : K.e_naive2);
     t = launch_seconds(p7 * tiles(mq, nq, 128.0), 2.0 * 128 * 128 * kq, 512.0, K.R * e) +
