@@ -144,9 +144,9 @@ def test_batched_all_products_launches():
     seven in-load two-level launches, a level-0 problem whose choice falls back to the persistent
     kernel) beside persistent-kernel problems: eager run and graph replays equal single calls."""
     shapes = [(1024, 1024, 1024), (1024, 704, 512), (960, 1088, 768), (512, 512, 1024),
-              (768, 640, 512), (260, 300, 200), (640, 640, 640)]
-    levels = [1, 1, 1, 2, 0, 1, 0]
-    cfg = [2, 2, 2, 2, 2, 2, 0]
+              (768, 640, 512), (260, 300, 200), (640, 640, 640), (301, 259, 271)]
+    levels = [1, 1, 1, 2, 0, 1, 0, 1]
+    cfg = [2, 2, 2, 2, 2, 2, 0, 2]     # the last: layout does not apply, persistent kernel
     print(f"case batched all-products {shapes}", flush=True)
     ops = _operands(shapes, 800)
     b = sx.Batched(shapes, levels, cfg)
