@@ -220,6 +220,7 @@ def precision_suite(args):
             r["speedup_vs_same_mode_classical"] = round(base[(r["mode"], 0)]["ms"] / r["ms"], 4)
     q = 4
     exec_flops = 49 * 2.0 * (n // q) ** 3 * 3
+    _, bf16_rate = sx.probe_rates(stream)   # measured BF16 matrix-core issue rate
     out = {"metric": "effective TFLOPS (2mnk/t) of the reduced-precision mode, with rel error vs FP64",
            "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1,
            "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak",
@@ -228,6 +229,7 @@ def precision_suite(args):
            "config": {"workload": f"strassen_gemm_ex L=2 bf16x3 m=n=k={n}, inputs uniform[-1,1] "
                                   "and wide-range rows 2^U[-8,8]", "m": n, "n": n, "k": n},
            "roofline": {"bound": "mfma", "peak": 2500.0, "unit": "TFLOP/s",
+                        "peak_measured": round(bf16_rate, 1),
                         "kernel": "bf16_gemm_kernel (bf16x3)",
                         "achieved_note": "executed bf16 MFMA flops of the two-level bf16x3 call "
                                          "(49 products x 3 MFMA passes) over the product kernel's "
@@ -638,6 +640,11 @@ def main():
     if sums_launches:
         roofline["outer_sum_passes"] = {"launches_per_step": sums_launches // args.steps,
                                         "ms_per_step": round(sums_ms / args.steps, 3)}
+    # the matrix cores' measured issue rate on this device, beside the datasheet peak
+    f64_rate, _ = sx.probe_rates(stream)
+    roofline["peak_measured"] = round(f64_rate, 2)
+    roofline["frac_of_measured"] = round(achieved / f64_rate, 4)
+    log(f"  measured FP64 MFMA issue rate {f64_rate:.2f} TFLOP/s")
 
     # ---- CPU baseline: the oracle on a bounded column sample -----------------------------------
     cpu = None

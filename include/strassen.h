@@ -303,6 +303,16 @@ int strassen_timing_enable(int on);
 int strassen_timing_collect(int kind, double *ms_total, int *launches);
 
 /*
+ * strassen_probe_rates(fp64_tflops, bf16_tflops, stream) — measurement support: the matrix
+ * cores' issue rate on the current device, measured by a kernel in which every wave issues
+ * eight independent chains of the instruction the library's kernels use (FP64
+ * v_mfma_f64_16x16x4_f64; BF16 v_mfma_f32_16x16x32_bf16), eight waves per SIMD, about 20 ms
+ * each; the roofline fractions are also quoted against these.  Allocates and frees a small
+ * device buffer, synchronises `stream`.  Returns 0, -1 (NULL output) or a positive error.
+ */
+int strassen_probe_rates(double *fp64_tflops, double *bf16_tflops, void *stream);
+
+/*
  * Table introspection (host only, no device needed): the operation table the kernels execute.
  * strassen_table_size returns the number of products for `levels` (1, 7, 49) or -1.
  * strassen_table_get fills, for product r, the operand and destination terms as

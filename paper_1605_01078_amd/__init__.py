@@ -94,6 +94,7 @@ def _optional(L):
                                ctypes.c_float, ctypes.c_float, vp], ci),
         "strassen_timing_enable": ([ci], ci),
         "strassen_timing_collect": ([ci, ctypes.POINTER(dbl), ctypes.POINTER(ci)], ci),
+        "strassen_probe_rates": ([ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp], ci),
     }
     for name, (args, res) in specs.items():
         f = getattr(L, name)
@@ -248,6 +249,13 @@ def set_tile_config(cfg):
 
 
 KERNEL_KINDS = {"all_products": 0, "outer_sums": 1, "tile": 2, "bf16": 3, "cast": 4, "pad": 5}
+
+
+def probe_rates(stream=None):
+    """Measured FP64 and BF16 matrix-core issue rates (TFLOP/s) of the current device."""
+    f, b = ctypes.c_double(), ctypes.c_double()
+    check(lib().strassen_probe_rates(ctypes.byref(f), ctypes.byref(b), _stream(stream)))
+    return f.value, b.value
 
 
 def timing_enable(on=True):

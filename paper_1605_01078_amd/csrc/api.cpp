@@ -996,6 +996,45 @@ int strassen_timing_enable(int on) {
   return 0;
 }
 
+int strassen_probe_rates(double* fp64_tflops, double* bf16_tflops, void* stream) {
+  smx::g_last_error.clear();
+  if (!fp64_tflops || !bf16_tflops) return smx::fail(-1, "NULL output");
+  int dev = 0;
+  if (int rc = smx::device_ready(&dev)) return rc;
+  hipDeviceProp_t prop;
+  SMX_HIP(hipGetDeviceProperties(&prop, dev));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int grid = smx::probe_grid(prop.multiProcessorCount);
+  double* out = nullptr;
+  SMX_HIP(hipMalloc(&out, (size_t)grid * 256 * sizeof(double)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  // about 20 ms per timed launch at the datasheet rates
+  const int iters[2] = {10000, 40000};
+  double* res[2] = {fp64_tflops, bf16_tflops};
+  for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
+    e = smx::launch_rate_probe(kind, out, grid, iters[kind] / 10, s);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = smx::launch_rate_probe(kind, out, grid, iters[kind], s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess) {
+      const double flops = (double)grid * 4.0 * iters[kind] * smx::probe_flops_per_wave_iter(kind);
+      *res[kind] = flops / (ms * 1e-3) * 1e-12;
+    }
+  }
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (e != hipSuccess) return smx::hip_fail(e, "rate probe");
+  if (es != hipSuccess) return smx::hip_fail(es, "rate probe");
+  return 0;
+}
+
 int strassen_timing_collect(int kind, double* ms_total, int* launches) {
   smx::g_last_error.clear();
   if (!ms_total || !launches) return smx::fail(-2, "NULL output");

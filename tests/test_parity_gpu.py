@@ -403,3 +403,13 @@ def test_block_padded_abc(case):
     finally:
         sx.set_tile_config(-1)
         sx.set_workspace(None)
+
+
+def test_probe_rates():
+    """The matrix-core rate probe: FP64 and BF16 issue rates between half and 105% of the
+    datasheet peaks (78.6 and 2500 TFLOP/s)."""
+    print("case rate probe", flush=True)
+    f64, bf16 = sx.probe_rates()
+    print(f"  FP64 {f64:.2f} TFLOP/s, BF16 {bf16:.1f} TFLOP/s", flush=True)
+    assert 0.5 * 78.6 < f64 < 1.05 * 78.6
+    assert 0.5 * 2500.0 < bf16 < 1.05 * 2500.0
