@@ -80,6 +80,9 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  *   levels : 0 (classical GEMM on FP64 MFMA, the effective-GFLOPS yardstick), 1 or 2.
  *   variant: STRASSEN_ABC, STRASSEN_AB or STRASSEN_NAIVE (ignored when levels == 0).
  * The general operation is eq. (e:straprim1) at one level and eq. (e:straprim3) at two.
+ * AB runs its products on the fused kernel of ABC, stored to the temporaries instead of added to
+ * C (one level; two levels over staged outer sums), where that kernel's layout applies to the
+ * operands as given, else on the general tile kernel; the results are the same bits.
  * AB and NAIVE use a library-owned workspace (grown on demand, kept until
  * strassen_release_workspace or process exit) unless strassen_set_workspace gave one;
  * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 3.3).  Two-level ABC
@@ -106,7 +109,8 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
 /*
  * strassen_workspace_size — bytes of device workspace strassen_dgemm needs for these sizes
  * (0 for levels 0).  AB: one M_r temporary per product (7^L of ceil(m/2^L) x ceil(n/2^L)
- * doubles); NAIVE adds the operand-sum temporaries.  ABC, for 16-byte aligned operands with
+ * doubles, leading dimension rounded up to 8, each slot to 32), plus at two levels the staging
+ * buffers below where two-level ABC would stage; NAIVE adds the operand-sum temporaries.  ABC, for 16-byte aligned operands with
  * even leading dimensions: where m, k are multiples of 2^(L+1) (and, for two levels, n of 4 or
  * no staging), 0 at one level and at two the staging buffers of its outer operand sums where
  * staging is the default (five m/2 x k/2 and five k/2 x n/2 slots, each rounded up to 32

@@ -427,7 +427,8 @@ static int build_all_products(const Plan& p, const double* A, int64_t lda, const
 // operand sums are first formed into it by two streaming launches.
 static int run_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
                             int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
-                            double beta, double* stage, hipStream_t stream) {
+                            double beta, double* stage, hipStream_t stream,
+                            double* M = nullptr, int64_t ldm = 0, int64_t m_stride = 0) {
   std::vector<ApLaunch> launches;
   if (int rc = build_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta,
                                   p.levels == 2 ? stage : nullptr, &launches))
@@ -457,8 +458,17 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
     SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
     SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
   }
-  for (const ApLaunch& l : launches)
+  for (size_t i = 0; i < launches.size(); ++i) {
+    ApLaunch l = launches[i];
+    if (M) {   // the AB form: launch i holds products 7i .. 7i + 6 of the table
+      l.f.store_m = 1;
+      l.f.M = M;
+      l.f.ldm = ldm;
+      l.f.m_stride = m_stride;
+      l.f.prod_base = 7 * (int32_t)i;
+    }
     SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(l.f, l.na, l.nb, stream));
+  }
   return 0;
 }
 
@@ -696,8 +706,29 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     return 0;
   }
 
+  // AB on the all-products kernel where its layout applies to the operands as given: the seven
+  // products of one level side by side, each stored to its temporary (at two levels over the
+  // staged outer sums, the only two-level form with one term per side); the products are
+  // bitwise those of the tile kernel and the assembly below is the same.
+  bool ab_fused = false;
+  size_t ws_doubles = (size_t)p.total;
+  if (p.variant == STRASSEN_AB) {
+    const int forced = g_forced_cfg.load(std::memory_order_relaxed);
+    const bool fused_cfg = forced == -1 || forced == kCfgAll || forced == kCfgAllStaged;
+    if (fused_cfg && all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels) &&
+        (levels == 1 || (n % 4 == 0 && staging_applies(m, n, k, levels))) &&
+        8 * 64 * p.ldm < (int64_t(1) << 31)) {
+      const size_t with_stage =
+          (size_t)p.total +
+          (levels == 2 ? (size_t)make_stage_plan(make_plan(m, n, k, levels, STRASSEN_ABC)).total : 0);
+      if (!user_workspace_below(with_stage * sizeof(double))) {
+        ab_fused = true;
+        ws_doubles = with_stage;
+      }
+    }
+  }
   void* ws = nullptr;
-  if (int rc = get_workspace(dev, (size_t)p.total * sizeof(double), &ws)) return rc;
+  if (int rc = get_workspace(dev, ws_doubles * sizeof(double), &ws)) return rc;
   double* wsd = static_cast<double*>(ws);
   g.M = wsd + p.off_m;
   g.ldm = p.ldm;
@@ -744,14 +775,22 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     g.tb_stride = p.tb_stride;
   }
 
-  const int cfg = pick_cfg(p, p.td->nprod, maxt);
-  g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
-  g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
-  g.mode = kModeStoreM;
-  g.prod_begin = 0;
-  const int64_t grid = (int64_t)g.tiles_m * g.tiles_n * p.td->nprod;
-  if (grid >= tiles_limit) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
-  SMX_LAUNCH(STRASSEN_KERNEL_TILE, stream, launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+  if (ab_fused) {
+    const Plan pf = make_plan(m, n, k, levels, STRASSEN_ABC);
+    if (int rc = run_all_products(pf, A, lda, B, ldb, C, ldc, n, alpha, beta,
+                                  levels == 2 ? wsd + p.total : nullptr, stream, g.M, p.ldm,
+                                  p.m_stride))
+      return rc;
+  } else {
+    const int cfg = pick_cfg(p, p.td->nprod, maxt);
+    g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
+    g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
+    g.mode = kModeStoreM;
+    g.prod_begin = 0;
+    const int64_t grid = (int64_t)g.tiles_m * g.tiles_n * p.td->nprod;
+    if (grid >= tiles_limit) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+    SMX_LAUNCH(STRASSEN_KERNEL_TILE, stream, launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+  }
 
   AssembleArgs asmb;
   std::memset(&asmb, 0, sizeof asmb);
@@ -926,6 +965,10 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   }
   const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
   *bytes = (size_t)p.total * sizeof(double);
+  if (variant == STRASSEN_AB && levels == 2 && smx::staging_applies(m, n, k, levels))
+    // the all-products form of AB stages the outer operand sums behind the temporaries
+    *bytes += (size_t)smx::make_stage_plan(smx::make_plan(m, n, k, levels, STRASSEN_ABC)).total *
+              sizeof(double);
   if (variant == STRASSEN_ABC && levels >= 1) {
     // operands taken as 16-byte aligned with even leading dimensions
     const smx::PadPlan pp = smx::make_pad_plan(m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2),

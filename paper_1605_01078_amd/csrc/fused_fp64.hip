@@ -84,6 +84,9 @@ struct AllProducts {
 
   typedef d4_t Acc[7][2];
 
+  // STORE_M: the AB variant's form: every product M_r (unscaled) is stored to its temporary
+  // (slot prod_base + r, leading dimension ldm) instead of being added to C.
+  template <bool STORE_M>
   __device__ static void run(const FusedArgs& args, double* lds) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar addressing
@@ -317,10 +320,30 @@ struct AllProducts {
     // no DMA may still be writing this workgroup's LDS when its waves end
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
-    // ---- epilogue: every C quadrant of every outer destination, read once, written once ----
     const int er = 32 * wm + 2 * (lane & 15);   // tile row of the lane's row pair
     const int ec = 16 * wn + (lane >> 4);       // tile column of element 0
     const bool e_row_ok = i0 + er < mq;
+    if (STORE_M) {
+      // ---- epilogue (AB): the seven products to their temporaries (8-byte stores through
+      // as_u2: a 16-byte store of a pair built from accumulator elements stored wrong values) ----
+      const int64_t ldm = args.ldm;
+      const uint32_t m_off = (uint32_t)(8 * (er + (int64_t)ec * ldm));
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
+        const __amdgpu_buffer_rsrc_t rs =
+            make_rsrc(args.M + (int64_t)(args.prod_base + r) * args.m_stride + i0 + j0 * ldm);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = e_row_ok && j0 + ec + 4 * e < nq;
+          const uint32_t so = (uint32_t)(8 * 4 * e * ldm);
+          __builtin_amdgcn_raw_buffer_store_b64(as_u2(acc[r][0][e]), rs, ok ? m_off : kOOB, so, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(as_u2(acc[r][1][e]), rs, ok ? m_off + 8 : kOOB, so, 0);
+        }
+      }
+      return;
+    }
+
+    // ---- epilogue: every C quadrant of every outer destination, read once, written once ----
     const int64_t ldc = args.ldc;
     const uint32_t e_off = (uint32_t)(8 * (er + (int64_t)ec * ldc));
     for (int d = 0; d < args.nc; ++d) {
@@ -365,7 +388,15 @@ template <int NA, int NB, int BK, int NS, bool FULL>
 __global__ __launch_bounds__(512, 1) void all_products_kernel(const FusedArgs args) {
   using K = AllProducts<NA, NB, BK, NS, FULL>;
   __shared__ __attribute__((aligned(16))) double lds[K::LDS_D];
-  K::run(args, lds);
+  K::template run<false>(args, lds);
+}
+
+// The AB variant on the same main loop: the products are stored, C is assembled afterwards.
+template <int NA, int NB, int BK, int NS, bool FULL>
+__global__ __launch_bounds__(512, 1) void all_products_store_kernel(const FusedArgs args) {
+  using K = AllProducts<NA, NB, BK, NS, FULL>;
+  __shared__ __attribute__((aligned(16))) double lds[K::LDS_D];
+  K::template run<true>(args, lds);
 }
 
 }  // namespace
@@ -376,6 +407,11 @@ const void* all_products_fn(const FusedArgs& a, int na, int nb) {
   int64_t cb_max = 0;
   for (int t = 0; t < nb; ++t) cb_max = cb_max > a.b_cb[t] ? cb_max : a.b_cb[t];
   const bool full = a.mq % 64 == 0 && a.nq % 64 == 0 && a.kq % 16 == 0 && (cb_max + 2) * a.nq <= a.n;
+  if (a.store_m) {   // the AB form: one term per side (one level, or staged two-level sums)
+    if (na != 1 || nb != 1) return nullptr;
+    return full ? (const void*)all_products_store_kernel<1, 1, 16, 2, true>
+                : (const void*)all_products_store_kernel<1, 1, 16, 2, false>;
+  }
   if (na == 1 && nb == 1 && full) return (const void*)all_products_kernel<1, 1, 16, 2, true>;
   if (na == 1 && nb == 1) return (const void*)all_products_kernel<1, 1, 16, 2, false>;
   // (the whole-tile form of the two-level kernels measured slower: they keep the masked loads)

@@ -82,6 +82,11 @@ struct FusedArgs {
   int64_t a_off[2], b_off[2], c_off[2];   // element offsets of the outer blocks
   int32_t b_cb[2], c_cb[2];     // first column block (units of nq) of outer B terms / destinations
   double a_sg[2], b_sg[2], c_sg[2];
+  // AB form (store_m = 1): product r of this launch goes to temporary prod_base + r at
+  // M + (prod_base + r) * m_stride, leading dimension ldm (even); C is not touched
+  double* M;
+  int64_t ldm, m_stride;
+  int32_t store_m, prod_base;
 };
 
 // C assembly for AB / Naive: C_s := beta*C_s at the first update, then C_s += alpha*gamma*M_r
