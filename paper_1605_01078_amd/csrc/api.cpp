@@ -587,6 +587,41 @@ static int run_padded(const PadPlan& pp, int levels, int64_t m, int64_t n, int64
   return 0;
 }
 
+// AB on the all-products kernel: the store form writes each product to its temporary and the
+// assembly of the tile path follows.  A and B are block-padded where they do not fit the
+// kernel's layout (C is no operand of the fused loop); the temporaries keep the real problem's
+// leading dimension, which is at least the padded sub-block extent, so the padded rows land
+// outside the part the assembly reads.  Two levels need the staged outer sums (one term per
+// side).  Offsets are in doubles, behind the temporaries of `p`.
+struct AbLayout {
+  PadPlan pp;
+  bool fused = false;
+  int64_t a_off = 0, b_off = 0, s_off = 0, total = 0;
+};
+
+static AbLayout make_ab_layout(const Plan& p, int64_t m, int64_t n, int64_t k, int levels,
+                               const double* A, int64_t lda, const double* B, int64_t ldb,
+                               int forced) {
+  AbLayout l;
+  l.total = p.total;
+  const bool fused_cfg = forced == -1 || forced == kCfgAll || forced == kCfgAllStaged;
+  if (p.variant != STRASSEN_AB || levels < 1 || !fused_cfg) return l;
+  l.pp = make_pad_plan(m, n, k, levels, A, lda, B, ldb, nullptr, 2 * cdiv(m, 2), forced);
+  if (!l.pp.ok || (levels == 2 && !l.pp.stage) || 8 * 64 * p.ldm >= (int64_t(1) << 31))
+    return l;
+  int64_t off = p.total;
+  l.a_off = off;
+  if (l.pp.pa) off += round_up(l.pp.mp * l.pp.kp, 32);
+  l.b_off = off;
+  if (l.pp.pb) off += round_up(l.pp.kp * l.pp.np, 32);
+  l.s_off = off;
+  if (l.pp.stage)
+    off += make_stage_plan(make_plan(l.pp.mp, l.pp.np, l.pp.kp, levels, STRASSEN_ABC)).total;
+  l.fused = true;
+  l.total = off;
+  return l;
+}
+
 bool all_products_ok(int64_t m, int64_t k, const double* A, int64_t lda, const double* B,
                      int64_t ldb, const double* C, int64_t ldc, int levels) {
   return all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels);
@@ -706,27 +741,14 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     return 0;
   }
 
-  // AB on the all-products kernel where its layout applies to the operands as given: the seven
-  // products of one level side by side, each stored to its temporary (at two levels over the
-  // staged outer sums, the only two-level form with one term per side); the products are
-  // bitwise those of the tile kernel and the assembly below is the same.
-  bool ab_fused = false;
-  size_t ws_doubles = (size_t)p.total;
-  if (p.variant == STRASSEN_AB) {
-    const int forced = g_forced_cfg.load(std::memory_order_relaxed);
-    const bool fused_cfg = forced == -1 || forced == kCfgAll || forced == kCfgAllStaged;
-    if (fused_cfg && all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels) &&
-        (levels == 1 || (n % 4 == 0 && staging_applies(m, n, k, levels))) &&
-        8 * 64 * p.ldm < (int64_t(1) << 31)) {
-      const size_t with_stage =
-          (size_t)p.total +
-          (levels == 2 ? (size_t)make_stage_plan(make_plan(m, n, k, levels, STRASSEN_ABC)).total : 0);
-      if (!user_workspace_below(with_stage * sizeof(double))) {
-        ab_fused = true;
-        ws_doubles = with_stage;
-      }
-    }
-  }
+  // AB on the all-products kernel where it applies (block-padded A and B where needed)
+  AbLayout abl;
+  if (p.variant == STRASSEN_AB)
+    abl = make_ab_layout(p, m, n, k, levels, A, lda, B, ldb,
+                         g_forced_cfg.load(std::memory_order_relaxed));
+  const bool ab_fused = abl.fused && !user_workspace_below((size_t)abl.total * sizeof(double));
+  const PadPlan& abp = abl.pp;
+  const size_t ws_doubles = (size_t)(ab_fused ? abl.total : p.total);
   void* ws = nullptr;
   if (int rc = get_workspace(dev, ws_doubles * sizeof(double), &ws)) return rc;
   double* wsd = static_cast<double*>(ws);
@@ -776,9 +798,52 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
   }
 
   if (ab_fused) {
-    const Plan pf = make_plan(m, n, k, levels, STRASSEN_ABC);
-    if (int rc = run_all_products(pf, A, lda, B, ldb, C, ldc, n, alpha, beta,
-                                  levels == 2 ? wsd + p.total : nullptr, stream, g.M, p.ldm,
+    const double* Af = A;
+    const double* Bf = B;
+    int64_t lda_f = lda, ldb_f = ldb;
+    const int64_t whole_n = abp.np;
+    if (abp.pa) {
+      PadArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.src = A;
+      a.dst = wsd + abl.a_off;
+      a.ld_s = lda;
+      a.ld_d = abp.mp;
+      a.rows = m;
+      a.cols = k;
+      a.rb = abp.mq;
+      a.rb_e = abp.mq_e;
+      a.cb = abp.kq;
+      a.cb_e = abp.kq_e;
+      a.dst_rows = abp.mp;
+      a.dst_cols = abp.kp;
+      SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream, launch_pad_copy(a, stream));
+      Af = a.dst;
+      lda_f = abp.mp;
+    }
+    if (abp.pb) {
+      PadArgs b;
+      std::memset(&b, 0, sizeof b);
+      b.src = B;
+      b.dst = wsd + abl.b_off;
+      b.ld_s = ldb;
+      b.ld_d = abp.kp;
+      b.rows = k;
+      b.cols = n;
+      b.rb = abp.kq;
+      b.rb_e = abp.kq_e;
+      b.cb = whole_n;
+      b.cb_e = whole_n;
+      b.dst_rows = abp.kp;
+      b.dst_cols = abp.np;
+      SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream, launch_pad_copy(b, stream));
+      Bf = b.dst;
+      ldb_f = abp.kp;
+    }
+    // C is not read or written by the store form; its pointer only fills the arguments
+    const Plan pf = make_plan(abp.mp, abp.np, abp.kp, levels, STRASSEN_ABC);
+    if (int rc = run_all_products(pf, Af, lda_f, Bf, ldb_f, C, ldc, abp.np, alpha, beta,
+                                  abp.stage ? wsd + abl.s_off : nullptr, stream, g.M, p.ldm,
                                   p.m_stride))
       return rc;
   } else {
@@ -965,10 +1030,12 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   }
   const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
   *bytes = (size_t)p.total * sizeof(double);
-  if (variant == STRASSEN_AB && levels == 2 && smx::staging_applies(m, n, k, levels))
-    // the all-products form of AB stages the outer operand sums behind the temporaries
-    *bytes += (size_t)smx::make_stage_plan(smx::make_plan(m, n, k, levels, STRASSEN_ABC)).total *
-              sizeof(double);
+  if (variant == STRASSEN_AB)
+    // the all-products form of AB: padded A and B copies and staged outer sums behind the
+    // temporaries (operands taken as 16-byte aligned with even leading dimensions)
+    *bytes = (size_t)smx::make_ab_layout(p, m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2),
+                                         nullptr, 2 * smx::cdiv(k, 2), -1).total *
+             sizeof(double);
   if (variant == STRASSEN_ABC && levels >= 1) {
     // operands taken as 16-byte aligned with even leading dimensions
     const smx::PadPlan pp = smx::make_pad_plan(m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2),

@@ -101,15 +101,25 @@ def test_workspace_sizes(m, n, k):
             assert sx.workspace_size(m, n, k, levels, "abc") == want
         ab = sx.workspace_size(m, n, k, levels, "ab")
         nprod = 7 ** levels
-        # one M_r per product, leading dimension rounded to 8 doubles, slot to 32; two-level AB
-        # on the all-products kernel also stages the outer sums (where two-level ABC would)
+        # one M_r per product, leading dimension rounded to 8 doubles, slot to 32; AB on the
+        # all-products kernel adds block-padded A and B copies where m or k is not a multiple of
+        # 2^(L+1) and, at two levels, the staged outer sums (where two-level ABC would stage)
         per = _cdiv(_cdiv(mq, 8) * 8 * nq, 32) * 32
-        stage = 0
-        if levels == 2 and n % 4 == 0 and (m // 2) * (n // 2) >= 2048 ** 2 and k >= 2048:
-            r32 = lambda x: _cdiv(x, 32) * 32
-            stage = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
-        assert ab == 8 * nprod * per + stage
-        ab -= stage
+        r32 = lambda x: _cdiv(x, 32) * 32
+        u = 2 * q
+        mp, kp = q * 2 * _cdiv(mq, 2), q * 2 * _cdiv(kq, 2)
+        staged = levels == 2 and (mp // 2) * (_cdiv(n, 4) * 2) >= 2048 ** 2 and kp >= 2048
+        extra = 0
+        if levels == 1 or staged:
+            np_ = 4 * nq if staged and n % 4 else n
+            if m % u or k % u:
+                extra += 8 * r32(mp * kp)
+            if k % u or np_ != n:
+                extra += 8 * r32(kp * np_)
+            if staged:
+                extra += 8 * (5 * r32((mp // 2) * (kp // 2)) + 5 * r32((kp // 2) * (np_ // 2)))
+        assert ab == 8 * nprod * per + extra
+        ab -= extra
         nv = sx.workspace_size(m, n, k, levels, "naive")
         tab = otab.table(levels)
         na = sum(1 for a, _, _ in tab if len(a) > 1 or a[0][1] < 0)

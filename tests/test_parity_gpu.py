@@ -352,9 +352,9 @@ PADDED_CASES = [
 @pytest.mark.parametrize("case", PADDED_CASES)
 def test_block_padded_abc(case):
     """ABC on block-padded copies: the copies run (timing hooks), the result is bitwise that of
-    the unpadded path (the general tile kernel and Naive), exact on integers, within tolerance
-    on reals, C write-only with beta = 0, and a caller workspace too small for the copies gives
-    the same result without them."""
+    the unpadded path (the general tile kernel, Naive, and AB on its padded store form), exact on
+    integers, within tolerance on reals, C write-only with beta = 0, and a caller workspace too
+    small for the copies gives the same result without them."""
     m, n, k, levels, ea, eb, ec, off, cfg = case
     print(f"case padded {case}", flush=True)
     lda, ldb, ldc = m + ea, k + eb, m + ec
@@ -384,6 +384,20 @@ def test_block_padded_abc(case):
         assert np.array_equal(run(Ar, Br, Cn, 0.5, 0.0, levels, "abc", lda, ldb, ldc, off), out0)
         sx.set_tile_config(-1)
         assert np.array_equal(run(Ar, Br, Cr, 0.5, -1.5, levels, "naive", lda, ldb, ldc, off), got)
+        # AB: the store form of the all-products kernel on padded A and B (one level, or two
+        # with the staged outer sums), bitwise the products of the tile kernel
+        sx.set_tile_config(cfg)
+        for kind in sx.KERNEL_KINDS:
+            sx.timing_collect(kind)
+        sx.timing_enable(True)
+        try:
+            got_ab = run(Ar, Br, Cr, 0.5, -1.5, levels, "ab", lda, ldb, ldc, off)
+        finally:
+            sx.timing_enable(False)
+        n_ap_ab = sx.timing_collect("all_products")[1]
+        assert (n_ap_ab >= 1) == (levels == 1 or cfg == 5), n_ap_ab
+        assert np.array_equal(got_ab, got)
+        assert np.array_equal(run(A, B, C, 1.0, 1.0, levels, "ab", lda, ldb, ldc, off), ref)
     finally:
         sx.set_tile_config(-1)
     # a caller workspace too small for the copies: the unpadded path, the same result
