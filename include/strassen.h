@@ -275,10 +275,11 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
  * kernel and tile configuration per call; 0..5 forces one for every later call in the process:
  *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;
  *   2: 128 x 128, k step 8, two workgroups per CU;        3: 128 x 128, k step 16, one per CU;
- *   4: ABC with levels >= 1 runs the all-products kernel (the seven products of a level side
- *      by side on 64 x 64 tiles of the four quadrants) wherever its layout applies (m and k
- *      multiples of 2^(levels+1), 16-byte aligned A, B, C, even leading dimensions), the
- *      default choice otherwise, with the two-level outer sums formed in the load;
+ *   4: ABC and AB with levels >= 1 run the all-products kernel (the seven products of a level
+ *      side by side on 64 x 64 tiles of the four quadrants) on the operands as given where its
+ *      layout applies (m and k multiples of 2^(levels+1), 16-byte aligned operands, even
+ *      leading dimensions), else on block-padded copies as by default; ABC forms the two-level
+ *      outer sums in the load (two-level AB, which needs them staged, runs the tile kernel);
  *   5: as 4, with the two-level outer operand sums staged wherever n % 4 == 0 (the workspace,
  *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise).
  * The default (-1) uses the all-products kernel wherever it applies and stages as described

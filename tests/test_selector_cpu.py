@@ -35,7 +35,7 @@ def test_model_choice_valid_and_strassen_at_large_sizes():
     # at 16384 the measured order (two-level ABC, one-level ABC, classical) is reproduced
     t = _model(16384, 16384, 16384, 0)
     assert t[4] < t[1] < t[0] and S.select(16384, 16384, 16384, 0) == (2, "abc")
-    # where the all-products layout does not apply, ABC runs on the slower general kernel
+    # where the all-products layout does not fit, ABC pays for its block-padded copies
     assert _model(16383, 16384, 16383, 0)[1] > _model(16384, 16384, 16384, 0)[1]
     assert S.select(20000, 20000, 20000, 1)[1] == "abc"
 
