@@ -189,3 +189,32 @@ def test_workspace_size_ex(m, n, k):
         assert sx.workspace_size_ex(m, n, k, levels, "bf16x3") == 4 * nprod * (mp + np_) * kp
     out = ctypes.c_size_t()
     assert sx.lib().strassen_workspace_size_ex(1, 1, 1, 1, 3, ctypes.byref(out)) == -5
+
+
+def test_ab_padded_workspace():
+    """AB on the all-products kernel reports its block-padded A and B copies (A as mp x kp, B as
+    kp x n', every sub-block extent rounded up to even, n' = n rounded up to 4 where two-level
+    staging needs it) and the staged outer sums of the padded problem behind the product
+    temporaries; two levels without staging run the tile kernel and need the temporaries only."""
+    r32 = lambda x: _cdiv(x, 32) * 32
+
+    def temps(m, n, levels):
+        q = 2 ** levels
+        return 8 * 7 ** levels * r32(_cdiv(_cdiv(m, q), 8) * 8 * _cdiv(n, q))
+
+    # one level, m and k not multiples of 4: both operands copied
+    m, n, k = 1001, 777, 333
+    mp, kp = 2 * 2 * _cdiv(_cdiv(m, 2), 2), 2 * 2 * _cdiv(_cdiv(k, 2), 2)
+    assert sx.workspace_size(m, n, k, 1, "ab") == temps(m, n, 1) + 8 * (r32(mp * kp) + r32(kp * n))
+    # one level, only k ragged in the sense of the layout (k % 4 == 2): A and B copied
+    m, n, k = 1000, 777, 1026
+    kp = 2 * 2 * _cdiv(_cdiv(k, 2), 2)
+    assert sx.workspace_size(m, n, k, 1, "ab") == temps(m, n, 1) + 8 * (r32(m * kp) + r32(kp * n))
+    # two levels staged, n % 4 == 2: B copied with n rounded up to 4, A used in place
+    m, n, k = 8192, 8190, 8192
+    n4 = 4 * _cdiv(n, 4)
+    want = temps(m, n, 2) + 8 * (r32(k * n4) + 5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n4 // 2)))
+    assert sx.workspace_size(m, n, k, 2, "ab") == want
+    # two levels where staging does not apply: the tile kernel, temporaries only
+    for m, n, k in [(1001, 777, 333), (2048, 4096, 4096)]:
+        assert sx.workspace_size(m, n, k, 2, "ab") == temps(m, n, 2)
