@@ -82,9 +82,11 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * The general operation is eq. (e:straprim1) at one level and eq. (e:straprim3) at two.
  * AB runs its products on the fused kernel of ABC, stored to the temporaries instead of added to
  * C (one level; two levels over staged outer sums), on block-padded copies of A and B where
- * their layout does not fit that kernel (as ABC below; C is updated in place by the assembly),
- * else on the general tile kernel (a tile configuration 0..3 forces it, or a caller workspace
- * too small for the copies and staging); the results are the same bits.
+ * their layout does not fit that kernel (as ABC below; C is updated in place by the assembly)
+ * and a launch has at least 192 tile positions of 64 x 64 (below that the general tile kernel
+ * is faster than the copies), else on the general tile kernel (also where a tile configuration
+ * 0..3 forces it, or a caller workspace is too small for the copies and staging); the results
+ * are the same bits.
  * AB and NAIVE use a library-owned workspace (grown on demand, kept until
  * strassen_release_workspace or process exit) unless strassen_set_workspace gave one;
  * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 3.3).  Two-level ABC

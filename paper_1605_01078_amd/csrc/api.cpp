@@ -592,7 +592,13 @@ static int run_padded(const PadPlan& pp, int levels, int64_t m, int64_t n, int64
 // kernel's layout (C is no operand of the fused loop); the temporaries keep the real problem's
 // leading dimension, which is at least the padded sub-block extent, so the padded rows land
 // outside the part the assembly reads.  Two levels need the staged outer sums (one term per
-// side).  Offsets are in doubles, behind the temporaries of `p`.
+// side).  By default the copies are made only where a launch has at least kAbPadMinTiles
+// 64 x 64 tile positions (three quarters of MI355X's 256 CUs at one 512-thread workgroup each):
+// on 500 ragged shapes (m, n, k log-uniform in 256..20000) the copies plus the fused kernel
+// were up to 3x slower than the tile kernel below that and up to 1.25x faster above it.
+// Offsets are in doubles, behind the temporaries of `p`.
+constexpr int64_t kAbPadMinTiles = 192;
+
 struct AbLayout {
   PadPlan pp;
   bool fused = false;
@@ -609,6 +615,8 @@ static AbLayout make_ab_layout(const Plan& p, int64_t m, int64_t n, int64_t k, i
   l.pp = make_pad_plan(m, n, k, levels, A, lda, B, ldb, nullptr, 2 * cdiv(m, 2), forced);
   if (!l.pp.ok || (levels == 2 && !l.pp.stage) || 8 * 64 * p.ldm >= (int64_t(1) << 31))
     return l;
+  const int64_t positions = cdiv(l.pp.mq_e, 64) * cdiv(l.pp.nq, 64);   // per launch
+  if (forced == -1 && (l.pp.pa || l.pp.pb) && positions < kAbPadMinTiles) return l;
   int64_t off = p.total;
   l.a_off = off;
   if (l.pp.pa) off += round_up(l.pp.mp * l.pp.kp, 32);

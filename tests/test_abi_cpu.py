@@ -109,8 +109,11 @@ def test_workspace_sizes(m, n, k):
         u = 2 * q
         mp, kp = q * 2 * _cdiv(mq, 2), q * 2 * _cdiv(kq, 2)
         staged = levels == 2 and (mp // 2) * (_cdiv(n, 4) * 2) >= 2048 ** 2 and kp >= 2048
+        # copies are made only where a launch has at least 192 tile positions of 64 x 64
+        positions = _cdiv(2 * _cdiv(mq, 2), 64) * _cdiv(nq, 64)
+        copies = bool(m % u or k % u or (staged and n % 4))
         extra = 0
-        if levels == 1 or staged:
+        if (levels == 1 or staged) and (not copies or positions >= 192):
             np_ = 4 * nq if staged and n % 4 else n
             if m % u or k % u:
                 extra += 8 * r32(mp * kp)
@@ -195,21 +198,26 @@ def test_ab_padded_workspace():
     """AB on the all-products kernel reports its block-padded A and B copies (A as mp x kp, B as
     kp x n', every sub-block extent rounded up to even, n' = n rounded up to 4 where two-level
     staging needs it) and the staged outer sums of the padded problem behind the product
-    temporaries; two levels without staging run the tile kernel and need the temporaries only."""
+    temporaries, where a launch has at least 192 tile positions; two levels without staging and
+    smaller padded problems run the tile kernel and need the temporaries only."""
     r32 = lambda x: _cdiv(x, 32) * 32
 
     def temps(m, n, levels):
         q = 2 ** levels
         return 8 * 7 ** levels * r32(_cdiv(_cdiv(m, q), 8) * 8 * _cdiv(n, q))
 
-    # one level, m and k not multiples of 4: both operands copied
-    m, n, k = 1001, 777, 333
+    # one level, m and k not multiples of 4: both operands copied (528 tile positions)
+    m, n, k = 3001, 2777, 1333
     mp, kp = 2 * 2 * _cdiv(_cdiv(m, 2), 2), 2 * 2 * _cdiv(_cdiv(k, 2), 2)
     assert sx.workspace_size(m, n, k, 1, "ab") == temps(m, n, 1) + 8 * (r32(mp * kp) + r32(kp * n))
     # one level, only k ragged in the sense of the layout (k % 4 == 2): A and B copied
-    m, n, k = 1000, 777, 1026
+    m, n, k = 3000, 2777, 1026
     kp = 2 * 2 * _cdiv(_cdiv(k, 2), 2)
     assert sx.workspace_size(m, n, k, 1, "ab") == temps(m, n, 1) + 8 * (r32(m * kp) + r32(kp * n))
+    # fewer than 192 tile positions of 64 x 64 per launch (here 56): no copies, the tile kernel
+    assert sx.workspace_size(1001, 777, 333, 1, "ab") == temps(1001, 777, 1)
+    # but operands that fit the layout run the fused kernel at any size, with no copies
+    assert sx.workspace_size(1000, 776, 332, 1, "ab") == temps(1000, 776, 1)
     # two levels staged, n % 4 == 2: B copied with n rounded up to 4, A used in place
     m, n, k = 8192, 8190, 8192
     n4 = 4 * _cdiv(n, 4)
