@@ -420,6 +420,30 @@ def test_block_padded_abc(case):
         sx.set_workspace(None)
 
 
+def test_ab_padded_by_default_from_192_positions():
+    """AB by default: ragged problems with at least 192 tile positions of 64 x 64 per launch run
+    the store form on block-padded A and B, smaller ones the tile kernel; both give the bits of
+    ABC, within tolerance of the oracle and exact on integers."""
+    for (m, n, k), fused in [((3001, 2777, 1333), True), ((1001, 777, 333), False)]:
+        print(f"case ab default padded {(m, n, k)}", flush=True)
+        A, B, C = W.problem(43, m, n, k, "uniform")
+        ref = oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0)
+        Ai, Bi, Ci = W.problem(44, m, n, k, "integer")
+        refi = oracle_dgemm(Ai, Bi, Ci.copy(order="F"), 1.0, 1.0)
+        for kind in sx.KERNEL_KINDS:
+            sx.timing_collect(kind)
+        sx.timing_enable(True)
+        try:
+            got = run(A, B, C, 1.0, 1.0, 1, "ab")
+        finally:
+            sx.timing_enable(False)
+        assert (sx.timing_collect("all_products")[1] >= 1) == fused
+        assert (sx.timing_collect("pad")[1] >= 2) == fused
+        assert rel_fro(got, ref) <= TOL[1]
+        assert np.array_equal(got, run(A, B, C, 1.0, 1.0, 1, "abc"))
+        assert np.array_equal(run(Ai, Bi, Ci, 1.0, 1.0, 1, "ab"), refi)
+
+
 def test_probe_rates():
     """The matrix-core rate probe: FP64 and BF16 issue rates between half and 105% of the
     datasheet peaks (78.6 and 2500 TFLOP/s)."""
