@@ -113,8 +113,10 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
 /*
  * strassen_workspace_size — bytes of device workspace strassen_dgemm needs for these sizes
  * (0 for levels 0).  AB: one M_r temporary per product (7^L of ceil(m/2^L) x ceil(n/2^L)
- * doubles, leading dimension rounded up to 8, each slot to 32), plus at two levels the staging
- * buffers below where two-level ABC would stage; NAIVE adds the operand-sum temporaries.  ABC, for 16-byte aligned operands with
+ * doubles, leading dimension rounded up to 8, each slot to 32), plus, where AB runs the fused
+ * kernel (see strassen_dgemm), the block-padded A and B copies described below for ABC (where
+ * m or k is not a multiple of 2^(L+1)) and at two levels the staging buffers of the (padded)
+ * problem; NAIVE adds the operand-sum temporaries.  ABC, for 16-byte aligned operands with
  * even leading dimensions: where m, k are multiples of 2^(L+1) (and, for two levels, n of 4 or
  * no staging), 0 at one level and at two the staging buffers of its outer operand sums where
  * staging is the default (five m/2 x k/2 and five k/2 x n/2 slots, each rounded up to 32
