@@ -8,8 +8,8 @@ uniform on [-1, 1], inputs resident in HBM) with `levels` levels of Strassen in 
 one per outer product).  Printed as ONE JSON line:
 the headline value plus, measured in the same run,
   * the library's own classical FP64 MFMA GEMM (levels = 0) and every (levels, variant) pair,
-    timed with HIP events, with the speedup over classical; classical and the headline member
-    at n - 1 (`ragged`: sub-block extents odd, ABC on block-padded copies);
+    timed with HIP events, with the speedup over classical; classical, the headline member
+    and AB at n - 1 (`ragged`: sub-block extents odd, ABC and AB on block-padded copies);
   * the relative Frobenius error of the headline result against the CPU oracle on sampled
     columns (and of the classical result), checked against 1e-12 (one level) / 1e-11 (two);
   * roofline of the dominant kernel (the all-products kernel for ABC, the FP64 tile kernel
@@ -588,20 +588,22 @@ def main():
         vendor = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
         log(f"  vendor BLAS FP64 GEMM (torch.matmul), context: {ms:8.3f} ms")
         del Cv, Ac, Bc
-        # a size that does not split evenly (n - 1: every sub-block extent odd), classical and
-        # the headline member; ABC runs on block-padded copies (copy time included)
+        # a size that does not split evenly (n - 1: every sub-block extent odd), classical, the
+        # headline member and AB at its level; ABC and AB run on block-padded copies (copy time
+        # included)
         r = n - 1
         rflops = 2.0 * r * r * r
         Ar, Br, Cr = A[:r, :r], B[:r, :r], Cw[:r, :r]
         ragged = {"m": r, "n": r, "k": r}
-        for lev in (0, L):
-            f = lambda lev=lev: sx.dgemm(Ar, Br, Cr, 1.0, 1.0, lev, variant if lev else "abc", stream)
+        ragged_runs = [(0, "abc"), (L, variant)] + ([(L, "ab")] if L and variant != "ab" else [])
+        for lev, var in ragged_runs:
+            f = lambda lev=lev, var=var: sx.dgemm(Ar, Br, Cr, 1.0, 1.0, lev, var, stream)
             f()
             torch.cuda.synchronize()
             ms, _ = timed(f, 3, stream)
-            ragged[f"L{lev}_{variant if lev else 'abc'}"] = {
+            ragged[f"L{lev}_{var}"] = {
                 "ms": round(ms, 3), "tflops": round(rflops / (ms * 1e-3) * 1e-12, 2)}
-            log(f"  {r}^3 L={lev}: {ms:8.3f} ms")
+            log(f"  {r}^3 L={lev} {var}: {ms:8.3f} ms")
         ragged["speedup_vs_classical"] = round(ragged[f"L{L}_{variant}"]["tflops"] /
                                                ragged["L0_abc"]["tflops"], 4)
         base = variants["L0_abc"]["tflops"]
