@@ -89,8 +89,9 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * are the same bits.
  * AB and NAIVE use a library-owned workspace (grown on demand, kept until
  * strassen_release_workspace or process exit) unless strassen_set_workspace gave one;
- * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 3.3).  Two-level ABC
- * may use one to stage its outer-level operand sums (the ten two-term sums of the one-level
+ * strassen_workspace_size reports its size.  ABC needs no workspace (Sec. 4.1): it can always
+ * run without one, and only uses one where it is available, to stage its outer-level operand
+ * sums at two levels (the ten two-term sums of the one-level
  * table over the 2 x 2 outer blocks, formed once by a streaming pass; the seven outer products
  * then run the one-level fused kernel on them and update C in place, bitwise as without
  * staging): by default where (m/2)(n/2) >= 2048^2 and k >= 2048 and a library-owned or large
@@ -101,7 +102,15 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * partition is stored with an even extent, the extra rows and columns zero, and C is copied
  * back.  The result is bitwise that of the unpadded computation; the copies take workspace
  * (reported by strassen_workspace_size for aligned operands with even leading dimensions) and
- * are skipped, with the same result, when a caller workspace is too small for them.
+ * are skipped, with the same result, when a caller workspace is too small for them, when
+ * they would exceed the limit of strassen_set_workspace_limit, or when the library-owned
+ * allocation fails: ABC then runs its workspace-free path (the all-products kernel in place,
+ * with the two-level outer sums formed in the load, or the general tile kernel).
+ * The general tile kernel (classical levels = 0, AB and Naive where they do not run the fused
+ * kernel, and ABC where neither fused form applies) addresses each tile with 32-bit byte
+ * offsets: a leading dimension of 2^21 - 1 or more on such a path returns
+ * STRASSEN_ERR_UNSUPPORTED before anything is enqueued (decided on the host, before any device
+ * call); the fused paths accept leading dimensions up to their block-padded copies' limits.
  * Argument positions for -i: m=1 n=2 k=3 alpha=4 A=5 lda=6 B=7 ldb=8 beta=9 C=10 ldc=11
  * levels=12 variant=13.
  */
@@ -141,6 +150,16 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
  * Returns 0, -1 (misaligned ptr) or -2 (ptr != NULL with bytes == 0).
  */
 int strassen_set_workspace(void *ptr, size_t bytes);
+
+/*
+ * strassen_set_workspace_limit — cap the library-owned workspace at `bytes` (0 = no cap, the
+ * default) for memory-constrained callers.  A call needing more behaves as if the allocation
+ * failed: ABC drops its block-padded copies or staging (same result, workspace-free path),
+ * AB, NAIVE and strassen_gemm_ex fail with STRASSEN_ERR_ALLOC without touching C.  A buffer
+ * already allocated is kept (strassen_release_workspace frees it).  No effect on a caller
+ * workspace set by strassen_set_workspace.  Returns 0.
+ */
+int strassen_set_workspace_limit(size_t bytes);
 
 /* strassen_release_workspace — synchronise the device and free the library-owned workspace. */
 int strassen_release_workspace(void);

@@ -49,6 +49,8 @@ def lib():
         L.strassen_workspace_size_ex.restype = ci
         L.strassen_set_workspace.argtypes = [vp, ctypes.c_size_t]
         L.strassen_set_workspace.restype = ci
+        L.strassen_set_workspace_limit.argtypes = [ctypes.c_size_t]
+        L.strassen_set_workspace_limit.restype = ci
         L.strassen_release_workspace.argtypes = []
         L.strassen_release_workspace.restype = ci
         L.strassen_table_size.argtypes = [ci]
@@ -240,6 +242,11 @@ def set_workspace(tensor_or_none):
     else:
         t = tensor_or_none
         check(lib().strassen_set_workspace(t.data_ptr(), t.numel() * t.element_size()))
+
+
+def set_workspace_limit(nbytes):
+    """Cap the library-owned workspace at `nbytes` (0 or None: no cap)."""
+    check(lib().strassen_set_workspace_limit(int(nbytes or 0)))
 
 
 def set_tile_config(cfg):

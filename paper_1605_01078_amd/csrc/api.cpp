@@ -141,16 +141,15 @@ int device_ready(int* dev_out) {
   return 0;
 }
 
-// Device workspace of at least `bytes`: caller-provided if set, else the library's own.
-static int get_workspace(int dev, size_t bytes, void** out) {
+// Library-owned workspace of at least `bytes` on device `dev` (grown on demand, capped by
+// strassen_set_workspace_limit).
+static size_t g_ws_limit = SIZE_MAX;
+
+static int library_workspace(int dev, size_t bytes, void** out) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (g_user_ws) {
-    if (bytes > g_user_ws_bytes)
-      return fail(STRASSEN_ERR_ALLOC, "caller workspace has %zu bytes, %zu needed",
-                  g_user_ws_bytes, bytes);
-    *out = g_user_ws;
-    return 0;
-  }
+  if (bytes > g_ws_limit)
+    return fail(STRASSEN_ERR_ALLOC, "workspace of %zu bytes exceeds the limit of %zu bytes", bytes,
+                g_ws_limit);
   DeviceState& d = g_dev[dev];
   if (d.ws_bytes < bytes) {
     if (d.ws) {
@@ -162,12 +161,42 @@ static int get_workspace(int dev, size_t bytes, void** out) {
     hipError_t e = hipMalloc(&d.ws, bytes);
     if (e != hipSuccess) {
       d.ws = nullptr;
+      (void)hipGetLastError();   // an allocation failure is not sticky; clear it
       return fail(STRASSEN_ERR_ALLOC, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
     }
     d.ws_bytes = bytes;
   }
   *out = d.ws;
   return 0;
+}
+
+WsSource default_workspace() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  WsSource w;
+  if (g_user_ws) {
+    w.fixed = true;
+    w.ptr = g_user_ws;
+    w.bytes = g_user_ws_bytes;
+  } else {
+    w.bytes = g_ws_limit;
+  }
+  return w;
+}
+
+// Device workspace of at least `bytes` from `src`: a fixed buffer (the caller's or the static
+// scratch) if it is large enough, else the library's own.
+static int get_workspace(const WsSource& src, int dev, size_t bytes, void** out) {
+  if (src.fixed) {
+    if (bytes > src.bytes)
+      return fail(STRASSEN_ERR_ALLOC, "%s has %zu bytes, %zu needed",
+                  src.what ? src.what : "caller workspace", src.bytes, bytes);
+    void* ptr = src.ptr;
+    if (!ptr && src.resolve)
+      if (int rc = src.resolve(dev, &ptr)) return rc;
+    *out = ptr;
+    return 0;
+  }
+  return library_workspace(dev, bytes, out);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -325,11 +354,6 @@ static StagePlan make_stage_plan(const Plan& p) {
 // 16384 with k = 8192); below that the default stays unstaged.
 static bool staging_applies(int64_t m, int64_t n, int64_t k, int levels) {
   return levels == 2 && n % 4 == 0 && (m / 2) * (n / 2) >= int64_t(2048) * 2048 && k >= 2048;
-}
-
-static bool user_workspace_below(size_t bytes) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return g_user_ws != nullptr && g_user_ws_bytes < bytes;
 }
 
 // The all-products launches of ABC: one at one level; at two, one per outer product of the
@@ -673,20 +697,35 @@ static int run_scale(double* C, int64_t ldc, int64_t m, int64_t n, double beta, 
   return 0;
 }
 
+// Whether the general tile kernel's 32-bit lane offsets reach every element of its tiles: a
+// tile spans at most 128 columns of B, C and the temporaries and 16 of A (8 bytes each), and
+// each access is one wave-uniform base plus a per-lane offset below 2^31 bytes.
+static bool tile_offsets_fit(int64_t lda, int64_t ldb, int64_t ldc, int64_t ldm) {
+  const int64_t ld = std::max(std::max(lda, ldb), std::max(ldc, ldm));
+  return 8 * 128 * (ld + 1) < (int64_t(1) << 31);
+}
+
+static int tile_offsets_error() {
+  return fail(STRASSEN_ERR_UNSUPPORTED,
+              "a leading dimension of 2^21 - 1 or more on a path that runs the general tile kernel "
+              "(128 columns would span 2 GiB past its 32-bit lane offsets)");
+}
+
 int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
-          int variant, hipStream_t stream) {
+          int variant, const WsSource& wsrc, hipStream_t stream) {
   g_last_error.clear();
   if (int rc = validate(m, n, k, alpha, A, lda, B, ldb, C, ldc, levels, variant)) return rc;
   if (m == 0 || n == 0) return 0;
-  int dev = 0;
-  if (int rc = device_ready(&dev)) return rc;
   if (alpha == 0.0 || k == 0) {
     if (beta == 1.0) return 0;
+    int dev = 0;
+    if (int rc = device_ready(&dev)) return rc;
     return run_scale(C, ldc, m, n, beta, stream);
   }
   const Plan p = make_plan(m, n, k, levels, variant);
   const int64_t tiles_limit = 1ll << 30;
+  const int forced = g_forced_cfg.load(std::memory_order_relaxed);
 
   GemmArgs g;
   std::memset(&g, 0, sizeof g);
@@ -710,31 +749,49 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
              k % 2 == 0 && p.mq % 2 == 0 && p.kq % 2 == 0;
 
   if (p.variant == STRASSEN_ABC) {
-    const int forced = g_forced_cfg.load(std::memory_order_relaxed);
+    // Route (decided on the host): block-padded copies for the all-products kernel where its
+    // layout does not fit the operands as given and the workspace allows them, else the
+    // all-products kernel in place, else the general tile kernel.  ABC needs no workspace: a
+    // workspace that is too small or cannot be allocated only drops the copies or the staging.
     const bool all_products = forced == -1 || forced == kCfgAll || forced == kCfgAllStaged;
+    PadPlan pp;
+    bool padded = false;
     if (all_products && levels >= 1) {
-      const PadPlan pp = make_pad_plan(m, n, k, levels, A, lda, B, ldb, C, ldc, forced);
-      const size_t bytes = (size_t)pp.total * sizeof(double);
-      // a caller workspace too small for the copies: the unpadded path below (same result)
-      if ((pp.pa || pp.pb || pp.pc) && pp.ok && !user_workspace_below(bytes)) {
-        void* ws = nullptr;
-        if (int rc = get_workspace(dev, bytes, &ws)) return rc;
+      pp = make_pad_plan(m, n, k, levels, A, lda, B, ldb, C, ldc, forced);
+      padded = (pp.pa || pp.pb || pp.pc) && pp.ok && wsrc.fits((size_t)pp.total * sizeof(double));
+    }
+    const bool in_place = all_products && all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels);
+    const bool tile_ok = tile_offsets_fit(lda, ldb, ldc, 0);
+    if (!padded && !in_place && !tile_ok) return tile_offsets_error();
+    int dev = 0;
+    if (int rc = device_ready(&dev)) return rc;
+    if (padded) {
+      void* ws = nullptr;
+      const int rc = get_workspace(wsrc, dev, (size_t)pp.total * sizeof(double), &ws);
+      if (rc == 0)
         return run_padded(pp, levels, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                           static_cast<double*>(ws), stream);
-      }
+      // the library-owned allocation failed: the workspace-free path below (same result)
+      if (wsrc.fixed) return rc;
+      if (!in_place && !tile_ok) return tile_offsets_error();
+      g_last_error.clear();
     }
-    if (all_products && all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels)) {
+    if (in_place) {
       double* stage = nullptr;
       const bool want = levels == 2 && n % 4 == 0 &&
                         (forced == kCfgAllStaged ||
                          (forced == -1 && staging_applies(m, n, k, levels)));
       if (want) {
         const size_t bytes = (size_t)make_stage_plan(p).total * sizeof(double);
-        // a caller workspace too small for the staging buffers: form the sums in the load
-        if (forced == kCfgAllStaged || !user_workspace_below(bytes)) {
+        // a workspace too small for the staging buffers: form the sums in the load
+        if (forced == kCfgAllStaged || wsrc.fits(bytes)) {
           void* ws = nullptr;
-          if (int rc = get_workspace(dev, bytes, &ws)) return rc;
-          stage = static_cast<double*>(ws);
+          if (int rc = get_workspace(wsrc, dev, bytes, &ws)) {
+            if (forced == kCfgAllStaged || wsrc.fixed) return rc;
+            g_last_error.clear();
+          } else {
+            stage = static_cast<double*>(ws);
+          }
         }
       }
       return run_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta, stage, stream);
@@ -749,16 +806,32 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     return 0;
   }
 
-  // AB on the all-products kernel where it applies (block-padded A and B where needed)
+  // AB on the all-products kernel where it applies (block-padded A and B where needed), else
+  // AB and Naive on the tile kernel (StoreM) over the operands or Naive's temporaries
   AbLayout abl;
-  if (p.variant == STRASSEN_AB)
-    abl = make_ab_layout(p, m, n, k, levels, A, lda, B, ldb,
-                         g_forced_cfg.load(std::memory_order_relaxed));
-  const bool ab_fused = abl.fused && !user_workspace_below((size_t)abl.total * sizeof(double));
+  if (p.variant == STRASSEN_AB) abl = make_ab_layout(p, m, n, k, levels, A, lda, B, ldb, forced);
+  bool ab_fused = abl.fused && wsrc.fits((size_t)abl.total * sizeof(double));
+  const bool tile_ok = tile_offsets_fit(lda, ldb, 0, std::max(p.ldm, std::max(p.mq, p.kq)));
+  if (!ab_fused && !tile_ok) return tile_offsets_error();
+  if (!wsrc.fits((size_t)p.total * sizeof(double)))
+    return fail(STRASSEN_ERR_ALLOC, "%s has %zu bytes, %zu needed",
+                wsrc.fixed ? (wsrc.what ? wsrc.what : "caller workspace") : "the workspace limit",
+                wsrc.bytes, (size_t)p.total * sizeof(double));
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
   const PadPlan& abp = abl.pp;
-  const size_t ws_doubles = (size_t)(ab_fused ? abl.total : p.total);
   void* ws = nullptr;
-  if (int rc = get_workspace(dev, ws_doubles * sizeof(double), &ws)) return rc;
+  if (ab_fused) {
+    if (int rc = get_workspace(wsrc, dev, (size_t)abl.total * sizeof(double), &ws)) {
+      // the library-owned allocation failed: the tile kernel needs only the temporaries
+      if (wsrc.fixed) return rc;
+      if (!tile_ok) return tile_offsets_error();
+      ab_fused = false;
+      g_last_error.clear();
+    }
+  }
+  if (!ab_fused)
+    if (int rc = get_workspace(wsrc, dev, (size_t)p.total * sizeof(double), &ws)) return rc;
   double* wsd = static_cast<double*>(ws);
   g.M = wsd + p.off_m;
   g.ldm = p.ldm;
@@ -921,7 +994,8 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   if (sum_prec < 0 || sum_prec > 1) return fail(-15, "sum_prec = %d not in 0..1", sum_prec);
   if (c_prec < 0 || c_prec > 1) return fail(-16, "c_prec = %d not in 0..1", c_prec);
   if (compute == STRASSEN_COMPUTE_F64)
-    return dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant, stream);
+    return dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant,
+                 default_workspace(), stream);
   if (variant != STRASSEN_ABC)
     return fail(-13, "the reduced-precision mode runs the ABC variant only (variant = %d)", variant);
   if (m == 0 || n == 0) return 0;
@@ -936,7 +1010,7 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   if (2 * p.slot_a >= lim || 2 * p.slot_b >= lim || 8 * 128 * ldc >= lim)
     return fail(STRASSEN_ERR_UNSUPPORTED, "reduced-precision operands past the 32-bit offset range");
   void* ws = nullptr;
-  if (int rc = get_workspace(dev, p.bytes, &ws)) return rc;
+  if (int rc = get_workspace(default_workspace(), dev, p.bytes, &ws)) return rc;
   uint16_t* w = static_cast<uint16_t*>(ws);
   uint16_t* TAh = w;
   uint16_t* TBh = TAh + p.slot_a * p.nslots;
@@ -1020,7 +1094,7 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* 
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
                    int variant, void* stream) {
   return smx::dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant,
-                    static_cast<hipStream_t>(stream));
+                    smx::default_workspace(), static_cast<hipStream_t>(stream));
 }
 
 int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int variant,
@@ -1064,6 +1138,13 @@ int strassen_set_workspace(void* ptr, size_t bytes) {
   std::lock_guard<std::mutex> lk(smx::g_mu);
   smx::g_user_ws = ptr;
   smx::g_user_ws_bytes = ptr ? bytes : 0;
+  return 0;
+}
+
+int strassen_set_workspace_limit(size_t bytes) {
+  smx::g_last_error.clear();
+  std::lock_guard<std::mutex> lk(smx::g_mu);
+  smx::g_ws_limit = bytes == 0 ? SIZE_MAX : bytes;
   return 0;
 }
 

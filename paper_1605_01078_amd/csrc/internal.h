@@ -25,6 +25,30 @@ const TableDev* host_tables();
 // Current device checked (gfx950) and its constant tables uploaded; returns 0 or an error code.
 int device_ready(int* dev_out);
 
+// Where a call's workspace comes from.  fixed: the buffer [ptr, ptr + bytes) (a caller's
+// workspace, or the library's static scratch), nothing is allocated; otherwise the
+// library-owned workspace, grown on demand up to `bytes` (the limit).  fits(b): a workspace of
+// b bytes can be had without exceeding the buffer or the limit (a library-owned allocation can
+// still fail).
+struct WsSource {
+  bool fixed = false;
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  const char* what = nullptr;   // name used in error messages (fixed buffers)
+  // fixed buffer whose device address is resolved on first use (ptr == nullptr), on the
+  // current device
+  int (*resolve)(int dev, void** ptr) = nullptr;
+  bool fits(size_t b) const { return b <= bytes; }
+};
+// The workspace of the ordinary entry points: the caller's (strassen_set_workspace) if set,
+// else library-owned under the current limit.
+WsSource default_workspace();
+
+// C := alpha*A*B + beta*C (strassen_dgemm) with its workspace taken from `ws`.
+int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+          const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
+          int variant, const WsSource& ws, hipStream_t stream);
+
 // One launch of the all-products kernel (operand terms per side: na, nb).
 struct ApLaunch {
   FusedArgs f;

@@ -226,3 +226,47 @@ def test_ab_padded_workspace():
     # two levels where staging does not apply: the tile kernel, temporaries only
     for m, n, k in [(1001, 777, 333), (2048, 4096, 4096)]:
         assert sx.workspace_size(m, n, k, 2, "ab") == temps(m, n, 2)
+
+
+def _no_gpu():
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+TILE_LD = 2 ** 21 - 1   # 8 * 128 * (ld + 1) reaches 2^31: the tile kernel's lane offsets overflow
+
+
+@pytest.mark.parametrize("levels,variant,which", [
+    (0, 0, "ldb"), (0, 0, "ldc"), (0, 0, "lda"),        # classical: the tile kernel
+    (1, 2, "lda"), (2, 2, "ldb"),                        # Naive: tile kernel over temporaries
+    (1, 1, "ldb"),                                        # AB below 192 positions: tile kernel
+])
+def test_tile_kernel_offset_guard_is_host_side(levels, variant, which):
+    """Leading dimensions whose 128 columns span 2 GiB are refused with STRASSEN_ERR_UNSUPPORTED
+    on every path that runs the general tile kernel, before any device call (this machine may
+    have no GPU: the code must not be STRASSEN_ERR_NO_DEVICE)."""
+    m = n = k = 64
+    ld = {"lda": m, "ldb": k, "ldc": m}
+    ld[which] = TILE_LD
+    fake = 1 << 20   # never dereferenced: the call is refused on the host
+    rc = sx.raw_dgemm(m, n, k, 1.0, fake, ld["lda"], fake, ld["ldb"], 1.0, fake, ld["ldc"],
+                      levels, variant, None)
+    assert rc == 3, (rc, sx.last_error())
+    assert "tile kernel" in sx.last_error()
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="with a GPU this call would launch on fake pointers")
+def test_tile_kernel_offset_guard_boundary():
+    """One below the limit the call passes the host checks and reaches the device check."""
+    fake = 1 << 20
+    rc = sx.raw_dgemm(64, 64, 64, 1.0, fake, 64, fake, TILE_LD - 1, 1.0, fake, 64, 0, 0, None)
+    assert rc == 4, (rc, sx.last_error())   # STRASSEN_ERR_NO_DEVICE on a machine without GPU
+
+
+def test_workspace_limit_entry_point():
+    L = sx.lib()
+    assert L.strassen_set_workspace_limit(1 << 20) == 0
+    assert L.strassen_set_workspace_limit(0) == 0   # no cap

@@ -180,6 +180,34 @@ def test_caller_workspace():
         sx.set_workspace(None)
 
 
+@pytest.mark.parametrize("levels", [1, 2])
+def test_workspace_limit_abc_falls_back_ab_refuses(levels):
+    """A cap on the library-owned workspace below what the block-padded copies (ragged shape)
+    need: ABC runs its workspace-free path and gives the same bits; AB, whose temporaries the
+    cap does not allow, fails with STRASSEN_ERR_ALLOC and leaves C untouched."""
+    m, n, k = 300, 260, 270
+    print(f"case workspace limit L={levels}", flush=True)
+    A, B, C = W.problem(12, m, n, k, "uniform")
+    free = run(A, B, C, 0.5, -1.5, levels, "abc")
+    sx.release_workspace()
+    sx.set_workspace_limit(4096)
+    try:
+        capped = run(A, B, C, 0.5, -1.5, levels, "abc")
+        assert np.array_equal(capped, free)
+        Ai, Bi, Ci = W.problem(13, m, n, k, "integer")
+        ref = oracle_dgemm(Ai, Bi, Ci.copy(order="F"), 1.0, 1.0)
+        assert np.array_equal(run(Ai, Bi, Ci, 1.0, 1.0, levels, "abc"), ref)
+        dA, dB, dC = sx.to_device(A), sx.to_device(B), sx.to_device(C)
+        with pytest.raises(sx.StrassenError) as ei:
+            sx.dgemm(dA, dB, dC, 1.0, 1.0, levels, "ab")
+        assert ei.value.code == 2
+        torch.cuda.synchronize()
+        assert np.array_equal(sx.to_host(dC), C)
+    finally:
+        sx.set_workspace_limit(0)
+    assert np.array_equal(run(A, B, C, 0.5, -1.5, levels, "ab"), free)
+
+
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("levels", [0, 1, 2])
 def test_every_tile_config_bitwise_and_exact(cfg, levels):
