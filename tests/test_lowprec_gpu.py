@@ -4,8 +4,12 @@ against the CPU oracle of the same mode (oracle/lowprec.py) and the FP64 oracle.
   * small-integer inputs: every step is exact, so every mode must return the exact product
     (bit-exact against the FP64 oracle);
   * real inputs: |C_gpu - C_mode_oracle| <= the oracle's elementwise bound, which allows for
-    FP32 accumulation in any order and the fused multiply-add of the update (the operands
-    themselves, sums and bf16 rounding, must be identical on both sides).
+    FP32 accumulation in any order and the fused multiply-add of the update;
+  * the operands themselves (sums and bf16 rounding) must be identical on both sides:
+    test_operand_pass_bitwise reads the GPU's hi / lo operands back from a caller workspace and
+    compares them bit for bit with the oracle's (the bound alone would let a truncating split
+    or sums in the wrong precision through; tests/test_oracle_lowprec.py measures which
+    planted mistakes each check catches).
 """
 import numpy as np
 import pytest
@@ -109,3 +113,50 @@ def test_product_tile_widths_bitwise(levels, compute):
     finally:
         sx.set_tile_config(-1)
     assert np.array_equal(outs[0], outs[1])
+
+
+def _bf16_bits(x32):
+    """Upper 16 bits of float32 values that are exact bf16 values."""
+    return (np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("sum_prec", ["f32", "f64"])
+@pytest.mark.parametrize("kind", ["uniform", "wide_both"])
+def test_operand_pass_bitwise(levels, sum_prec, kind):
+    """The bf16 operands the GPU forms (hi and lo of every product's A-side and B-side sum) are
+    read from a caller workspace in the layout strassen_workspace_size_ex documents and compared
+    bit for bit with the oracle's operand_sum + split_hi_lo (round to nearest even), padding
+    zero.  This pins what the result bound cannot see: a truncating split or sums in the wrong
+    precision stay inside that bound (tests/test_oracle_lowprec.py)."""
+    from oracle.lowprec import operand_sum, split_hi_lo
+    from oracle.tables import table
+    m, n, k = 300, 260, 270
+    print(f"case operand pass L={levels} {sum_prec} {kind}", flush=True)
+    A, B, C = W.problem(61, m, n, k, kind)
+    q = 2 ** levels
+    mq, nq, kq = -(-m // q), -(-n // q), -(-k // q)
+    mp, np_, kp = -(-mq // 128) * 128, -(-nq // 128) * 128, -(-kq // 64) * 64
+    nprod = 7 ** levels
+    need = sx.workspace_size_ex(m, n, k, levels, "bf16x3")
+    assert need == 4 * nprod * (mp + np_) * kp
+    ws = torch.full((need // 2 + 128,), -1, dtype=torch.int16, device="cuda")
+    sx.set_workspace(ws)
+    try:
+        run_ex(A, B, C, 1.0, 1.0, levels, ("bf16x3", sum_prec, "f64"))
+        raw = ws.cpu().numpy().view(np.uint16)
+    finally:
+        sx.set_workspace(None)
+    sa, sb = mp * kp, np_ * kp
+    TAh = raw[:nprod * sa].reshape(nprod, mp, kp)
+    TBh = raw[nprod * sa:nprod * (sa + sb)].reshape(nprod, np_, kp)
+    TAl = raw[nprod * (sa + sb):nprod * (2 * sa + sb)].reshape(nprod, mp, kp)
+    TBl = raw[nprod * (2 * sa + sb):nprod * (2 * sa + 2 * sb)].reshape(nprod, np_, kp)
+    for r, (a_t, b_t, _) in enumerate(table(levels)):
+        ha, la = split_hi_lo(operand_sum(A, a_t, mq, kq, sum_prec))          # mq x kq
+        hb, lb = split_hi_lo(operand_sum(B, b_t, kq, nq, sum_prec))          # kq x nq
+        for got, want in ((TAh[r], _bf16_bits(ha)), (TAl[r], _bf16_bits(la)),
+                          (TBh[r], _bf16_bits(hb.T)), (TBl[r], _bf16_bits(lb.T))):
+            rows, cols = want.shape
+            assert np.array_equal(got[:rows, :cols], want), r
+            assert not got[rows:, :].any() and not got[:, cols:].any(), r   # zero padding

@@ -101,3 +101,98 @@ def test_bound_is_positive_and_scales():
     _, b1 = gemm_lowprec(A, B, C, 1.0, 1.0, 1, "bf16", "f32", "f32")
     _, b2 = gemm_lowprec(A, B, C, 2.0, 1.0, 1, "bf16", "f32", "f32")
     assert (b1 > 0).all() and (b2 >= b1).all()
+
+
+# ---------------------------------------------------------------------------------------------
+# Discriminating power of the two checks the GPU tests apply to the mode on real inputs:
+#   (1) the operand pass: every bf16 hi / lo operand the GPU writes must equal, bit for bit,
+#       the oracle's operand_sum + split_hi_lo (test_lowprec_gpu.py reads the GPU's operand
+#       buffers from a caller workspace);
+#   (2) the result: |C_gpu - C_oracle| <= gemm_lowprec's elementwise bound (FP32 accumulation
+#       in any order is the one freedom the GPU has).
+# A copy of the mode with one plausible mistake planted is run on the CPU; each mistake must
+# be caught by at least one check, and the test records which one does.
+# ---------------------------------------------------------------------------------------------
+def _trunc_bf16(x):
+    x = np.asarray(x, dtype=np.float32)
+    return (x.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+
+
+def _planted_operands(S, mistake):
+    rnd = _trunc_bf16 if mistake == "trunc_all" else bf16_round
+    hi = rnd(S)
+    lo = (_trunc_bf16 if mistake in ("trunc_lo", "trunc_all") else bf16_round)(S - hi)
+    return hi, lo
+
+
+def _planted_mode(A, B, C, alpha, beta, levels, compute, sum_prec, mistake):
+    """The mode of oracle/lowprec.py (FP64 C update) with `mistake` planted; returns the
+    result and the operands of every product (hi, lo of both sides)."""
+    from oracle.tables import table
+    m, k = A.shape
+    n = B.shape[1]
+    q = 2 ** levels
+    mq, nq, kq = -(-m // q), -(-n // q), -(-k // q)
+    Cp = np.zeros((q * mq, q * nq))
+    Cp[:m, :n] = C
+    first = np.ones((q, q), dtype=bool)
+    ops = []
+    for a_t, b_t, c_t in table(levels):
+        sp = "f64" if mistake == "f64_sums" else sum_prec
+        ha, la = _planted_operands(operand_sum(A, a_t, mq, kq, sp), mistake)
+        hb, lb = _planted_operands(operand_sum(B, b_t, kq, nq, sp), mistake)
+        ops.append((ha, la, hb, lb))
+        ha, la, hb, lb = (x.astype(np.float64) for x in (ha, la, hb, lb))
+        M = ha @ hb
+        if compute == "bf16x3":
+            M = M + ha @ lb + (0.0 if mistake == "drop_cross" else la @ hb)
+        for (ci, cj), gam in c_t:
+            sl = (slice(ci * mq, (ci + 1) * mq), slice(cj * nq, (cj + 1) * nq))
+            if first[ci, cj]:
+                b = beta * beta if mistake == "beta_twice" else beta
+                Cp[sl] = alpha * gam * M + b * Cp[sl]
+            else:
+                Cp[sl] = Cp[sl] + alpha * gam * M
+            first[ci, cj] = False
+    return Cp[:m, :n], ops
+
+
+# (mistake, compute, sum_prec) -> caught by the bound?  (measured at 256^3, seed 42)
+PLANTED = [
+    ("trunc_lo", "bf16x3", "f64", False),     # truncating lo split: 0.03-0.25x the bound
+    ("trunc_all", "bf16x3", "f64", False),    # truncating hi and lo: lo makes up for hi
+    ("trunc_all", "bf16", "f64", True),       # truncating bf16: 77-440x
+    ("drop_cross", "bf16x3", "f64", True),    # lo_A*hi_B dropped: 6-54x
+    ("f64_sums", "bf16x3", "f32", False),     # FP64 sums where FP32 was asked
+    ("beta_twice", "bf16x3", "f64", True),    # beta applied at two updates
+    ("beta_twice", "bf16", "f32", True),
+]
+
+
+@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("kind", ["uniform", "wide_both"])
+@pytest.mark.parametrize("mistake,compute,sum_prec,by_bound", PLANTED)
+def test_planted_mistakes_are_caught(mistake, compute, sum_prec, by_bound, levels, kind):
+    A, B, C = W.problem(42, 256, 256, 256, kind)
+    ref, bound = gemm_lowprec(A, B, C, -0.5, 2.5, levels, compute, sum_prec, "f64")
+    got, ops = _planted_mode(A, B, C, -0.5, 2.5, levels, compute, sum_prec, mistake)
+    _, clean = _planted_mode(A, B, C, -0.5, 2.5, levels, compute, sum_prec, "none")
+    caught_bound = bool((np.abs(got - ref) > bound).any())
+    if not (mistake == "f64_sums" and levels == 0):   # one term: FP64 and FP32 sums agree
+        assert caught_bound == by_bound, (float(np.max(np.abs(got - ref) / bound)))
+    used = [0, 2] if compute == "bf16" else [0, 1, 2, 3]
+    caught_operands = any(not np.array_equal(o[i], c[i]) for o, c in zip(ops, clean) for i in used)
+    assert caught_bound or caught_operands or (mistake == "f64_sums" and levels == 0)
+    # the planted copy without a mistake is the oracle (same operands, result within rounding)
+    assert np.allclose(_planted_mode(A, B, C, -0.5, 2.5, levels, compute, sum_prec, "none")[0],
+                       ref, rtol=0, atol=1e-12)
+
+
+def test_rne_and_truncation_differ_on_the_gpu_test_inputs():
+    """The inputs of the GPU operand-pass test separate a round-to-nearest-even split from a
+    truncating one in a large share of the lo parts."""
+    A, _, _ = W.problem(61, 300, 260, 270, "uniform")
+    S = operand_sum(A, [((0, 0), 1), ((1, 1), 1)], 150, 135, "f64")
+    hi = bf16_round(S)
+    lo_rne, lo_tr = bf16_round(S - hi), _trunc_bf16(S - hi)
+    assert np.mean(lo_rne != lo_tr) > 0.3
