@@ -120,6 +120,27 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
                    int levels, int variant, void *stream);
 
 /*
+ * strassen_dgemm_noalloc — strassen_dgemm for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, semantics, error codes and bits as strassen_dgemm; it calls no hipMalloc, hipFree
+ * or allocating routine.  Its workspace is a static device array of
+ * STRASSEN_NOALLOC_SCRATCH_BYTES that every device the library runs on holds until the process
+ * ends (its address is resolved on the first call on each device); the caller workspace of
+ * strassen_set_workspace and the library-owned workspace are not used.  AB and NAIVE keep
+ * their temporaries there: a call whose workspace (strassen_workspace_size) exceeds the
+ * scratch returns STRASSEN_ERR_ALLOC before anything is enqueued.  ABC uses it for block-padded
+ * copies and staged sums only where they fit, else runs its workspace-free path (same bits).
+ * Every call on a device shares that device's scratch, which keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap in time on one device (different
+ * streams, or different host threads) race.  Calls on one stream are ordered and safe.
+ */
+#define STRASSEN_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int strassen_dgemm_noalloc(int64_t m, int64_t n, int64_t k, double alpha,
+                           const double *A, int64_t lda, const double *B, int64_t ldb,
+                           double beta, double *C, int64_t ldc,
+                           int levels, int variant, void *stream);
+
+/*
  * strassen_workspace_size — bytes of device workspace strassen_dgemm needs for these sizes
  * (0 for levels 0).  AB: one M_r temporary per product (7^L of ceil(m/2^L) x ceil(n/2^L)
  * doubles, leading dimension rounded up to 8, each slot to 32), plus, where AB runs the fused

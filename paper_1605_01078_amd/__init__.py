@@ -41,6 +41,8 @@ def lib():
         gemm = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, ci, ci]
         L.strassen_dgemm.argtypes = gemm + [vp]
         L.strassen_dgemm.restype = ci
+        L.strassen_dgemm_noalloc.argtypes = gemm + [vp]
+        L.strassen_dgemm_noalloc.restype = ci
         L.strassen_gemm_ex.argtypes = gemm + [ci, ci, ci, vp]
         L.strassen_gemm_ex.restype = ci
         L.strassen_workspace_size.argtypes = [i64, i64, i64, ci, ci, ctypes.POINTER(ctypes.c_size_t)]
@@ -199,6 +201,22 @@ def dgemm(A, B, C, alpha=1.0, beta=1.0, levels=1, variant="abc", stream=None):
     check(lib().strassen_dgemm(m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc, int(levels),
                                _variant(variant), _stream(stream)))
     return C
+
+
+def dgemm_noalloc(A, B, C, alpha=1.0, beta=1.0, levels=1, variant="abc", stream=None):
+    """As :func:`dgemm`, through strassen_dgemm_noalloc: no device memory is allocated (the
+    library's static scratch is the workspace)."""
+    pa, m, k, lda = _mat(A, "A")
+    pb, k2, n, ldb = _mat(B, "B")
+    pc, m2, n2, ldc = _mat(C, "C")
+    if k2 != k or m2 != m or n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    check(lib().strassen_dgemm_noalloc(m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc,
+                                       int(levels), _variant(variant), _stream(stream)))
+    return C
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 def gemm_ex(A, B, C, alpha=1.0, beta=1.0, levels=1, compute="bf16", sum_prec="f64",
