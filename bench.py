@@ -36,7 +36,7 @@ METRIC = "effective TFLOPS (2mnk/t), Strassen vs own classical GEMM, at stated r
 PEAK_F64_MFMA = 78.6   # TFLOP/s, MI355X datasheet, dense FP64 matrix
 TOL = {0: None, 1: 1e-12, 2: 1e-11}
 KERNEL_SOURCES = ["paper_1605_01078_amd/csrc/tile_fp64.h", "paper_1605_01078_amd/csrc/kernels_fp64.hip",
-                  "paper_1605_01078_amd/csrc/fused_fp64.hip"]
+                  "paper_1605_01078_amd/csrc/fused_fp64.hip", "paper_1605_01078_amd/csrc/classical_fp64.hip"]
 
 
 def log(*a):
@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--no-parity", action="store_true", help="skip the sampled oracle check")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--reps", type=int, default=5,
+                   help="rounds of the round-robin member timing (median per member)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
     p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep"],
@@ -94,7 +96,22 @@ def copy_calibration():
 
 
 def dominant_kernel(L, variant):
-    return "all_products_kernel" if (variant == "abc" and L >= 1) else "fp64_tile_kernel"
+    if L == 0:
+        return "classical_kernel"
+    return "all_products_kernel" if variant in ("abc", "ab") else "fp64_tile_kernel"
+
+
+def kernel_kind(L, variant):
+    return {"classical_kernel": "classical", "all_products_kernel": "all_products"}.get(
+        dominant_kernel(L, variant), "tile")
+
+
+def headline_key(L, variant, staged):
+    """Member name of the headline call in the per-member table: two-level ABC with its outer
+    operand sums staged in workspace is `L2_abc_staged`; `L2_abc` is the workspace-free form."""
+    if L == 2 and variant == "abc" and staged:
+        return "L2_abc_staged"
+    return f"L{L}_{variant}"
 
 
 def traffic_path(L, variant, n):
@@ -529,7 +546,7 @@ def main():
     t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
     end_all = torch.cuda.Event(enable_timing=True)
-    kind = "all_products" if dominant_kernel(L, variant) == "all_products_kernel" else "tile"
+    kind = kernel_kind(L, variant)
     for k_ in sx.KERNEL_KINDS:   # drop what the warmup recorded
         sx.timing_collect(k_)
     sx.timing_enable(True)       # library-side event pairs around each kernel launch
@@ -553,62 +570,92 @@ def main():
     log(f"headline L={L} {variant}: {ms_per_step:.3f} ms/step, {value:.2f} effective TFLOP/s "
         f"(wall {wall:.2f} s)")
 
-    # ---- classical and every variant (same inputs, outside the timed steps) --------------------
+    # ---- classical and every member (same inputs, outside the timed steps) --------------------
+    # Round-robin: every round times each member once (HIP events around one call), so clock and
+    # thermal drift reach all members alike; each member's figure is the median of its rounds,
+    # and every ratio below divides medians.
     variants, vendor, ragged = {}, None, None
     if not args.no_compare:
         Cw = C0.clone()
-        pairs = [(0, "abc")] + [(lv, v) for lv in (1, 2) for v in ("abc", "ab", "naive")]
-        for lev, var in pairs:
-            f = call(lev, var, Cw)
-            f()
-            torch.cuda.synchronize()
-            ms, _ = timed(f, 3, stream)
-            variants[f"L{lev}_{var}"] = {"ms": round(ms, 3),
-                                         "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
-            log(f"  L={lev} {var:5s}: {ms:8.3f} ms  {variants[f'L{lev}_{var}']['tflops']:6.2f} TF")
-        # two-level ABC with its outer operand sums formed in the tile load (no staging)
-        sx.set_tile_config(4)
-        try:
-            f = call(2, "abc", Cw)
-            f()
-            torch.cuda.synchronize()
-            ms, _ = timed(f, 3, stream)
-        finally:
-            sx.set_tile_config(-1)
-        variants["L2_abc_unstaged"] = {"ms": round(ms, 3),
-                                       "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
-        log(f"  L=2 abc, outer sums in the load: {ms:8.3f} ms")
-        # context only: the vendor BLAS FP64 GEMM through torch (not this library's code)
         Ac, Bc = A.contiguous(), B.contiguous()   # plain row-major operands (same values)
         Cv = torch.empty(n, n, dtype=torch.float64, device=A.device)
-        f = lambda: torch.matmul(Ac, Bc, out=Cv)
-        f()
-        torch.cuda.synchronize()
-        ms, _ = timed(f, 3, stream)
-        vendor = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
-        log(f"  vendor BLAS FP64 GEMM (torch.matmul), context: {ms:8.3f} ms")
+        # (levels, variant, tile configuration); two-level ABC as the paper defines it, without
+        # workspace (outer sums formed in the load: configuration 4), beside the default form
+        # that stages the outer operand sums in workspace
+        members = {"L0_abc": (0, "abc", -1), "L1_abc": (1, "abc", -1), "L1_ab": (1, "ab", -1),
+                   "L1_naive": (1, "naive", -1), "L2_abc": (2, "abc", 4),
+                   "L2_abc_staged": (2, "abc", -1), "L2_ab": (2, "ab", -1),
+                   "L2_naive": (2, "naive", -1)}
+
+        def one(key):
+            if key == "vendor":
+                f = lambda: torch.matmul(Ac, Bc, out=Cv)
+                cfg = -1
+            else:
+                lev, var, cfg = members[key]
+                f = lambda: sx.dgemm(A, B, Cw, 1.0, 1.0, lev, var, stream)
+            if cfg >= 0:
+                sx.set_tile_config(cfg)
+            try:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                f()
+                e1.record(stream)
+                e1.synchronize()
+            finally:
+                if cfg >= 0:
+                    sx.set_tile_config(-1)
+            return e0.elapsed_time(e1)
+
+        keys = list(members) + ["vendor"]
+        for key in keys:   # one untimed call each (workspace, code objects)
+            one(key)
+        times = {key: [] for key in keys}
+        for _ in range(args.reps):
+            for key in keys:
+                times[key].append(one(key))
+        base_ms = float(np.median(times["L0_abc"]))
+        for key in keys:
+            ms = float(np.median(times[key]))
+            entry = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2),
+                     "speedup_vs_classical": round(base_ms / ms, 4),
+                     "spread_ms": [round(min(times[key]), 3), round(max(times[key]), 3)]}
+            if key == "vendor":
+                vendor = entry
+            else:
+                variants[key] = entry
+            log(f"  {key:16s}: {ms:8.3f} ms  {entry['tflops']:6.2f} TF  x{entry['speedup_vs_classical']:.3f}")
         del Cv, Ac, Bc
         # a size that does not split evenly (n - 1: every sub-block extent odd), classical, the
-        # headline member and AB at its level; ABC and AB run on block-padded copies (copy time
-        # included)
+        # headline member and AB at its level, round-robin as above; every member runs on
+        # block-padded copies there (copy time included)
         r = n - 1
         rflops = 2.0 * r * r * r
         Ar, Br, Cr = A[:r, :r], B[:r, :r], Cw[:r, :r]
         ragged = {"m": r, "n": r, "k": r}
         ragged_runs = [(0, "abc"), (L, variant)] + ([(L, "ab")] if L and variant != "ab" else [])
-        for lev, var in ragged_runs:
-            f = lambda lev=lev, var=var: sx.dgemm(Ar, Br, Cr, 1.0, 1.0, lev, var, stream)
+        fr = {f"L{lev}_{var}": (lambda lev=lev, var=var: sx.dgemm(Ar, Br, Cr, 1.0, 1.0, lev, var, stream))
+              for lev, var in ragged_runs}
+        rt = {key: [] for key in fr}
+        for key, f in fr.items():
             f()
-            torch.cuda.synchronize()
-            ms, _ = timed(f, 3, stream)
-            ragged[f"L{lev}_{var}"] = {
-                "ms": round(ms, 3), "tflops": round(rflops / (ms * 1e-3) * 1e-12, 2)}
-            log(f"  {r}^3 L={lev} {var}: {ms:8.3f} ms")
-        ragged["speedup_vs_classical"] = round(ragged[f"L{L}_{variant}"]["tflops"] /
-                                               ragged["L0_abc"]["tflops"], 4)
-        base = variants["L0_abc"]["tflops"]
-        for key, v in variants.items():
-            v["speedup_vs_classical"] = round(v["tflops"] / base, 4)
+        torch.cuda.synchronize()
+        for _ in range(args.reps):
+            for key, f in fr.items():
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                f()
+                e1.record(stream)
+                e1.synchronize()
+                rt[key].append(e0.elapsed_time(e1))
+        for key in fr:
+            ms = float(np.median(rt[key]))
+            ragged[key] = {"ms": round(ms, 3), "tflops": round(rflops / (ms * 1e-3) * 1e-12, 2)}
+            log(f"  {r}^3 {key}: {ms:8.3f} ms")
+        ragged["speedup_vs_classical"] = round(float(np.median(rt["L0_abc"])) /
+                                               float(np.median(rt[f"L{L}_{variant}"])), 4)
         del Cw
         sx.release_workspace()
 
@@ -619,7 +666,7 @@ def main():
     # products.  The average launch duration comes from the library's event pairs around each
     # launch of that kernel during the timed steps (the staged outer-sum passes of two-level ABC
     # and the assembly / sum passes are timed apart from it).
-    launches = 7 ** (L - 1) if (variant == "abc" and L >= 1) else 1
+    launches = 7 ** (L - 1) if (variant in ("abc", "ab") and L >= 1) else 1
     if kern_launches != launches * args.steps:
         raise SystemExit(f"expected {launches * args.steps} launches of the {kind} kernel in the "
                          f"timed steps, recorded {kern_launches}")
@@ -700,9 +747,12 @@ def main():
         "variants": variants,
     }
     if variants:
+        head = headline_key(L, variant, sums_launches)
         out["classical_tflops"] = variants["L0_abc"]["tflops"]
-        out["speedup_vs_classical"] = round(value / variants["L0_abc"]["tflops"], 4)
-        out["context_vendor_blas_fp64"] = dict(vendor, speedup_of_value=round(value / vendor["tflops"], 4))
+        out["headline_member"] = head
+        out["speedup_vs_classical"] = variants[head]["speedup_vs_classical"]
+        out["context_vendor_blas_fp64"] = dict(
+            vendor, speedup_of_headline=round(vendor["ms"] / variants[head]["ms"], 4))
         out["ragged"] = ragged
     print(json.dumps(out), flush=True)
 

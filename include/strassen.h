@@ -348,7 +348,8 @@ enum strassen_kernel_kind {
     STRASSEN_KERNEL_TILE = 2,          /* the general FP64 tile kernel (classical, AB, Naive, ABC fallback) */
     STRASSEN_KERNEL_BF16 = 3,          /* the reduced-precision product kernel (strassen_gemm_ex) */
     STRASSEN_KERNEL_CAST = 4,          /* its operand pass (sums rounded to bf16 hi / lo)       */
-    STRASSEN_KERNEL_PAD = 5            /* block-padded operand copies of ABC (and the copy back) */
+    STRASSEN_KERNEL_PAD = 5,           /* block-padded operand copies of ABC (and the copy back) */
+    STRASSEN_KERNEL_CLASSICAL = 6      /* the classical FP64 kernel on the fused load path (levels 0) */
 };
 int strassen_timing_enable(int on);
 int strassen_timing_collect(int kind, double *ms_total, int *launches);

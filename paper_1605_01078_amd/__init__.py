@@ -273,7 +273,8 @@ def set_tile_config(cfg):
     check(lib().strassen_set_tile_config(int(cfg)))
 
 
-KERNEL_KINDS = {"all_products": 0, "outer_sums": 1, "tile": 2, "bf16": 3, "cast": 4, "pad": 5}
+KERNEL_KINDS = {"all_products": 0, "outer_sums": 1, "tile": 2, "bf16": 3, "cast": 4, "pad": 5,
+                "classical": 6}
 
 
 def probe_rates(stream=None):

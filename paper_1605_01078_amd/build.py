@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstrassen.so")
-SOURCES = ["kernels_fp64.hip", "fused_fp64.hip", "kernels_bf16.hip", "kernels_batched.hip", "kernels_mlp.hip",
+SOURCES = ["kernels_fp64.hip", "fused_fp64.hip", "classical_fp64.hip", "kernels_bf16.hip", "kernels_batched.hip", "kernels_mlp.hip",
            "probe_rates.hip", "noalloc.hip",
            "tables.cpp", "api.cpp", "batched.cpp", "selector.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -496,6 +496,45 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
   return 0;
 }
 
+// Classical GEMM on the all-products kernel's load path: its layout needs m and k even (16-byte
+// row pairs of A and k pairs of B), 16-byte aligned operands with even leading dimensions, and
+// per-lane offsets spanning eight columns of B and 64 of C below 2^31 bytes.
+static bool classical_layout(int64_t m, int64_t k, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, const double* C, int64_t ldc) {
+  const int64_t lim = int64_t(1) << 31;
+  return m % 2 == 0 && k % 2 == 0 && aligned16(A) && aligned16(B) && aligned16(C) &&
+         lda % 2 == 0 && ldb % 2 == 0 && ldc % 2 == 0 && 8 * 64 * (ldc + 1) < lim &&
+         8 * 8 * (ldb + 1) < lim;
+}
+
+// Its 256 x 128 tiles fill MI355X's 256 CUs at least once; smaller problems keep the general
+// tile kernel, whose 128 x 128 or 64 x 64 tiles spread them over more CUs.
+static bool classical_size(int64_t m, int64_t n) { return cdiv(m, 256) * cdiv(n, 128) >= 256; }
+
+static int run_classical(int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                         int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                         int64_t ldc, hipStream_t stream) {
+  ClassicalArgs c;
+  std::memset(&c, 0, sizeof c);
+  c.A = A;
+  c.B = B;
+  c.C = C;
+  c.lda = lda;
+  c.ldb = ldb;
+  c.ldc = ldc;
+  c.m = m;
+  c.n = n;
+  c.k = k;
+  c.alpha = alpha;
+  c.beta = beta;
+  c.tiles_m = (int32_t)cdiv(m, 256);
+  c.tiles_n = (int32_t)cdiv(n, 128);
+  if ((int64_t)c.tiles_m * c.tiles_n >= (int64_t(1) << 30))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+  SMX_LAUNCH(STRASSEN_KERNEL_CLASSICAL, stream, launch_classical(c, stream));
+  return 0;
+}
+
 // Block padding (the zero padding of Sec. 3.3 made physical).  Where the all-products layout
 // does not apply to the operands as given (m or k not a multiple of 2^(L+1), operands not
 // 16-byte aligned, odd leading dimensions) or two-level staging needs n % 4 == 0, ABC runs on
@@ -601,10 +640,16 @@ static int run_padded(const PadPlan& pp, int levels, int64_t m, int64_t n, int64
       SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream,
                  copy(C, ldc, m, n, pp.mq, pp.mq_e, whole_n, whole_n, Cp, pp.mp, pp.mp, pp.np, 0));
   }
-  const Plan p = make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC);
-  if (int rc = run_all_products(p, Ap, lda_p, Bp, ldb_p, Cp, ldc_p, pp.np, alpha, beta,
-                                pp.stage ? ws + pp.s_off : nullptr, stream))
-    return rc;
+  if (levels == 0) {
+    if (int rc = run_classical(pp.mp, pp.np, pp.kp, alpha, Ap, lda_p, Bp, ldb_p, beta, Cp, ldc_p,
+                               stream))
+      return rc;
+  } else {
+    const Plan p = make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC);
+    if (int rc = run_all_products(p, Ap, lda_p, Bp, ldb_p, Cp, ldc_p, pp.np, alpha, beta,
+                                  pp.stage ? ws + pp.s_off : nullptr, stream))
+      return rc;
+  }
   if (pp.pc)
     SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream,
                copy(Cp, pp.mp, m, n, pp.mq, pp.mq_e, whole_n, whole_n, C, ldc, pp.mp, pp.np, 1));
@@ -754,6 +799,29 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     // all-products kernel in place, else the general tile kernel.  ABC needs no workspace: a
     // workspace that is too small or cannot be allocated only drops the copies or the staging.
     const bool all_products = forced == -1 || forced == kCfgAll || forced == kCfgAllStaged;
+    if (levels == 0 && all_products && classical_size(m, n)) {
+      // classical: the fused load path in place, else on block-padded copies (m or k odd,
+      // misaligned operands or odd leading dimensions), else the general tile kernel below
+      const bool in_place = classical_layout(m, k, A, lda, B, ldb, C, ldc);
+      PadPlan pp;
+      bool padded = false;
+      if (!in_place) {
+        pp = make_pad_plan(m, n, k, 0, A, lda, B, ldb, C, ldc, forced);
+        padded = pp.ok && wsrc.fits((size_t)pp.total * sizeof(double));
+      }
+      if (in_place || padded) {
+        int dev = 0;
+        if (int rc = device_ready(&dev)) return rc;
+        if (in_place) return run_classical(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+        void* ws = nullptr;
+        const int rc = get_workspace(wsrc, dev, (size_t)pp.total * sizeof(double), &ws);
+        if (rc == 0)
+          return run_padded(pp, 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                            static_cast<double*>(ws), stream);
+        if (wsrc.fixed) return rc;
+        g_last_error.clear();   // the library-owned allocation failed: the tile kernel
+      }
+    }
     PadPlan pp;
     bool padded = false;
     if (all_products && levels >= 1) {
@@ -1112,6 +1180,12 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   }
   const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
   *bytes = (size_t)p.total * sizeof(double);
+  if (levels == 0 && smx::classical_size(m, n) && (m % 2 != 0 || k % 2 != 0)) {
+    // the classical kernel on block-padded copies (m or k rounded up to even)
+    const smx::PadPlan pp = smx::make_pad_plan(m, n, k, 0, nullptr, 2 * smx::cdiv(m, 2), nullptr,
+                                               2 * smx::cdiv(k, 2), nullptr, 2 * smx::cdiv(m, 2), -1);
+    if (pp.ok) *bytes = (size_t)pp.total * sizeof(double);
+  }
   if (variant == STRASSEN_AB)
     // the all-products form of AB: padded A and B copies and staged outer sums behind the
     // temporaries (operands taken as 16-byte aligned with even leading dimensions)

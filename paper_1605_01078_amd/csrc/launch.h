@@ -31,6 +31,9 @@ hipError_t launch_fp64_tile(const GemmArgs& a, int cfg, int maxt, bool vec, int 
 // grid = a.tiles_m * a.tiles_n workgroups of 512 threads.
 hipError_t launch_all_products(const FusedArgs& a, int na, int nb, hipStream_t s);
 const void* all_products_fn(const FusedArgs& a, int na, int nb);   // its kernel symbol (graph nodes)
+// Classical FP64 GEMM (levels = 0) on the same load path; grid = tiles_m * tiles_n workgroups of
+// 512 threads, 256 x 128 tiles.
+hipError_t launch_classical(const ClassicalArgs& a, hipStream_t s);
 // Reduced-precision mode: operand pass over nslots products; BF16 product kernel.
 hipError_t upload_tables_bf16(const TableDev* tabs);
 hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s);

@@ -89,6 +89,17 @@ struct FusedArgs {
   int32_t store_m, prod_base;
 };
 
+// Classical FP64 GEMM on the all-products kernel's load path (levels = 0).
+struct ClassicalArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int64_t m, n, k;
+  double alpha, beta;
+  int32_t tiles_m, tiles_n;     // 256 x 128 tiles of C
+};
+
 // C assembly for AB / Naive: C_s := beta*C_s at the first update, then C_s += alpha*gamma*M_r
 // for the products r feeding sub-block s, in increasing r.
 struct AssembleArgs {

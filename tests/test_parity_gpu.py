@@ -338,7 +338,7 @@ def test_two_level_staging_default_and_small_caller_workspace():
 
 def test_kernel_timing_hooks():
     """The library's event pairs: one all-products launch at one level, seven plus two staged
-    outer-sum passes at two levels (m = n = k = 4096), one tile-kernel launch for classical."""
+    outer-sum passes at two levels (m = n = k = 4096), one classical-kernel launch for levels 0."""
     import torch
     n = 4096
     print("case timing hooks", flush=True)
@@ -356,8 +356,9 @@ def test_kernel_timing_hooks():
     ms_ap, n_ap = sx.timing_collect("all_products")
     ms_os, n_os = sx.timing_collect("outer_sums")
     ms_t, n_t = sx.timing_collect("tile")
-    assert (n_ap, n_os, n_t) == (8, 2, 1)
-    assert ms_ap > 0 and ms_os > 0 and ms_t > 0
+    ms_c, n_c = sx.timing_collect("classical")
+    assert (n_ap, n_os, n_t, n_c) == (8, 2, 0, 1)
+    assert ms_ap > 0 and ms_os > 0 and ms_c > 0
     assert sx.timing_collect("all_products") == (0.0, 0)
 
 
@@ -480,3 +481,38 @@ def test_probe_rates():
     print(f"  FP64 {f64:.2f} TFLOP/s, BF16 {bf16:.1f} TFLOP/s", flush=True)
     assert 0.5 * 78.6 < f64 < 1.05 * 78.6
     assert 0.5 * 2500.0 < bf16 < 1.05 * 2500.0
+
+
+@pytest.mark.parametrize("shape,offset,kind", [
+    ((4096, 4096, 528), 0, "integer"),    # whole tiles
+    ((4094, 4093, 530), 0, "uniform"),    # ragged tiles (masked loads and stores)
+    ((4097, 4096, 531), 0, "uniform"),    # m, k odd: block-padded copies
+    ((4096, 4096, 520), 1, "uniform"),    # operands not 16-byte aligned: copies
+])
+def test_classical_kernel_bitwise_with_tile_kernel(shape, offset, kind):
+    """The classical kernel on the fused load path (levels 0, default) performs the same FP64
+    operations as the general tile kernel (forced with tile configuration 0): bitwise equal
+    results; on integers both equal the oracle."""
+    m, n, k = shape
+    print(f"case classical kernel {shape} offset={offset} {kind}", flush=True)
+    A, B, C = W.problem(81, m, n, k, kind)
+    sx.timing_enable(True)
+    try:
+        sx.timing_collect("classical")
+        got = run(A, B, C, 1.5, -0.5, 0, "abc", offset=offset)
+        ms, launches = sx.timing_collect("classical")
+        assert launches == 1
+        sx.set_tile_config(0)
+        try:
+            ref = run(A, B, C, 1.5, -0.5, 0, "abc", offset=offset)
+        finally:
+            sx.set_tile_config(-1)
+        assert sx.timing_collect("classical")[1] == 0
+    finally:
+        sx.timing_enable(False)
+    assert np.array_equal(got, ref)
+    if kind == "integer":
+        assert np.array_equal(got, oracle_dgemm(A, B, C.copy(order="F"), 1.5, -0.5))
+    else:
+        assert (np.abs(got - oracle_dgemm(A, B, C.copy(order="F"), 1.5, -0.5))
+                <= classical_bound(A, B, C, 1.5, -0.5)).all()
