@@ -17,7 +17,8 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Column-major storage: element (i,j) of X is X[i + j*ldX].  A is m x k (lda >= max(1,m)),
- *    B is k x n (ldb >= max(1,k)), C is m x n (ldc >= max(1,m)).  No transposes.
+ *    B is k x n (ldb >= max(1,k)), C is m x n (ldc >= max(1,m)).  strassen_gemm takes
+ *    transposed operands (BLAS transa / transb); the other entry points take none.
  *  - A, B, C are DEVICE pointers owned by the caller.  The library never frees or retains
  *    them.  A and B are only read.  C must not overlap A or B.
  *  - Dimensions that are not multiples of 2^L are handled inside the kernels: every sub-block
@@ -118,6 +119,26 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
                    const double *A, int64_t lda, const double *B, int64_t ldb,
                    double beta, double *C, int64_t ldc,
                    int levels, int variant, void *stream);
+
+/*
+ * strassen_gemm — the full dgemm interface of Sec. 2.2 with transposes:
+ *   C := alpha * op(A) * op(B) + beta * C,   op(X) = X (trans 'N'/'n') or X^T ('T'/'t'/'C'/'c')
+ * op(A) is m x k (A is m x k with lda >= max(1,m), or k x m with lda >= max(1,k) when
+ * transposed), op(B) is k x n (B is k x n with ldb >= max(1,k), or n x k with ldb >= max(1,n)).
+ * levels 0..2 and variant as strassen_dgemm; levels = -1 lets the library choose the member
+ * (strassen_select, FP64; variant is then ignored).  A transposed operand is packed, transposed,
+ * into workspace first (a tiled copy, the counterpart of BLIS's packing of a transposed block;
+ * round_up(m, 2) * k or round_up(k, 2) * n doubles, each rounded up to 32), and the member then
+ * runs on the packed operands with the remaining workspace; untransposed calls are exactly
+ * strassen_dgemm.  The packed operands need workspace even for ABC: STRASSEN_ERR_ALLOC when the
+ * caller workspace or the workspace limit cannot hold them.  The result is bitwise that of
+ * strassen_dgemm on the explicitly transposed matrices.
+ * Argument positions for -i: transa=1 transb=2 m=3 n=4 k=5 alpha=6 A=7 lda=8 B=9 ldb=10
+ * beta=11 C=12 ldc=13 levels=14 variant=15.
+ */
+int strassen_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                  double *C, int64_t ldc, int levels, int variant, void *stream);
 
 /*
  * strassen_dgemm_noalloc — strassen_dgemm for callers that cannot allocate device memory

@@ -41,6 +41,8 @@ def lib():
         gemm = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, ci, ci]
         L.strassen_dgemm.argtypes = gemm + [vp]
         L.strassen_dgemm.restype = ci
+        L.strassen_gemm.argtypes = [ctypes.c_char, ctypes.c_char] + gemm + [vp]
+        L.strassen_gemm.restype = ci
         L.strassen_dgemm_noalloc.argtypes = gemm + [vp]
         L.strassen_dgemm_noalloc.restype = ci
         L.strassen_gemm_ex.argtypes = gemm + [ci, ci, ci, vp]
@@ -200,6 +202,24 @@ def dgemm(A, B, C, alpha=1.0, beta=1.0, levels=1, variant="abc", stream=None):
         raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
     check(lib().strassen_dgemm(m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc, int(levels),
                                _variant(variant), _stream(stream)))
+    return C
+
+
+def gemm(A, B, C, alpha=1.0, beta=1.0, transa="N", transb="N", levels=-1, variant="abc",
+         stream=None):
+    """C := alpha*op(A)*op(B) + beta*C through strassen_gemm: op(X) = X ('N') or X^T ('T');
+    A and B are the stored (untransposed) column-major matrices; levels = -1 lets the library
+    choose the member."""
+    pa, ra, ca, lda = _mat(A, "A")
+    pb, rb, cb, ldb = _mat(B, "B")
+    pc, m, n, ldc = _mat(C, "C")
+    ta, tb = transa.upper() != "N", transb.upper() != "N"
+    k = ra if ta else ca
+    if (ca if ta else ra) != m or (cb if tb else rb) != k or (rb if tb else cb) != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)} ({transa}), B {tuple(B.shape)} "
+                         f"({transb}), C {tuple(C.shape)}")
+    check(lib().strassen_gemm(transa.encode(), transb.encode(), m, n, k, alpha, pa, lda, pb, ldb,
+                              beta, pc, ldc, int(levels), _variant(variant), _stream(stream)))
     return C
 
 

@@ -13,6 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstrassen.so")
+BLAS_LIB = os.path.join(HERE, "libstrassen_blas.so")
 SOURCES = ["kernels_fp64.hip", "fused_fp64.hip", "classical_fp64.hip", "kernels_bf16.hip", "kernels_batched.hip", "kernels_mlp.hip",
            "probe_rates.hip", "noalloc.hip",
            "tables.cpp", "api.cpp", "batched.cpp", "selector.cpp"]
@@ -49,6 +50,20 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the drop-in BLAS (dgemm_, cblas_dgemm) on top of it, found beside it at run time
+    blas_obj = os.path.join(objdir, "blas_dgemm.cpp.o")
+    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "blas_dgemm.cpp"), "-o", blas_obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    _wait(("blas_dgemm.cpp", subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)),
+          verbose)
+    tmp = BLAS_LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, blas_obj, "-L" + HERE,
+           "-lstrassen", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, BLAS_LIB)
     return LIB
 
 

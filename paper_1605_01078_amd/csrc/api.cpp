@@ -1151,6 +1151,120 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   return 0;
 }
 
+// Workspace strassen_dgemm uses for these sizes with 16-byte aligned operands of even leading
+// dimensions (strassen_workspace_size).
+size_t workspace_bytes(int64_t m, int64_t n, int64_t k, int levels, int variant) {
+  if (m == 0 || n == 0 || k == 0) return 0;
+  const Plan p = make_plan(m, n, k, levels, variant);
+  size_t bytes = (size_t)p.total * sizeof(double);
+  if (levels == 0 && classical_size(m, n) && (m % 2 != 0 || k % 2 != 0)) {
+    // the classical kernel on block-padded copies (m or k rounded up to even)
+    const PadPlan pp = make_pad_plan(m, n, k, 0, nullptr, 2 * cdiv(m, 2), nullptr,
+                                     2 * cdiv(k, 2), nullptr, 2 * cdiv(m, 2), -1);
+    if (pp.ok) bytes = (size_t)pp.total * sizeof(double);
+  }
+  if (variant == STRASSEN_AB)
+    // the all-products form of AB: padded A and B copies and staged outer sums behind the
+    // temporaries (operands taken as 16-byte aligned with even leading dimensions)
+    bytes = (size_t)make_ab_layout(p, m, n, k, levels, nullptr, 2 * cdiv(m, 2), nullptr,
+                                   2 * cdiv(k, 2), -1).total *
+            sizeof(double);
+  if (variant == STRASSEN_ABC && levels >= 1) {
+    // operands taken as 16-byte aligned with even leading dimensions
+    const PadPlan pp = make_pad_plan(m, n, k, levels, nullptr, 2 * cdiv(m, 2), nullptr,
+                                     2 * cdiv(k, 2), nullptr, 2 * cdiv(m, 2), -1);
+    if ((pp.pa || pp.pb || pp.pc) && pp.ok)
+      bytes = (size_t)pp.total * sizeof(double);
+    else if (staging_applies(m, n, k, levels))
+      bytes = (size_t)make_stage_plan(p).total * sizeof(double);
+  }
+  return bytes;
+}
+
+// C := alpha*op(A)*op(B) + beta*C with op(X) = X or X^T (Sec. 2.2).  A transposed operand is
+// packed, transposed, into workspace (a tiled copy through LDS, the counterpart of BLIS packing
+// a transposed block) with an even leading dimension and 16-byte alignment; the call then runs
+// strassen_dgemm on the packed operands with the rest of the same workspace.  levels < 0: the
+// member is chosen by strassen_select.
+static bool trans_code(char t, bool* out) {
+  if (t == 'N' || t == 'n') *out = false;
+  else if (t == 'T' || t == 't' || t == 'C' || t == 'c') *out = true;
+  else return false;
+  return true;
+}
+
+int gemm_t(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+           int64_t ldc, int levels, int variant, const WsSource& wsrc, hipStream_t stream) {
+  g_last_error.clear();
+  bool ta = false, tb = false;
+  if (!trans_code(transa, &ta)) return fail(-1, "transa = '%c' is not N, T or C", transa);
+  if (!trans_code(transb, &tb)) return fail(-2, "transb = '%c' is not N, T or C", transb);
+  if (m < 0) return fail(-3, "m = %lld < 0", (long long)m);
+  if (n < 0) return fail(-4, "n = %lld < 0", (long long)n);
+  if (k < 0) return fail(-5, "k = %lld < 0", (long long)k);
+  const bool reads_ab = m > 0 && n > 0 && k > 0 && alpha != 0.0;
+  if (reads_ab && A == nullptr) return fail(-7, "A is NULL");
+  if (lda < std::max<int64_t>(1, ta ? k : m)) return fail(-8, "lda = %lld too small", (long long)lda);
+  if (reads_ab && B == nullptr) return fail(-9, "B is NULL");
+  if (ldb < std::max<int64_t>(1, tb ? n : k)) return fail(-10, "ldb = %lld too small", (long long)ldb);
+  if (m > 0 && n > 0 && C == nullptr) return fail(-12, "C is NULL");
+  if (ldc < std::max<int64_t>(1, m)) return fail(-13, "ldc = %lld < max(1, m)", (long long)ldc);
+  if (levels < -1 || levels > kMaxLevels) return fail(-14, "levels = %d not in -1..%d", levels, kMaxLevels);
+  if (levels >= 0 && (variant < 0 || variant > 2)) return fail(-15, "variant = %d not in 0..2", variant);
+  if (m == 0 || n == 0) return 0;
+  if (levels < 0) {
+    if (int rc = strassen_select(m, n, k, 0, &levels, &variant)) return rc;
+    g_last_error.clear();
+  }
+  if (!reads_ab || (!ta && !tb)) {   // nothing to pack (A and B unread when !reads_ab)
+    const int64_t la = ta ? std::max<int64_t>(1, m) : lda, lb = tb ? std::max<int64_t>(1, k) : ldb;
+    return dgemm(m, n, k, alpha, ta ? nullptr : A, la, tb ? nullptr : B, lb, beta, C, ldc,
+                 levels, variant, wsrc, stream);
+  }
+  // packed operands: op(A) as m x k with ld round_up(m, 2), op(B) as k x n with ld round_up(k, 2)
+  const int64_t lda_p = round_up(m, 2), ldb_p = round_up(k, 2);
+  const int64_t a_elems = ta ? round_up(lda_p * k, 32) : 0;
+  const int64_t b_elems = tb ? round_up(ldb_p * n, 32) : 0;
+  const size_t pack = (size_t)(a_elems + b_elems) * sizeof(double);
+  const size_t rest = workspace_bytes(m, n, k, levels, variant);
+  if (!wsrc.fits(pack + rest)) {
+    // the packed operands are required; the rest only as far as the member needs it
+    if (!wsrc.fits(pack))
+      return fail(STRASSEN_ERR_ALLOC, "packing the transposed operands needs %zu bytes of workspace",
+                  pack);
+  }
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
+  const size_t want = wsrc.fits(pack + rest) ? pack + rest : pack;
+  void* ws = nullptr;
+  if (int rc = get_workspace(wsrc, dev, want, &ws)) return rc;
+  double* wsd = static_cast<double*>(ws);
+  const double* Ap = A;
+  const double* Bp = B;
+  int64_t la = lda, lb = ldb;
+  if (ta) {
+    TransposeArgs t{A, wsd, lda, lda_p, m, k};
+    SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream, launch_transpose(t, stream));
+    Ap = wsd;
+    la = lda_p;
+  }
+  if (tb) {
+    TransposeArgs t{B, wsd + a_elems, ldb, ldb_p, k, n};
+    SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream, launch_transpose(t, stream));
+    Bp = wsd + a_elems;
+    lb = ldb_p;
+  }
+  // the member's own workspace: the rest of the same buffer (nothing is reallocated under the
+  // packed operands)
+  WsSource tail;
+  tail.fixed = true;
+  tail.ptr = static_cast<char*>(ws) + pack;
+  tail.bytes = want - pack;
+  tail.what = wsrc.fixed ? wsrc.what : "the workspace left after packing";
+  return dgemm(m, n, k, alpha, Ap, la, Bp, lb, beta, C, ldc, levels, variant, tail, stream);
+}
+
 }  // namespace smx
 
 // ---------------------------------------------------------------------------------------------
@@ -1165,6 +1279,13 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* 
                     smx::default_workspace(), static_cast<hipStream_t>(stream));
 }
 
+int strassen_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                  double* C, int64_t ldc, int levels, int variant, void* stream) {
+  return smx::gemm_t(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels,
+                     variant, smx::default_workspace(), static_cast<hipStream_t>(stream));
+}
+
 int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int variant,
                             size_t* bytes) {
   smx::g_last_error.clear();
@@ -1174,34 +1295,7 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   if (levels < 0 || levels > smx::kMaxLevels) return smx::fail(-4, "levels out of range");
   if (variant < 0 || variant > 2) return smx::fail(-5, "variant out of range");
   if (!bytes) return smx::fail(-6, "bytes is NULL");
-  if (m == 0 || n == 0 || k == 0) {
-    *bytes = 0;
-    return 0;
-  }
-  const smx::Plan p = smx::make_plan(m, n, k, levels, variant);
-  *bytes = (size_t)p.total * sizeof(double);
-  if (levels == 0 && smx::classical_size(m, n) && (m % 2 != 0 || k % 2 != 0)) {
-    // the classical kernel on block-padded copies (m or k rounded up to even)
-    const smx::PadPlan pp = smx::make_pad_plan(m, n, k, 0, nullptr, 2 * smx::cdiv(m, 2), nullptr,
-                                               2 * smx::cdiv(k, 2), nullptr, 2 * smx::cdiv(m, 2), -1);
-    if (pp.ok) *bytes = (size_t)pp.total * sizeof(double);
-  }
-  if (variant == STRASSEN_AB)
-    // the all-products form of AB: padded A and B copies and staged outer sums behind the
-    // temporaries (operands taken as 16-byte aligned with even leading dimensions)
-    *bytes = (size_t)smx::make_ab_layout(p, m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2),
-                                         nullptr, 2 * smx::cdiv(k, 2), -1).total *
-             sizeof(double);
-  if (variant == STRASSEN_ABC && levels >= 1) {
-    // operands taken as 16-byte aligned with even leading dimensions
-    const smx::PadPlan pp = smx::make_pad_plan(m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2),
-                                               nullptr, 2 * smx::cdiv(k, 2), nullptr,
-                                               2 * smx::cdiv(m, 2), -1);
-    if ((pp.pa || pp.pb || pp.pc) && pp.ok)
-      *bytes = (size_t)pp.total * sizeof(double);
-    else if (smx::staging_applies(m, n, k, levels))
-      *bytes = (size_t)smx::make_stage_plan(p).total * sizeof(double);
-  }
+  *bytes = smx::workspace_bytes(m, n, k, levels, variant);
   return 0;
 }
 

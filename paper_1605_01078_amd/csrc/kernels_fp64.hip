@@ -278,6 +278,39 @@ hipError_t launch_pad_copy(const PadArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Transposed copy (the packing of a transposed operand, Sec. 2.2 / Sec. 4.1): dst (rows x cols,
+// leading dimension ld_d) := src^T with src cols x rows (ld_s).  A workgroup moves a 64 x 64
+// block through LDS: it reads 64 consecutive elements of each source column (coalesced) and
+// writes 64 consecutive elements of each destination column (coalesced).
+constexpr int kTrT = 64;
+
+__global__ __launch_bounds__(256) void transpose_kernel(const TransposeArgs a) {
+  __shared__ double tile[kTrT][kTrT + 1];
+  const int64_t bi = (int64_t)blockIdx.x * kTrT;   // destination rows (source columns)
+  const int64_t bj = (int64_t)blockIdx.y * kTrT;   // destination columns (source rows)
+  const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
+#pragma unroll
+  for (int p = 0; p < kTrT / 4; ++p) {
+    const int c = hi + 4 * p;                        // source column bi + c, row bj + lo
+    const bool ok = bi + c < a.rows && bj + lo < a.cols;
+    tile[c][lo] = ok ? a.src[(bj + lo) + (bi + c) * a.ld_s] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kTrT / 4; ++p) {
+    const int c = hi + 4 * p;                        // destination column bj + c, row bi + lo
+    if (bi + lo < a.rows && bj + c < a.cols) a.dst[(bi + lo) + (bj + c) * a.ld_d] = tile[lo][c];
+  }
+}
+
+hipError_t launch_transpose(const TransposeArgs& a, hipStream_t s) {
+  if (a.rows <= 0 || a.cols <= 0) return hipSuccess;
+  const int64_t gx = (a.rows + kTrT - 1) / kTrT, gy = (a.cols + kTrT - 1) / kTrT;
+  if (gx >= (int64_t(1) << 31) || gy > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s) {
   const int chunks_m = (int)((a.m + 255) / 256);
   hipLaunchKernelGGL(scale_kernel, dim3((unsigned)(chunks_m * a.n)), dim3(256), 0, s, a, chunks_m);

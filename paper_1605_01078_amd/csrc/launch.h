@@ -56,6 +56,7 @@ hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
 hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s);   // side 0 A, 1 B
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
+hipError_t launch_transpose(const TransposeArgs& a, hipStream_t s);
 hipError_t launch_pad_copy(const PadArgs& a, hipStream_t s);
 // Matrix-core rate probe (probe_rates.hip): kind 0 FP64, 1 BF16; `out` holds grid * 256 doubles.
 int probe_grid(int cus);

@@ -195,6 +195,13 @@ struct BatchItem {
   int32_t tile;                 // tile index, ti + tiles_m * tj
 };
 
+// Transposed copy: dst (rows x cols, leading dimension ld_d) := src^T, src cols x rows (ld_s).
+struct TransposeArgs {
+  const double* src;
+  double* dst;
+  int64_t ld_s, ld_d, rows, cols;
+};
+
 // C := beta*C (alpha == 0 or k == 0).
 struct ScaleArgs {
   double* C;
