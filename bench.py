@@ -67,12 +67,13 @@ def parse():
                    help="rounds of the round-robin member timing (median per member)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
-    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep"],
+    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep", "levels"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
                         "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
                         "one persistent graph launch; selector: the committed network's choice "
                         "against exhaustive timing on held-out shapes; sweep: every member on the "
-                        "square sizes 2048..16384 and the rank-k shapes; each prints one JSON line")
+                        "square sizes 2048..16384 and the rank-k shapes; levels: three levels "
+                        "against two and classical at 32768; each prints one JSON line")
     p.add_argument("--shapes", type=int, default=200,
                    help="selector suite: held-out shapes timed exhaustively")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -466,6 +467,90 @@ def sweep_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def levels_suite(args):
+    """Three levels of Strassen (343 products) against two levels and classical at m = n = k =
+    --n (default 32768, where three levels are meant to pay; FP64, uniform[-1, 1] entries):
+    round-robin event timing, median of --reps rounds each, relative error of three levels on
+    sampled columns against the oracle, and the roofline of its all-products launches."""
+    import torch
+    import paper_1605_01078_amd as sx
+    import workloads as W
+    from oracle import oracle_dgemm, rel_fro
+    n = args.n if args.n != 16384 else 32768
+    stream = torch.cuda.current_stream()
+    A = W.device_uniform(1, n, n)
+    B = W.device_uniform(2, n, n)
+    C0 = W.device_uniform(3, n, n)
+    C = C0.clone()
+    flops = 2.0 * n * n * n
+    members = {"L0_abc": 0, "L2_abc_staged": 2, "L3_abc": 3}
+    times = {key: [] for key in members}
+
+    def one(lev):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sx.dgemm(A, B, C, 1.0, 1.0, lev, "abc", stream)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+    for lev in members.values():
+        one(lev)
+    reps = max(3, args.reps)
+    for k_ in sx.KERNEL_KINDS:
+        sx.timing_collect(k_)
+    for _ in range(reps):
+        for key, lev in members.items():
+            if lev == 3:
+                sx.timing_enable(True)
+            times[key].append(one(lev))
+            sx.timing_enable(False)
+    ap_ms, ap_n = sx.timing_collect("all_products")
+    os_ms, os_n = sx.timing_collect("outer_sums")
+    for k_ in sx.KERNEL_KINDS:
+        sx.timing_collect(k_)
+    base = float(np.median(times["L0_abc"]))
+    variants = {}
+    for key in members:
+        ms = float(np.median(times[key]))
+        variants[key] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2),
+                         "speedup_vs_classical": round(base / ms, 4),
+                         "spread_ms": [round(min(times[key]), 3), round(max(times[key]), 3)]}
+        log(f"  {n}^3 {key}: {ms:9.3f} ms  {variants[key]['tflops']:6.2f} TF")
+    # parity of three levels on sampled columns
+    C = C0.clone()
+    sx.dgemm(A, B, C, 1.0, 1.0, 3, "abc", stream)
+    torch.cuda.synchronize()
+    cols = np.sort(np.random.default_rng(0).choice(n, size=4, replace=False))
+    idx = torch.as_tensor(cols, device=C.device)
+    got = C[:, idx].cpu().numpy()
+    del C
+    ref = oracle_dgemm(sx.to_host(A), np.asfortranarray(B[:, idx].cpu().numpy()),
+                       np.asfortranarray(C0[:, idx].cpu().numpy()), 1.0, 1.0)
+    err = float(rel_fro(got, ref))
+    nq = n // 8
+    exec_launch = 7 * 2.0 * nq ** 3
+    avg = ap_ms / ap_n
+    achieved = exec_launch / (avg * 1e-3) * 1e-12
+    out = {"metric": METRIC, "value": variants["L3_abc"]["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"strassen_dgemm L=3 ABC m=n=k={n} FP64 C:=A*B+C, entries "
+                                  f"uniform[-1,1] (343 products; upper two levels staged)",
+                      "m": n, "n": n, "k": n, "levels": 3, "reps": reps},
+           "variants": variants,
+           "speedup_vs_classical": variants["L3_abc"]["speedup_vs_classical"],
+           "parity": {"L3_abc": err, "tolerance": 1e-10, "columns": [int(c) for c in cols],
+                      "pass": err <= 1e-10},
+           "roofline": {"bound": "mfma", "kernel": "all_products_kernel",
+                        "launches_per_step": ap_n // reps, "avg_launch_ms": round(avg, 4),
+                        "exec_flops_per_launch": exec_launch, "achieved": round(achieved, 3),
+                        "peak": PEAK_F64_MFMA, "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_F64_MFMA, 4),
+                        "staged_sum_passes": {"launches_per_step": os_n // reps,
+                                              "ms_per_step": round(os_ms / reps, 3)}}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -491,6 +576,9 @@ def main():
         return
     if args.suite == "sweep":
         sweep_suite(args)
+        return
+    if args.suite == "levels":
+        levels_suite(args)
         return
     if args.copy_calibration:
         copy_calibration()

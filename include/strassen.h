@@ -78,8 +78,16 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
 
 /*
  * strassen_dgemm — C := alpha*A*B + beta*C with `levels` levels of Strassen.
- *   levels : 0 (classical GEMM on FP64 MFMA, the effective-GFLOPS yardstick), 1 or 2.
- *   variant: STRASSEN_ABC, STRASSEN_AB or STRASSEN_NAIVE (ignored when levels == 0).
+ *   levels : 0 (classical GEMM on FP64 MFMA, the effective-GFLOPS yardstick), 1, 2 or 3.
+ *   variant: STRASSEN_ABC, STRASSEN_AB or STRASSEN_NAIVE (ignored when levels == 0; three
+ *            levels run ABC only: -13 for the others).
+ * Three levels (343 products, eq. e:straprim4 with L = 3) stage the operand sums of the two
+ * upper levels in workspace (five m/2 x k/2 and five k/2 x n/2 slots, five m/4 x k/4 and five
+ * k/4 x n/4 slots reused per top-level product) and run the one-level fused kernel for each of
+ * the 49 upper products, adding its seven products into up to four destination blocks; every C
+ * element receives its updates in increasing product index.  m and k must be multiples of 16
+ * and n of 8 with aligned operands of even leading dimensions, else block-padded copies are
+ * made (as below).  The workspace is required (STRASSEN_ERR_ALLOC when it cannot be had).
  * The general operation is eq. (e:straprim1) at one level and eq. (e:straprim3) at two.
  * AB runs its products on the fused kernel of ABC, stored to the temporaries instead of added to
  * C (one level; two levels over staged outer sums), on block-padded copies of A and B where
@@ -387,7 +395,7 @@ int strassen_probe_rates(double *fp64_tflops, double *bf16_tflops, void *stream)
 
 /*
  * Table introspection (host only, no device needed): the operation table the kernels execute.
- * strassen_table_size returns the number of products for `levels` (1, 7, 49) or -1.
+ * strassen_table_size returns the number of products for `levels` (1, 7, 49, 343) or -1.
  * strassen_table_get fills, for product r, the operand and destination terms as
  * codes  sign * (1 + row_block + 2^L * col_block)  (sign = -1 for a subtraction) in
  * a_terms[0..*na), b_terms[0..*nb), c_terms[0..*nc) (arrays of at least 8 entries).

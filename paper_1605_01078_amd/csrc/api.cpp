@@ -96,6 +96,16 @@ const TableDev* host_tables() {
   return tabs;
 }
 
+// The product-side table for `levels` (0..kMaxLevelsAbc), built once.
+const std::vector<Product>& host_table(int levels) {
+  static std::vector<Product> tabs[kMaxLevelsAbc + 1];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int l = 0; l <= kMaxLevelsAbc; ++l) tabs[l] = build_table(l);
+  });
+  return tabs[levels];
+}
+
 static int table_maxt(const TableDev& td) {
   int mx = 1;
   for (int r = 0; r < td.nprod; ++r) {
@@ -713,6 +723,230 @@ int all_products_plan(int64_t m, int64_t n, int64_t k, int levels, const double*
                             alpha, beta, nullptr, out);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Three levels (Sec. 3.5, eq. e:straprim4 with L = 3): product 49 R + 7 S + r applies outer row R
+// of the one-level table to the 2 x 2 blocks of A, B and C, row S to the 2 x 2 blocks of those,
+// and row r inside them.  The two upper levels' operand sums are staged: the five two-term sums
+// of each side over the four top blocks once (slots of m/2 x k/2 and k/2 x n/2), then, for each
+// R, the five sums over the four blocks of R's operand (slots of m/4 x k/4 and k/4 x n/4, reused
+// from R to R); each pair (R, S) is one launch of the one-level all-products kernel on its
+// staged (or single-term) operands, adding its seven products into the 2 x 2 sub-blocks of
+// every destination block (2 row_R + row_S, 2 col_R + col_S) with sign gamma_R gamma_S.  Launches
+// run in (R, S) order, so every C element receives its 343 updates in increasing product index.
+// Each staged sum is x0 + s1 x1 rounded once, formed from the previous level's sums: the
+// association of applying the one-level algorithm recursively.
+// ---------------------------------------------------------------------------------------------
+struct L3Plan {
+  int64_t mq, kq, nq, mq_e, kq_e;   // level-3 sub-block extents, plain and padded (even)
+  int64_t mp, kp, np;               // padded problem: 8 mq_e x 8 kq_e x 8 nq
+  bool pa, pb, pc;                  // operands copied to block-padded buffers
+  bool ok;                          // the layout fits the kernel's 32-bit lane offsets
+  int64_t a_off, b_off, c_off, s1a, s1b, s2a, s2b, total;   // workspace layout (doubles)
+};
+
+static L3Plan make_l3_plan(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                           const double* B, int64_t ldb, const double* C, int64_t ldc) {
+  L3Plan p;
+  p.mq = cdiv(m, 8);
+  p.kq = cdiv(k, 8);
+  p.nq = cdiv(n, 8);
+  p.mq_e = round_up(p.mq, 2);
+  p.kq_e = round_up(p.kq, 2);
+  p.mp = 8 * p.mq_e;
+  p.kp = 8 * p.kq_e;
+  p.np = 8 * p.nq;
+  const int64_t lim = int64_t(1) << 31;
+  p.pa = p.mp != m || p.kp != k || !aligned16(A) || lda % 2 != 0 || 8 * 16 * lda >= lim;
+  p.pb = p.kp != k || p.np != n || !aligned16(B) || ldb % 2 != 0 || 8 * 64 * ldb >= lim;
+  p.pc = p.mp != m || p.np != n || !aligned16(C) || ldc % 2 != 0 || 8 * 64 * ldc >= lim;
+  p.ok = 8 * 16 * (p.pa ? p.mp : lda) < lim && 8 * 64 * (p.pb ? p.kp : ldb) < lim &&
+         8 * 64 * (p.pc ? p.mp : ldc) < lim;
+  int64_t off = 0;
+  auto take = [&](bool used, int64_t elems) {
+    const int64_t at = off;
+    if (used) off += round_up(elems, 32);
+    return at;
+  };
+  p.a_off = take(p.pa, p.mp * p.kp);
+  p.b_off = take(p.pb, p.kp * p.np);
+  p.c_off = take(p.pc, p.mp * p.np);
+  p.s1a = take(true, 5 * round_up((p.mp / 2) * (p.kp / 2), 32));
+  p.s1b = take(true, 5 * round_up((p.kp / 2) * (p.np / 2), 32));
+  p.s2a = take(true, 5 * round_up((p.mp / 4) * (p.kp / 4), 32));
+  p.s2b = take(true, 5 * round_up((p.kp / 4) * (p.np / 4), 32));
+  p.total = off;
+  return p;
+}
+
+// The five two-term sums of one side of the one-level table over the 2 x 2 blocks (rows x cols
+// each) of src, into slots of rows x cols (leading dimension rows) at dst + s * stride.
+static int stage_sums(const double* src, int64_t ld, int64_t rows, int64_t cols, double* dst,
+                      int64_t stride, int side, hipStream_t stream) {
+  OuterSumArgs o;
+  std::memset(&o, 0, sizeof o);
+  o.src = src;
+  o.dst = dst;
+  o.ld = ld;
+  o.rows = rows;
+  o.cols = cols;
+  o.dst_stride = stride;
+  for (int q = 0; q < 4; ++q) o.blk[q] = (q >> 1) * rows + (q & 1) * cols * ld;
+  SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(o, side, stream));
+  return 0;
+}
+
+// One side's operand of a one-level product P over the 2 x 2 blocks (rows x cols) of src: its
+// staged sum (slot `slot` of dst, leading dimension rows) or its single block of src.
+struct Operand {
+  const double* p;
+  int64_t ld;
+};
+static Operand level_operand(const QTerm* terms, int nt, int slot, const double* src, int64_t ld,
+                             int64_t rows, int64_t cols, const double* slots, int64_t stride) {
+  if (nt == 2) return {slots + slot * stride, rows};
+  const int q = terms[0].q;
+  return {src + (q >> 1) * rows + (q & 1) * cols * ld, ld};
+}
+
+static int run_l3(const L3Plan& lp, double alpha, const double* A, int64_t lda, const double* B,
+                  int64_t ldb, double beta, double* C, int64_t ldc, double* ws,
+                  hipStream_t stream) {
+  const int64_t mq = lp.mq_e, kq = lp.kq_e, nq = lp.nq;   // level-3 extents (padded problem)
+  const int64_t m1 = 4 * mq, k1 = 4 * kq, n1 = 4 * nq;    // level-1 blocks
+  const int64_t m2 = 2 * mq, k2 = 2 * kq, n2 = 2 * nq;    // level-2 blocks
+  const int64_t s1a = round_up(m1 * k1, 32), s1b = round_up(k1 * n1, 32);
+  const int64_t s2a = round_up(m2 * k2, 32), s2b = round_up(k2 * n2, 32);
+  double* S1A = ws + lp.s1a;
+  double* S1B = ws + lp.s1b;
+  double* S2A = ws + lp.s2a;
+  double* S2B = ws + lp.s2b;
+  if (int rc = stage_sums(A, lda, m1, k1, S1A, s1a, 0, stream)) return rc;
+  if (int rc = stage_sums(B, ldb, k1, n1, S1B, s1b, 1, stream)) return rc;
+  int slot_a[7], slot_b[7];
+  for (int r = 0, sa = 0, sb = 0; r < 7; ++r) {
+    slot_a[r] = kOneLevel[r].na == 2 ? sa++ : -1;
+    slot_b[r] = kOneLevel[r].nb == 2 ? sb++ : -1;
+  }
+  bool touched[4][4] = {};
+  FusedArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.C = C;
+  f.ldc = ldc;
+  f.n = 8 * nq;
+  f.mq = mq;
+  f.nq = nq;
+  f.kq = kq;
+  f.alpha = alpha;
+  f.beta = beta;
+  f.tiles_m = (int32_t)cdiv(mq, 64);
+  f.tiles_n = (int32_t)cdiv(nq, 64);
+  f.a_sg[0] = f.b_sg[0] = 1.0;
+  for (int R = 0; R < 7; ++R) {
+    const QProduct& PR = kOneLevel[R];
+    const Operand aR = level_operand(PR.a, PR.na, slot_a[R], A, lda, m1, k1, S1A, s1a);
+    const Operand bR = level_operand(PR.b, PR.nb, slot_b[R], B, ldb, k1, n1, S1B, s1b);
+    if (int rc = stage_sums(aR.p, aR.ld, m2, k2, S2A, s2a, 0, stream)) return rc;
+    if (int rc = stage_sums(bR.p, bR.ld, k2, n2, S2B, s2b, 1, stream)) return rc;
+    for (int S = 0; S < 7; ++S) {
+      const QProduct& PS = kOneLevel[S];
+      const Operand a = level_operand(PS.a, PS.na, slot_a[S], aR.p, aR.ld, m2, k2, S2A, s2a);
+      const Operand b = level_operand(PS.b, PS.nb, slot_b[S], bR.p, bR.ld, k2, n2, S2B, s2b);
+      f.A = a.p;
+      f.lda = a.ld;
+      f.B = b.p;
+      f.ldb = b.ld;
+      f.nc = PR.nc * PS.nc;
+      f.c_first = 0;
+      int d = 0;
+      for (int dr = 0; dr < PR.nc; ++dr)
+        for (int ds = 0; ds < PS.nc; ++ds, ++d) {
+          const int row = 2 * (PR.c[dr].q >> 1) + (PS.c[ds].q >> 1);
+          const int col = 2 * (PR.c[dr].q & 1) + (PS.c[ds].q & 1);
+          f.c_off[d] = row * m2 + col * n2 * ldc;
+          f.c_cb[d] = 2 * col;
+          f.c_sg[d] = (double)(PR.c[dr].sign * PS.c[ds].sign);
+          if (!touched[row][col]) f.c_first |= 1 << d;
+          touched[row][col] = true;
+        }
+      SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, 1, 1, stream));
+    }
+  }
+  return 0;
+}
+
+static int pad_copy(const double* src, int64_t ld_s, int64_t rows, int64_t cols, int64_t rb,
+                    int64_t rb_e, int64_t cb, int64_t cb_e, double* dst, int64_t ld_d,
+                    int64_t dst_rows, int64_t dst_cols, int unpad, hipStream_t stream) {
+  PadArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.src = src;
+  a.dst = dst;
+  a.ld_s = ld_s;
+  a.ld_d = ld_d;
+  a.rows = rows;
+  a.cols = cols;
+  a.rb = rb;
+  a.rb_e = rb_e;
+  a.cb = cb;
+  a.cb_e = cb_e;
+  a.dst_rows = dst_rows;
+  a.dst_cols = dst_cols;
+  a.unpad = unpad;
+  SMX_LAUNCH(STRASSEN_KERNEL_PAD, stream, launch_pad_copy(a, stream));
+  return 0;
+}
+
+static int dgemm_l3(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                    const WsSource& wsrc, hipStream_t stream) {
+  const L3Plan lp = make_l3_plan(m, n, k, A, lda, B, ldb, C, ldc);
+  if (!lp.ok)
+    return fail(STRASSEN_ERR_UNSUPPORTED, "three levels: sizes past the 32-bit tile offsets");
+  if ((int64_t)cdiv(lp.mq_e, 64) * cdiv(lp.nq, 64) >= (int64_t(1) << 30))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+  const size_t bytes = (size_t)lp.total * sizeof(double);
+  if (!wsrc.fits(bytes))
+    return fail(STRASSEN_ERR_ALLOC, "three levels stage their upper operand sums: %zu bytes of "
+                "workspace needed, %zu available", bytes, wsrc.bytes);
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
+  void* w = nullptr;
+  if (int rc = get_workspace(wsrc, dev, bytes, &w)) return rc;
+  double* ws = static_cast<double*>(w);
+  const double* Ap = A;
+  const double* Bp = B;
+  double* Cp = C;
+  int64_t la = lda, lb = ldb, lc = ldc;
+  if (lp.pa) {
+    if (int rc = pad_copy(A, lda, m, k, lp.mq, lp.mq_e, lp.kq, lp.kq_e, ws + lp.a_off, lp.mp,
+                          lp.mp, lp.kp, 0, stream))
+      return rc;
+    Ap = ws + lp.a_off;
+    la = lp.mp;
+  }
+  if (lp.pb) {
+    if (int rc = pad_copy(B, ldb, k, n, lp.kq, lp.kq_e, lp.np, lp.np, ws + lp.b_off, lp.kp, lp.kp,
+                          lp.np, 0, stream))
+      return rc;
+    Bp = ws + lp.b_off;
+    lb = lp.kp;
+  }
+  if (lp.pc) {
+    Cp = ws + lp.c_off;
+    lc = lp.mp;
+    if (beta != 0.0)   // with beta = 0 no update reads C
+      if (int rc = pad_copy(C, ldc, m, n, lp.mq, lp.mq_e, lp.np, lp.np, Cp, lp.mp, lp.mp, lp.np,
+                            0, stream))
+        return rc;
+  }
+  if (int rc = run_l3(lp, alpha, Ap, la, Bp, lb, beta, Cp, lc, ws, stream)) return rc;
+  if (lp.pc)
+    if (int rc = pad_copy(Cp, lp.mp, m, n, lp.mq, lp.mq_e, lp.np, lp.np, C, ldc, lp.mp, lp.np, 1,
+                          stream))
+      return rc;
+  return 0;
+}
+
 static int validate(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double* C, int64_t ldc, int levels,
                     int variant) {
@@ -726,8 +960,11 @@ static int validate(int64_t m, int64_t n, int64_t k, double alpha, const double*
   if (ldb < std::max<int64_t>(1, k)) return fail(-8, "ldb = %lld < max(1, k)", (long long)ldb);
   if (m > 0 && n > 0 && C == nullptr) return fail(-10, "C is NULL");
   if (ldc < std::max<int64_t>(1, m)) return fail(-11, "ldc = %lld < max(1, m)", (long long)ldc);
-  if (levels < 0 || levels > kMaxLevels) return fail(-12, "levels = %d not in 0..%d", levels, kMaxLevels);
+  if (levels < 0 || levels > kMaxLevelsAbc)
+    return fail(-12, "levels = %d not in 0..%d", levels, kMaxLevelsAbc);
   if (variant < 0 || variant > 2) return fail(-13, "variant = %d not in 0..2", variant);
+  if (levels > kMaxLevels && variant != STRASSEN_ABC)
+    return fail(-13, "levels = %d runs the ABC variant only (variant = %d)", levels, variant);
   return 0;
 }
 
@@ -768,6 +1005,7 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     if (int rc = device_ready(&dev)) return rc;
     return run_scale(C, ldc, m, n, beta, stream);
   }
+  if (levels == 3) return dgemm_l3(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, wsrc, stream);
   const Plan p = make_plan(m, n, k, levels, variant);
   const int64_t tiles_limit = 1ll << 30;
   const int forced = g_forced_cfg.load(std::memory_order_relaxed);
@@ -1064,6 +1302,8 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   if (compute == STRASSEN_COMPUTE_F64)
     return dgemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels, variant,
                  default_workspace(), stream);
+  if (levels > kMaxLevels)
+    return fail(-12, "the reduced-precision mode runs levels 0..%d (levels = %d)", kMaxLevels, levels);
   if (variant != STRASSEN_ABC)
     return fail(-13, "the reduced-precision mode runs the ABC variant only (variant = %d)", variant);
   if (m == 0 || n == 0) return 0;
@@ -1155,6 +1395,9 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 // dimensions (strassen_workspace_size).
 size_t workspace_bytes(int64_t m, int64_t n, int64_t k, int levels, int variant) {
   if (m == 0 || n == 0 || k == 0) return 0;
+  if (levels == 3)
+    return (size_t)make_l3_plan(m, n, k, nullptr, 2 * cdiv(m, 2), nullptr, 2 * cdiv(k, 2),
+                                nullptr, 2 * cdiv(m, 2)).total * sizeof(double);
   const Plan p = make_plan(m, n, k, levels, variant);
   size_t bytes = (size_t)p.total * sizeof(double);
   if (levels == 0 && classical_size(m, n) && (m % 2 != 0 || k % 2 != 0)) {
@@ -1210,8 +1453,11 @@ int gemm_t(char transa, char transb, int64_t m, int64_t n, int64_t k, double alp
   if (ldb < std::max<int64_t>(1, tb ? n : k)) return fail(-10, "ldb = %lld too small", (long long)ldb);
   if (m > 0 && n > 0 && C == nullptr) return fail(-12, "C is NULL");
   if (ldc < std::max<int64_t>(1, m)) return fail(-13, "ldc = %lld < max(1, m)", (long long)ldc);
-  if (levels < -1 || levels > kMaxLevels) return fail(-14, "levels = %d not in -1..%d", levels, kMaxLevels);
+  if (levels < -1 || levels > kMaxLevelsAbc)
+    return fail(-14, "levels = %d not in -1..%d", levels, kMaxLevelsAbc);
   if (levels >= 0 && (variant < 0 || variant > 2)) return fail(-15, "variant = %d not in 0..2", variant);
+  if (levels > kMaxLevels && variant != STRASSEN_ABC)
+    return fail(-15, "levels = %d runs the ABC variant only (variant = %d)", levels, variant);
   if (m == 0 || n == 0) return 0;
   if (levels < 0) {
     if (int rc = strassen_select(m, n, k, 0, &levels, &variant)) return rc;
@@ -1292,8 +1538,10 @@ int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int var
   if (m < 0) return smx::fail(-1, "m < 0");
   if (n < 0) return smx::fail(-2, "n < 0");
   if (k < 0) return smx::fail(-3, "k < 0");
-  if (levels < 0 || levels > smx::kMaxLevels) return smx::fail(-4, "levels out of range");
+  if (levels < 0 || levels > smx::kMaxLevelsAbc) return smx::fail(-4, "levels out of range");
   if (variant < 0 || variant > 2) return smx::fail(-5, "variant out of range");
+  if (levels > smx::kMaxLevels && variant != STRASSEN_ABC)
+    return smx::fail(-5, "levels %d runs the ABC variant only", levels);
   if (!bytes) return smx::fail(-6, "bytes is NULL");
   *bytes = smx::workspace_bytes(m, n, k, levels, variant);
   return 0;
@@ -1441,27 +1689,27 @@ int strassen_set_tile_config(int cfg) {
 }
 
 int strassen_table_size(int levels) {
-  if (levels < 0 || levels > smx::kMaxLevels) return -1;
-  return smx::host_tables()[smx::table_id(levels, false)].nprod;
+  if (levels < 0 || levels > smx::kMaxLevelsAbc) return -1;
+  return (int)smx::host_table(levels).size();
 }
 
 int strassen_table_get(int levels, int r, int* na, int* a_terms, int* nb, int* b_terms, int* nc,
                        int* c_terms) {
-  if (levels < 0 || levels > smx::kMaxLevels) return -1;
-  const smx::TableDev& td = smx::host_tables()[smx::table_id(levels, false)];
-  if (r < 0 || r >= td.nprod) return -2;
-  const smx::ProdDesc& d = td.prod[r];
-  const int q = td.q;
-  auto dec = [q](uint8_t c) {
-    const int v = 1 + (c & 7) + q * ((c >> 3) & 7);
-    return (c & 0x80) ? -v : v;
+  if (levels < 0 || levels > smx::kMaxLevelsAbc) return -1;
+  const std::vector<smx::Product>& tab = smx::host_table(levels);
+  if (r < 0 || r >= (int)tab.size()) return -2;
+  const smx::Product& p = tab[r];
+  const int q = 1 << levels;
+  auto dec = [q](const smx::Term& t) {
+    const int v = 1 + t.row + q * t.col;
+    return t.sign < 0 ? -v : v;
   };
-  *na = d.na;
-  *nb = d.nb;
-  *nc = d.nc;
-  for (int s = 0; s < d.na; ++s) a_terms[s] = dec(d.a[s]);
-  for (int s = 0; s < d.nb; ++s) b_terms[s] = dec(d.b[s]);
-  for (int s = 0; s < d.nc; ++s) c_terms[s] = dec(d.c[s]);
+  *na = (int)p.a.size();
+  *nb = (int)p.b.size();
+  *nc = (int)p.c.size();
+  for (int s = 0; s < *na; ++s) a_terms[s] = dec(p.a[s]);
+  for (int s = 0; s < *nb; ++s) b_terms[s] = dec(p.b[s]);
+  for (int s = 0; s < *nc; ++s) c_terms[s] = dec(p.c[s]);
   return 0;
 }
 

@@ -22,6 +22,8 @@ void clear_error();
 
 // The kNumTables operation tables (host copies; the device copies are uploaded per device).
 const TableDev* host_tables();
+// The product-side table for 0..kMaxLevelsAbc levels (host only).
+const std::vector<Product>& host_table(int levels);
 // Current device checked (gfx950) and its constant tables uploaded; returns 0 or an error code.
 int device_ready(int* dev_out);
 

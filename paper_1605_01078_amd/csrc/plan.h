@@ -9,7 +9,8 @@
 
 namespace smx {
 
-constexpr int kMaxLevels = 2;
+constexpr int kMaxLevels = 2;      // device tables (tile kernel, AB, Naive, batched, BF16 mode)
+constexpr int kMaxLevelsAbc = 3;   // strassen_dgemm's ABC (three levels: staged upper levels)
 constexpr int kMaxProducts = 49;   // 7^kMaxLevels
 constexpr int kMaxTerms = 4;       // 2^kMaxLevels operand terms / destinations per product
 
@@ -67,7 +68,9 @@ struct GemmArgs {
 
 // Arguments of the all-products kernel: one launch computes the seven products of the one-level
 // table on the 2 x 2 inner sub-blocks of one outer product's operands (at one level the outer
-// product is the identity: one term of sign +1 covering the whole matrix).
+// product is the identity: one term of sign +1 covering the whole matrix; at three levels the
+// outer product is a pair of products of the two upper levels, its operands staged sums and its
+// destinations the Kronecker products of their destinations).
 struct FusedArgs {
   const double* A;
   const double* B;
@@ -77,11 +80,11 @@ struct FusedArgs {
   int64_t mq, nq, kq;           // inner sub-block extents (mq and kq even and exact)
   double alpha, beta;
   int32_t tiles_m, tiles_n;     // 64 x 64 tiles of one inner sub-block
-  int32_t nc;                   // outer destinations (1 or 2)
+  int32_t nc;                   // outer destinations (1 or 2; up to 4 at three levels)
   int32_t c_first;              // bit d: outer destination d gets its first update in this launch
-  int64_t a_off[2], b_off[2], c_off[2];   // element offsets of the outer blocks
-  int32_t b_cb[2], c_cb[2];     // first column block (units of nq) of outer B terms / destinations
-  double a_sg[2], b_sg[2], c_sg[2];
+  int64_t a_off[2], b_off[2], c_off[4];   // element offsets of the outer blocks
+  int32_t b_cb[2], c_cb[4];     // first column block (units of nq) of outer B terms / destinations
+  double a_sg[2], b_sg[2], c_sg[4];
   // AB form (store_m = 1): product r of this launch goes to temporary prod_base + r at
   // M + (prod_base + r) * m_stride, leading dimension ldm (even); C is not touched
   double* M;

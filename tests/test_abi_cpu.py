@@ -33,7 +33,9 @@ BAD = [
     ((4, 4, 5, 4, 4, 4, 1, 0, 1, 1, 1), -8),
     ((4, 4, 4, 4, 4, 4, 1, 0, 1, 1, 0), -10),
     ((4, 4, 4, 4, 4, 3, 1, 0, 1, 1, 1), -11),
-    ((4, 4, 4, 4, 4, 4, 3, 0, 1, 1, 1), -12),
+    ((4, 4, 4, 4, 4, 4, 4, 0, 1, 1, 1), -12),
+    ((4, 4, 4, 4, 4, 4, 3, 1, 1, 1, 1), -13),    # three levels: ABC only
+    ((4, 4, 4, 4, 4, 4, 3, 2, 1, 1, 1), -13),
     ((4, 4, 4, 4, 4, 4, -1, 0, 1, 1, 1), -12),
     ((4, 4, 4, 4, 4, 4, 1, 3, 1, 1, 1), -13),
     ((0, 4, 4, 0, 4, 0, 1, 0, 1, 1, 1), -6),     # lda >= max(1, m) even when m == 0
@@ -61,7 +63,7 @@ def test_null_operands_allowed_when_not_read():
     assert sx.raw_dgemm(0, 3, 3, 0.0, None, 1, None, 3, 1.0, None, 1, 1, 0, None) == 0
 
 
-@pytest.mark.parametrize("levels", [0, 1, 2])
+@pytest.mark.parametrize("levels", [0, 1, 2, 3])
 def test_tables_match_oracle(levels):
     lib_tab = sx.table(levels)
     ora = otab.table(levels)
@@ -74,7 +76,7 @@ def test_tables_match_oracle(levels):
 
 
 def test_tables_satisfy_identity():
-    for levels in (1, 2):
+    for levels in (1, 2, 3):
         tab = sx.table(levels)
         assert np.array_equal(otab.tensor_of(tab, levels), otab.matmul_tensor(levels))
 
@@ -270,3 +272,22 @@ def test_workspace_limit_entry_point():
     L = sx.lib()
     assert L.strassen_set_workspace_limit(1 << 20) == 0
     assert L.strassen_set_workspace_limit(0) == 0   # no cap
+
+
+def test_three_level_workspace():
+    """Three levels stage the sums of the two upper levels: five slots per side of m/2 x k/2 and
+    k/2 x n/2, and five of m/4 x k/4 and k/4 x n/4 reused from one top-level product to the next
+    (each rounded up to 32 doubles); ragged sizes add block-padded copies (every level-3 sub-block
+    extent even, n rounded up to 8)."""
+    r32 = lambda x: _cdiv(x, 32) * 32
+    m = n = k = 4096
+    want = 8 * 5 * (r32(2048 * 2048) * 2 + r32(1024 * 1024) * 2)
+    assert sx.workspace_size(m, n, k, 3, "abc") == want
+    m, n, k = 1000, 999, 1001
+    mp, kp, np_ = 8 * 2 * _cdiv(_cdiv(m, 8), 2), 8 * 2 * _cdiv(_cdiv(k, 8), 2), 8 * _cdiv(n, 8)
+    want = 8 * (r32(mp * kp) + r32(kp * np_) + r32(mp * np_) +
+                5 * (r32(mp // 2 * kp // 2) + r32(kp // 2 * np_ // 2)) +
+                5 * (r32(mp // 4 * kp // 4) + r32(kp // 4 * np_ // 4)))
+    assert sx.workspace_size(m, n, k, 3, "abc") == want
+    out = ctypes.c_size_t()
+    assert sx.lib().strassen_workspace_size(64, 64, 64, 3, 1, ctypes.byref(out)) == -5

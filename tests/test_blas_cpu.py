@@ -69,7 +69,8 @@ def test_dgemm_quick_return_without_device():
     ((b"T", b"N", 4, 4, 6, 5, 6, 4, 1, 0), -8),
     ((b"N", b"T", 4, 7, 4, 4, 6, 4, 1, 0), -10),
     ((b"N", b"N", 4, 4, 4, 4, 4, 3, 1, 0), -13),
-    ((b"N", b"N", 4, 4, 4, 4, 4, 4, 3, 0), -14),
+    ((b"N", b"N", 4, 4, 4, 4, 4, 4, 4, 0), -14),
+    ((b"N", b"N", 4, 4, 4, 4, 4, 4, 3, 1), -15),
     ((b"N", b"N", 4, 4, 4, 4, 4, 4, -2, 0), -14),
     ((b"N", b"N", 4, 4, 4, 4, 4, 4, 1, 5), -15),
 ])
