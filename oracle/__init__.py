@@ -8,6 +8,7 @@ input generators in ``workloads``.
 Contents
   oracle_dgemm(A, B, C, alpha, beta)        plain definition (Sec. 2.1/2.2)
   oracle_strassen(A, B, C, alpha, beta, L)  recursive textbook Strassen (Sec. 3.1-3.2)
+  oracle_winograd(A, B, C, alpha, beta, L)  recursive Winograd variant (Strassen-like scheme)
   oracle_dgemm_dot2(...)                    compensated reference (error yardstick)
   tables                                    the paper's operation tables (Fig. one-level,
                                             Fig. two-level via the Kronecker rule)
@@ -45,6 +46,8 @@ def _load():
         lib.oracle_dgemm_dot2.restype = ctypes.c_int
         lib.oracle_strassen.argtypes = sig + [ctypes.c_int]
         lib.oracle_strassen.restype = ctypes.c_int
+        lib.oracle_winograd.argtypes = sig + [ctypes.c_int]
+        lib.oracle_winograd.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -86,6 +89,11 @@ def oracle_dgemm_dot2(A, B, C, alpha=1.0, beta=1.0):
 def oracle_strassen(A, B, C, alpha=1.0, beta=1.0, levels=1):
     """C := alpha*(A*B by `levels` levels of recursive Strassen) + beta*C in place."""
     return _call(_load().oracle_strassen, A, B, C, alpha, beta, int(levels))
+
+
+def oracle_winograd(A, B, C, alpha=1.0, beta=1.0, levels=1):
+    """C := alpha*(A*B by `levels` levels of Winograd's variant) + beta*C in place."""
+    return _call(_load().oracle_winograd, A, B, C, alpha, beta, int(levels))
 
 
 def fortran(X, ld=None):

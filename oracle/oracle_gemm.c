@@ -12,6 +12,10 @@
  *   oracle_dgemm     — the definition of Sec. 2.1 ("Computing C = alpha A B + C"),
  *                      with the BLAS beta of Sec. 2.2: each c_ij is alpha times the
  *                      sum over p of a_ip*b_pj, summed in increasing p, plus beta*c_ij.
+ *   oracle_winograd  — recursive Winograd variant (the Strassen-like scheme of the
+ *                      paper's references and future work): seven products whose
+ *                      operand sums and C sums reuse one another (15 additions per
+ *                      level instead of 18), same padding and base case.
  *   oracle_strassen  — classic recursive Strassen (Sec. 3.2), each level being the
  *                      seven operations of Fig. "All operations for one-level
  *                      Strassen" (Sec. 3.1) written out with explicit temporaries.
@@ -166,6 +170,94 @@ int oracle_strassen(int64_t m, int64_t n, int64_t k, double alpha,
     if (!P) return 1;
     int rc = 0;
     if (k > 0 && alpha != 0.0) rc = strassen_product(m, n, k, A, lda, B, ldb, P, levels);
+    scale_add(m, n, alpha, P, m, beta, C, ldc);
+    free(P);
+    return rc;
+}
+
+/* ---- recursive Winograd variant ------------------------------------------ */
+
+/* Z := X - Y (or X + Y), elementwise over len entries. */
+static void sub_into(int64_t len, const double *X, const double *Y, double *Z)
+{
+    for (int64_t e = 0; e < len; ++e) Z[e] = X[e] - Y[e];
+}
+
+/* P := X*Y (overwrite) with `levels` levels of Winograd's variant of Strassen's
+ * algorithm (seven products; the operand sums reuse each other, S2 = S1 - A00,
+ * S4 = A01 - S2, T2 = B11 - T1, T4 = T2 - B10, and so do the sums that form C,
+ * U2 = M1 + M6, U3 = U2 + M7, U4 = U2 + M5), the plain product below them.
+ * Same zero padding of odd dimensions as strassen_product. */
+static int winograd_product(int64_t m, int64_t n, int64_t k,
+                            const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                            double *P, int levels)
+{
+    if (levels == 0) { plain_product(m, n, k, X, ldx, Y, ldy, P, m); return 0; }
+    const int64_t h = (m + 1) / 2, w = (n + 1) / 2, d = (k + 1) / 2;
+    const int64_t sa = h * d, sb = d * w, sc = h * w;
+    double *buf = (double *)calloc((size_t)(8 * sa + 8 * sb + 11 * sc), sizeof(double));
+    if (!buf) return 1;
+    double *A00 = buf, *A01 = A00 + sa, *A10 = A01 + sa, *A11 = A10 + sa;
+    double *S1 = A11 + sa, *S2 = S1 + sa, *S3 = S2 + sa, *S4 = S3 + sa;
+    double *B00 = S4 + sa, *B01 = B00 + sb, *B10 = B01 + sb, *B11 = B10 + sb;
+    double *T1 = B11 + sb, *T2 = T1 + sb, *T3 = T2 + sb, *T4 = T3 + sb;
+    double *M[8];
+    M[1] = T4 + sb;
+    for (int i = 2; i <= 7; ++i) M[i] = M[i - 1] + sc;
+    double *U2 = M[7] + sc, *U3 = U2 + sc, *Q = U3 + sc;
+    get_quadrant(X, ldx, m, k, 0, 0, h, d, A00);
+    get_quadrant(X, ldx, m, k, 0, 1, h, d, A01);
+    get_quadrant(X, ldx, m, k, 1, 0, h, d, A10);
+    get_quadrant(X, ldx, m, k, 1, 1, h, d, A11);
+    get_quadrant(Y, ldy, k, n, 0, 0, d, w, B00);
+    get_quadrant(Y, ldy, k, n, 0, 1, d, w, B01);
+    get_quadrant(Y, ldy, k, n, 1, 0, d, w, B10);
+    get_quadrant(Y, ldy, k, n, 1, 1, d, w, B11);
+    add_into(sa, A10, 1, A11, 1, S1);          /* S1 = A10 + A11 */
+    sub_into(sa, S1, A00, S2);                 /* S2 = S1 - A00  */
+    sub_into(sa, A00, A10, S3);                /* S3 = A00 - A10 */
+    sub_into(sa, A01, S2, S4);                 /* S4 = A01 - S2  */
+    sub_into(sb, B01, B00, T1);                /* T1 = B01 - B00 */
+    sub_into(sb, B11, T1, T2);                 /* T2 = B11 - T1  */
+    sub_into(sb, B11, B01, T3);                /* T3 = B11 - B01 */
+    sub_into(sb, T2, B10, T4);                 /* T4 = T2 - B10  */
+    int rc = 0;
+    rc |= winograd_product(h, w, d, A00, h, B00, d, M[1], levels - 1);   /* M1 = A00 B00 */
+    rc |= winograd_product(h, w, d, A01, h, B10, d, M[2], levels - 1);   /* M2 = A01 B10 */
+    rc |= winograd_product(h, w, d, S4, h, B11, d, M[3], levels - 1);    /* M3 = S4 B11  */
+    rc |= winograd_product(h, w, d, A11, h, T4, d, M[4], levels - 1);    /* M4 = A11 T4  */
+    rc |= winograd_product(h, w, d, S1, h, T1, d, M[5], levels - 1);     /* M5 = S1 T1   */
+    rc |= winograd_product(h, w, d, S2, h, T2, d, M[6], levels - 1);     /* M6 = S2 T2   */
+    rc |= winograd_product(h, w, d, S3, h, T3, d, M[7], levels - 1);     /* M7 = S3 T3   */
+    add_into(sc, M[1], 1, M[6], 1, U2);        /* U2 = M1 + M6 */
+    add_into(sc, U2, 1, M[7], 1, U3);          /* U3 = U2 + M7 */
+    /* the four C blocks: C00 = M1 + M2, C01 = (U2 + M5) + M3, C10 = U3 - M4,
+     * C11 = U3 + M5 */
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t e = (i % h) + (j % w) * h;
+            double v;
+            if (i < h && j < w) v = M[1][e] + M[2][e];
+            else if (i < h) v = (U2[e] + M[5][e]) + M[3][e];
+            else if (j < w) v = U3[e] - M[4][e];
+            else v = U3[e] + M[5][e];
+            P[i + j * m] = v;
+        }
+    (void)Q;
+    free(buf);
+    return rc;
+}
+
+int oracle_winograd(int64_t m, int64_t n, int64_t k, double alpha,
+                    const double *A, int64_t lda, const double *B, int64_t ldb,
+                    double beta, double *C, int64_t ldc, int levels)
+{
+    if (m <= 0 || n <= 0) return 0;
+    if (levels < 0) return -12;
+    double *P = (double *)calloc((size_t)m * (size_t)n, sizeof(double));
+    if (!P) return 1;
+    int rc = 0;
+    if (k > 0 && alpha != 0.0) rc = winograd_product(m, n, k, A, lda, B, ldb, P, levels);
     scale_add(m, n, alpha, P, m, beta, C, ldc);
     free(P);
     return rc;

@@ -43,6 +43,39 @@ ONE_LEVEL = [
 
 CLASSICAL = [([((0, 0), P)], [((0, 0), P)], [((0, 0), P)])]
 
+# Winograd's variant (the Strassen-like scheme among the paper's references) in the general
+# operation form: each product's operands flattened to signed sums of quadrants, and every
+# C block it reaches.  With S1 = A10 + A11, S2 = S1 - A00, S3 = A00 - A10, S4 = A01 - S2,
+# T1 = B01 - B00, T2 = B11 - T1, T3 = B11 - B01, T4 = T2 - B10, the products are
+# M1 = A00 B00, M2 = A01 B10, M3 = S4 B11, M4 = A11 T4, M5 = S1 T1, M6 = S2 T2, M7 = S3 T3 and
+# C00 = M1 + M2, C01 = M1 + M6 + M5 + M3, C10 = M1 + M6 + M7 - M4, C11 = M1 + M6 + M7 + M5.
+WINOGRAD = [
+    ([((0, 0), P)], [((0, 0), P)], [((0, 0), P), ((0, 1), P), ((1, 0), P), ((1, 1), P)]),
+    ([((0, 1), P)], [((1, 0), P)], [((0, 0), P)]),
+    ([((0, 1), P), ((1, 0), M_), ((1, 1), M_), ((0, 0), P)], [((1, 1), P)], [((0, 1), P)]),
+    ([((1, 1), P)], [((1, 1), P), ((0, 1), M_), ((0, 0), P), ((1, 0), M_)], [((1, 0), M_)]),
+    ([((1, 0), P), ((1, 1), P)], [((0, 1), P), ((0, 0), M_)], [((0, 1), P), ((1, 1), P)]),
+    ([((1, 0), P), ((1, 1), P), ((0, 0), M_)], [((1, 1), P), ((0, 1), M_), ((0, 0), P)],
+     [((0, 1), P), ((1, 0), P), ((1, 1), P)]),
+    ([((0, 0), P), ((1, 0), M_)], [((1, 1), P), ((0, 1), M_)], [((1, 0), P), ((1, 1), P)]),
+]
+
+
+def winograd_table(levels):
+    """Winograd's variant composed over `levels` levels (same rule as table())."""
+    if levels == 0:
+        return table(0)
+    t = [tuple(list(x) for x in row) for row in WINOGRAD]
+    for lev in range(2, levels + 1):
+        q_in = 2 ** (lev - 1)
+        inner = t
+        t = []
+        for (oa, ob, oc) in WINOGRAD:
+            for (ia, ib, ic) in inner:
+                t.append((_compose_terms(oa, ia, q_in), _compose_terms(ob, ib, q_in),
+                          _compose_terms(oc, ic, q_in)))
+    return t
+
 
 def _compose_terms(outer, inner, q_in):
     out = []
