@@ -673,7 +673,9 @@ def main():
         members = {"L0_abc": (0, "abc", -1), "L1_abc": (1, "abc", -1), "L1_ab": (1, "ab", -1),
                    "L1_naive": (1, "naive", -1), "L2_abc": (2, "abc", 4),
                    "L2_abc_staged": (2, "abc", -1), "L2_ab": (2, "ab", -1),
-                   "L2_naive": (2, "naive", -1)}
+                   "L2_naive": (2, "naive", -1),
+                   # Winograd's variant (ABC; two levels with staged outer chain sums)
+                   "L1_winograd": (1, "winograd", -1), "L2_winograd": (2, "winograd", -1)}
 
         def one(key):
             if key == "vendor":
@@ -681,7 +683,10 @@ def main():
                 cfg = -1
             else:
                 lev, var, cfg = members[key]
-                f = lambda: sx.dgemm(A, B, Cw, 1.0, 1.0, lev, var, stream)
+                if var == "winograd":
+                    f = lambda: sx.dgemm_winograd(A, B, Cw, 1.0, 1.0, lev, stream)
+                else:
+                    f = lambda: sx.dgemm(A, B, Cw, 1.0, 1.0, lev, var, stream)
             if cfg >= 0:
                 sx.set_tile_config(cfg)
             try:

@@ -129,6 +129,30 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
                    int levels, int variant, void *stream);
 
 /*
+ * strassen_dgemm_winograd — C := alpha*A*B + beta*C with `levels` (1 or 2) levels of Winograd's
+ * variant of Strassen's algorithm (a Strassen-like scheme among the paper's references and
+ * future work), in the ABC form: seven products per level,
+ *   M1 = A00 B00, M2 = A01 B10, M3 = S4 B11, M4 = A11 T4, M5 = S1 T1, M6 = S2 T2, M7 = S3 T3,
+ * with the operand sums formed in the load by Winograd's chain (S1 = A10 + A11, S2 = S1 - A00,
+ * S3 = A00 - A10, S4 = A01 - S2; T1 = B01 - B00, T2 = B11 - T1, T3 = B11 - B01, T4 = T2 - B10:
+ * eight additions per level where Strassen's table needs ten), and every product added in the
+ * epilogue to each C block it reaches (C00 = M1 + M2, C01 = M1 + M3 + M5 + M6,
+ * C10 = M1 - M4 + M6 + M7, C11 = M1 + M5 + M6 + M7), in product order.  Two levels stage the
+ * outer chain sums in workspace (four m/2 x k/2 and four k/2 x n/2 slots) and run one launch
+ * per outer product.  Sizes, layouts and conventions as strassen_dgemm; block-padded copies
+ * where m or k is not a multiple of 2^(L+1), n (two levels) not a multiple of 4, an operand is
+ * not 16-byte aligned or a leading dimension odd.  Workspace (copies, staging:
+ * strassen_workspace_size_winograd) is required: STRASSEN_ERR_ALLOC when it cannot be had.
+ * Argument positions for -i as strassen_dgemm, levels = 12.
+ */
+int strassen_dgemm_winograd(int64_t m, int64_t n, int64_t k, double alpha,
+                            const double *A, int64_t lda, const double *B, int64_t ldb,
+                            double beta, double *C, int64_t ldc, int levels, void *stream);
+/* Workspace bytes of strassen_dgemm_winograd for aligned operands with even leading dimensions.
+ * Returns 0 or -i (m=1 n=2 k=3 levels=4 bytes=5). */
+int strassen_workspace_size_winograd(int64_t m, int64_t n, int64_t k, int levels, size_t *bytes);
+
+/*
  * strassen_gemm — the full dgemm interface of Sec. 2.2 with transposes:
  *   C := alpha * op(A) * op(B) + beta * C,   op(X) = X (trans 'N'/'n') or X^T ('T'/'t'/'C'/'c')
  * op(A) is m x k (A is m x k with lda >= max(1,m), or k x m with lda >= max(1,k) when

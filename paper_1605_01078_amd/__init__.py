@@ -43,6 +43,11 @@ def lib():
         L.strassen_dgemm.restype = ci
         L.strassen_gemm.argtypes = [ctypes.c_char, ctypes.c_char] + gemm + [vp]
         L.strassen_gemm.restype = ci
+        L.strassen_dgemm_winograd.argtypes = gemm[:-1] + [vp]
+        L.strassen_dgemm_winograd.restype = ci
+        L.strassen_workspace_size_winograd.argtypes = [i64, i64, i64, ci,
+                                                       ctypes.POINTER(ctypes.c_size_t)]
+        L.strassen_workspace_size_winograd.restype = ci
         L.strassen_dgemm_noalloc.argtypes = gemm + [vp]
         L.strassen_dgemm_noalloc.restype = ci
         L.strassen_gemm_ex.argtypes = gemm + [ci, ci, ci, vp]
@@ -221,6 +226,24 @@ def gemm(A, B, C, alpha=1.0, beta=1.0, transa="N", transb="N", levels=-1, varian
     check(lib().strassen_gemm(transa.encode(), transb.encode(), m, n, k, alpha, pa, lda, pb, ldb,
                               beta, pc, ldc, int(levels), _variant(variant), _stream(stream)))
     return C
+
+
+def dgemm_winograd(A, B, C, alpha=1.0, beta=1.0, levels=1, stream=None):
+    """C := alpha*A*B + beta*C with `levels` (1, 2) levels of Winograd's variant (ABC)."""
+    pa, m, k, lda = _mat(A, "A")
+    pb, k2, n, ldb = _mat(B, "B")
+    pc, m2, n2, ldc = _mat(C, "C")
+    if k2 != k or m2 != m or n2 != n:
+        raise ValueError(f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    check(lib().strassen_dgemm_winograd(m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc,
+                                        int(levels), _stream(stream)))
+    return C
+
+
+def workspace_size_winograd(m, n, k, levels):
+    out = ctypes.c_size_t(0)
+    check(lib().strassen_workspace_size_winograd(m, n, k, levels, ctypes.byref(out)))
+    return out.value
 
 
 def dgemm_noalloc(A, B, C, alpha=1.0, beta=1.0, levels=1, variant="abc", stream=None):

@@ -979,6 +979,206 @@ static int run_scale(double* C, int64_t ldc, int64_t m, int64_t n, double beta, 
   return 0;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Winograd's variant (a Strassen-like scheme of the paper's references and future work), ABC:
+// one level is one launch of the all-products kernel with Winograd's table (the chain sums
+// formed on the fragments); two levels stage the outer chain sums (four slots per side) and run
+// one launch per outer product, each adding its seven inner products into the inner sub-blocks
+// of every outer block that product reaches (up to four), in product order.
+// ---------------------------------------------------------------------------------------------
+struct WPlan {
+  int levels;
+  int64_t mq, kq, nq, mq_e, kq_e;   // innermost sub-block extents, plain and padded (even)
+  int64_t mp, kp, np;               // padded problem
+  bool pa, pb, pc, ok;
+  int64_t a_off, b_off, c_off, sa, sb, sa_stride, sb_stride, total;   // doubles
+};
+
+static WPlan make_w_plan(int64_t m, int64_t n, int64_t k, int levels, const double* A,
+                         int64_t lda, const double* B, int64_t ldb, const double* C, int64_t ldc) {
+  WPlan p;
+  p.levels = levels;
+  const int64_t q = int64_t(1) << levels;
+  p.mq = cdiv(m, q);
+  p.kq = cdiv(k, q);
+  p.nq = cdiv(n, q);
+  p.mq_e = round_up(p.mq, 2);
+  p.kq_e = round_up(p.kq, 2);
+  p.mp = q * p.mq_e;
+  p.kp = q * p.kq_e;
+  p.np = levels == 2 ? q * p.nq : n;   // staged B sums need every outer column block full
+  const int64_t lim = int64_t(1) << 31;
+  p.pa = p.mp != m || p.kp != k || !aligned16(A) || lda % 2 != 0 || 8 * 16 * lda >= lim;
+  p.pb = p.kp != k || p.np != n || !aligned16(B) || ldb % 2 != 0 || 8 * 64 * ldb >= lim;
+  p.pc = p.mp != m || p.np != n || !aligned16(C) || ldc % 2 != 0 || 8 * 64 * ldc >= lim;
+  p.ok = 8 * 16 * (p.pa ? p.mp : lda) < lim && 8 * 64 * (p.pb ? p.kp : ldb) < lim &&
+         8 * 64 * (p.pc ? p.mp : ldc) < lim;
+  int64_t off = 0;
+  auto take = [&](bool used, int64_t elems) {
+    const int64_t at = off;
+    if (used) off += round_up(elems, 32);
+    return at;
+  };
+  p.a_off = take(p.pa, p.mp * p.kp);
+  p.b_off = take(p.pb, p.kp * p.np);
+  p.c_off = take(p.pc, p.mp * p.np);
+  p.sa_stride = round_up((p.mp / 2) * (p.kp / 2), 32);
+  p.sb_stride = round_up((p.kp / 2) * (p.np / 2), 32);
+  p.sa = take(levels == 2, 4 * p.sa_stride);
+  p.sb = take(levels == 2, 4 * p.sb_stride);
+  p.total = off;
+  return p;
+}
+
+static int run_winograd(const WPlan& wp, double alpha, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                        double* ws, hipStream_t stream) {
+  FusedArgs f;
+  std::memset(&f, 0, sizeof f);
+  f.scheme = 1;
+  f.C = C;
+  f.ldc = ldc;
+  f.n = wp.np;
+  f.mq = wp.mq_e;
+  f.nq = wp.nq;
+  f.kq = wp.kq_e;
+  f.alpha = alpha;
+  f.beta = beta;
+  f.tiles_m = (int32_t)cdiv(f.mq, 64);
+  f.tiles_n = (int32_t)cdiv(f.nq, 64);
+  f.a_sg[0] = f.b_sg[0] = 1.0;
+  if (wp.levels == 1) {
+    f.A = A;
+    f.lda = lda;
+    f.B = B;
+    f.ldb = ldb;
+    f.nc = 1;
+    f.c_first = 1;
+    f.c_sg[0] = 1.0;
+    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, 1, 1, stream));
+    return 0;
+  }
+  // two levels: outer blocks of m1 x k1 (A), k1 x n1 (B), m1 x n1 (C)
+  const int64_t m1 = 2 * wp.mq_e, k1 = 2 * wp.kq_e, n1 = 2 * wp.nq;
+  double* SA = ws + wp.sa;
+  double* SB = ws + wp.sb;
+  ChainSumArgs ca;
+  std::memset(&ca, 0, sizeof ca);
+  ca.src = A;
+  ca.dst = SA;
+  ca.ld = lda;
+  ca.rows = m1;
+  ca.cols = k1;
+  ca.dst_stride = wp.sa_stride;
+  ChainSumArgs cb = ca;
+  cb.src = B;
+  cb.dst = SB;
+  cb.ld = ldb;
+  cb.rows = k1;
+  cb.cols = n1;
+  cb.dst_stride = wp.sb_stride;
+  for (int q = 0; q < 4; ++q) {
+    ca.blk[q] = (q >> 1) * m1 + (q & 1) * k1 * lda;
+    cb.blk[q] = (q >> 1) * k1 + (q & 1) * n1 * ldb;
+  }
+  SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_chain_sums(ca, 0, stream));
+  SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_chain_sums(cb, 1, stream));
+  bool touched[4] = {false, false, false, false};
+  for (int R = 0; R < 7; ++R) {
+    const WProduct& P = kWinograd[R];
+    if (P.a < 4) {
+      f.A = A + ca.blk[P.a];
+      f.lda = lda;
+    } else {
+      f.A = SA + (P.a - 4) * wp.sa_stride;
+      f.lda = m1;
+    }
+    if (P.b < 4) {
+      f.B = B + cb.blk[P.b];
+      f.ldb = ldb;
+    } else {
+      f.B = SB + (P.b - 4) * wp.sb_stride;
+      f.ldb = k1;
+    }
+    f.nc = P.nc;
+    f.c_first = 0;
+    for (int d = 0; d < P.nc; ++d) {
+      const int q = P.c[d].q;
+      f.c_off[d] = (q >> 1) * m1 + (q & 1) * n1 * ldc;
+      f.c_cb[d] = 2 * (q & 1);
+      f.c_sg[d] = P.c[d].sign;
+      if (!touched[q]) f.c_first |= 1 << d;
+      touched[q] = true;
+    }
+    SMX_LAUNCH(STRASSEN_KERNEL_ALL_PRODUCTS, stream, launch_all_products(f, 1, 1, stream));
+  }
+  return 0;
+}
+
+int dgemm_winograd(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
+                   const WsSource& wsrc, hipStream_t stream) {
+  g_last_error.clear();
+  if (levels < 1 || levels > 2) return fail(-12, "levels = %d not in 1..2", levels);
+  if (int rc = validate(m, n, k, alpha, A, lda, B, ldb, C, ldc, levels, STRASSEN_ABC)) return rc;
+  if (m == 0 || n == 0) return 0;
+  if (alpha == 0.0 || k == 0) {
+    if (beta == 1.0) return 0;
+    int dev = 0;
+    if (int rc = device_ready(&dev)) return rc;
+    return run_scale(C, ldc, m, n, beta, stream);
+  }
+  const WPlan wp = make_w_plan(m, n, k, levels, A, lda, B, ldb, C, ldc);
+  if (!wp.ok) return fail(STRASSEN_ERR_UNSUPPORTED, "sizes past the 32-bit tile offsets");
+  if ((int64_t)cdiv(wp.mq_e, 64) * cdiv(wp.nq, 64) >= (int64_t(1) << 30))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+  const size_t bytes = (size_t)wp.total * sizeof(double);
+  if (bytes > 0 && !wsrc.fits(bytes))
+    return fail(STRASSEN_ERR_ALLOC, "Winograd's variant needs %zu bytes of workspace here (%s), "
+                "%zu available", bytes, levels == 2 ? "staged outer sums" : "block-padded copies",
+                wsrc.bytes);
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
+  double* ws = nullptr;
+  if (bytes > 0) {
+    void* w = nullptr;
+    if (int rc = get_workspace(wsrc, dev, bytes, &w)) return rc;
+    ws = static_cast<double*>(w);
+  }
+  const double* Ap = A;
+  const double* Bp = B;
+  double* Cp = C;
+  int64_t la = lda, lb = ldb, lc = ldc;
+  if (wp.pa) {
+    if (int rc = pad_copy(A, lda, m, k, wp.mq, wp.mq_e, wp.kq, wp.kq_e, ws + wp.a_off, wp.mp,
+                          wp.mp, wp.kp, 0, stream))
+      return rc;
+    Ap = ws + wp.a_off;
+    la = wp.mp;
+  }
+  if (wp.pb) {
+    if (int rc = pad_copy(B, ldb, k, n, wp.kq, wp.kq_e, wp.np, wp.np, ws + wp.b_off, wp.kp, wp.kp,
+                          wp.np, 0, stream))
+      return rc;
+    Bp = ws + wp.b_off;
+    lb = wp.kp;
+  }
+  if (wp.pc) {
+    Cp = ws + wp.c_off;
+    lc = wp.mp;
+    if (beta != 0.0)
+      if (int rc = pad_copy(C, ldc, m, n, wp.mq, wp.mq_e, wp.np, wp.np, Cp, wp.mp, wp.mp, wp.np,
+                            0, stream))
+        return rc;
+  }
+  if (int rc = run_winograd(wp, alpha, Ap, la, Bp, lb, beta, Cp, lc, ws, stream)) return rc;
+  if (wp.pc)
+    if (int rc = pad_copy(Cp, wp.mp, m, n, wp.mq, wp.mq_e, wp.np, wp.np, C, ldc, wp.mp, wp.np, 1,
+                          stream))
+      return rc;
+  return 0;
+}
+
 // Whether the general tile kernel's 32-bit lane offsets reach every element of its tiles: a
 // tile spans at most 128 columns of B, C and the temporaries and 16 of A (8 bytes each), and
 // each access is one wave-uniform base plus a per-lane offset below 2^31 bytes.
@@ -1530,6 +1730,28 @@ int strassen_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, dou
                   double* C, int64_t ldc, int levels, int variant, void* stream) {
   return smx::gemm_t(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels,
                      variant, smx::default_workspace(), static_cast<hipStream_t>(stream));
+}
+
+int strassen_dgemm_winograd(int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                            int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                            int64_t ldc, int levels, void* stream) {
+  return smx::dgemm_winograd(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, levels,
+                             smx::default_workspace(), static_cast<hipStream_t>(stream));
+}
+
+int strassen_workspace_size_winograd(int64_t m, int64_t n, int64_t k, int levels, size_t* bytes) {
+  smx::g_last_error.clear();
+  if (m < 0) return smx::fail(-1, "m < 0");
+  if (n < 0) return smx::fail(-2, "n < 0");
+  if (k < 0) return smx::fail(-3, "k < 0");
+  if (levels < 1 || levels > 2) return smx::fail(-4, "levels out of range");
+  if (!bytes) return smx::fail(-5, "bytes is NULL");
+  *bytes = (m == 0 || n == 0 || k == 0)
+               ? 0
+               : (size_t)smx::make_w_plan(m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2), nullptr,
+                                          2 * smx::cdiv(k, 2), nullptr, 2 * smx::cdiv(m, 2))
+                         .total * sizeof(double);
+  return 0;
 }
 
 int strassen_workspace_size(int64_t m, int64_t n, int64_t k, int levels, int variant,

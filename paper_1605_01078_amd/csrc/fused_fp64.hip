@@ -64,7 +64,11 @@ __device__ __forceinline__ d2_t fma2(double s, d2_t x, d2_t y) {
 // so the loads need no per-lane range masks; the registers this frees keep the main loop free of
 // spill reloads, whose wait on the vector-memory counter would also wait for the tile loads just
 // issued and stall the pipeline.
-template <int NA, int NB, int BK, int NS, bool FULL>
+// SCHEME 0: Strassen's one-level table; 1: Winograd's variant (one term per side only): the
+// chain sums S1..S4 and T1..T4 are formed on the fragments in the chain's order (S2 from the
+// rounded S1, and so on, as the recursive algorithm rounds them) and the C epilogue adds every
+// product to each quadrant it reaches, in product order.
+template <int NA, int NB, int BK, int NS, bool FULL, int SCHEME = 0>
 struct AllProducts {
   static constexpr int T = 64;                    // tile edge inside one inner sub-block
   static constexpr int NT = 512;
@@ -81,6 +85,7 @@ struct AllProducts {
   static_assert((NTILES * IPT) % 8 == 0 && (4 * NA * IPT) % 8 == 0, "load split");
   static_assert(NS == 2 || (NS == 3 && NPAIR == 1), "stages");
   static_assert(LDS_D * 8 <= 160 * 1024, "LDS");
+  static_assert(SCHEME == 0 || (NA == 1 && NB == 1), "Winograd's variant: one term per side");
 
   typedef d4_t Acc[7][2];
 
@@ -207,9 +212,39 @@ struct AllProducts {
       acc[r][1] = (d4_t){0.0, 0.0, 0.0, 0.0};
     }
 
+    // Winograd's variant: the chain sums (A: S1..S4 per MFMA e on row pairs; B: T1..T4 per e)
+    // and the 28 MFMAs of one group of eight k values.
+    auto mfma_frag_winograd = [&](const Frag& f) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        d2_t ao[8];
+        double bo[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ao[q] = f.a[q][e];
+          bo[q] = e == 0 ? f.b[q].x : f.b[q].y;
+        }
+        ao[4] = ao[2] + ao[3];   // S1 = A10 + A11
+        ao[5] = ao[4] - ao[0];   // S2 = S1 - A00
+        ao[6] = ao[0] - ao[2];   // S3 = A00 - A10
+        ao[7] = ao[1] - ao[5];   // S4 = A01 - S2
+        bo[4] = bo[1] - bo[0];   // T1 = B01 - B00
+        bo[5] = bo[3] - bo[4];   // T2 = B11 - T1
+        bo[6] = bo[3] - bo[1];   // T3 = B11 - B01
+        bo[7] = bo[5] - bo[2];   // T4 = T2 - B10
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+          const WProduct& P = kWinograd[r];
+          acc[r][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(bo[P.b], ao[P.a].x, acc[r][0], 0, 0, 0);
+          acc[r][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bo[P.b], ao[P.a].y, acc[r][1], 0, 0, 0);
+        }
+      }
+    };
+
     // Inner sums (the one-level table; every first inner term has sign +1) and the 28 MFMAs of
     // one group of eight k values.
     auto mfma_frag = [&](const Frag& f) {
+      if (SCHEME == 1) return mfma_frag_winograd(f);
 #pragma unroll
       for (int r = 0; r < 7; ++r) {
         const QProduct& P = kOneLevel[r];
@@ -365,11 +400,12 @@ struct AllProducts {
           bool first = first_outer;
 #pragma unroll
           for (int r = 0; r < 7; ++r) {
-            const QProduct& P = kOneLevel[r];
+            const int nc = SCHEME == 1 ? kWinograd[r].nc : kOneLevel[r].nc;
 #pragma unroll
-            for (int dd = 0; dd < 2; ++dd) {
-              if (dd < P.nc && P.c[dd].q == cq) {
-                const double ag = P.c[dd].sign > 0 ? ag_outer : -ag_outer;
+            for (int dd = 0; dd < 4; ++dd) {
+              const QTerm t = SCHEME == 1 ? kWinograd[r].c[dd] : kOneLevel[r].c[dd < 2 ? dd : 0];
+              if (dd < nc && t.q == cq) {
+                const double ag = t.sign > 0 ? ag_outer : -ag_outer;
                 c.x = c_update(c.x, acc[r][0][e], ag, args.beta, first);
                 c.y = c_update(c.y, acc[r][1][e], ag, args.beta, first);
                 first = false;
@@ -384,9 +420,9 @@ struct AllProducts {
   }
 };
 
-template <int NA, int NB, int BK, int NS, bool FULL>
+template <int NA, int NB, int BK, int NS, bool FULL, int SCHEME = 0>
 __global__ __launch_bounds__(512, 1) void all_products_kernel(const FusedArgs args) {
-  using K = AllProducts<NA, NB, BK, NS, FULL>;
+  using K = AllProducts<NA, NB, BK, NS, FULL, SCHEME>;
   __shared__ __attribute__((aligned(16))) double lds[K::LDS_D];
   K::template run<false>(args, lds);
 }
@@ -408,9 +444,14 @@ const void* all_products_fn(const FusedArgs& a, int na, int nb) {
   for (int t = 0; t < nb; ++t) cb_max = cb_max > a.b_cb[t] ? cb_max : a.b_cb[t];
   const bool full = a.mq % 64 == 0 && a.nq % 64 == 0 && a.kq % 16 == 0 && (cb_max + 2) * a.nq <= a.n;
   if (a.store_m) {   // the AB form: one term per side (one level, or staged two-level sums)
-    if (na != 1 || nb != 1) return nullptr;
+    if (na != 1 || nb != 1 || a.scheme != 0) return nullptr;
     return full ? (const void*)all_products_store_kernel<1, 1, 16, 2, true>
                 : (const void*)all_products_store_kernel<1, 1, 16, 2, false>;
+  }
+  if (a.scheme == 1) {   // Winograd's variant: ABC, one term per side
+    if (na != 1 || nb != 1) return nullptr;
+    return full ? (const void*)all_products_kernel<1, 1, 16, 2, true, 1>
+                : (const void*)all_products_kernel<1, 1, 16, 2, false, 1>;
   }
   if (na == 1 && nb == 1 && full) return (const void*)all_products_kernel<1, 1, 16, 2, true>;
   if (na == 1 && nb == 1) return (const void*)all_products_kernel<1, 1, 16, 2, false>;

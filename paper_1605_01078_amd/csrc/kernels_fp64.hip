@@ -158,6 +158,40 @@ __global__ __launch_bounds__(256) void outer_sum_kernel(const OuterSumArgs args)
   }
 }
 
+// Winograd's variant, staged outer level: the same walk as outer_sum_kernel, writing the four
+// chain sums of the side (A: S1 = X10 + X11, S2 = S1 - X00, S3 = X00 - X10, S4 = X01 - S2;
+// B: T1 = X01 - X00, T2 = X11 - T1, T3 = X11 - X01, T4 = T2 - X10), each rounded once from the
+// rounded sums before it, as the recursive algorithm forms them.
+template <int SIDE>
+__global__ __launch_bounds__(256) void chain_sum_kernel(const ChainSumArgs args) {
+  const int64_t i = (int64_t)(blockIdx.x % args.chunks_r) * kOuterSumRows + 2 * threadIdx.x;
+  const int64_t j0 = (int64_t)(blockIdx.x / args.chunks_r) * kOuterSumCols;
+  if (i >= args.rows) return;
+#pragma unroll
+  for (int c = 0; c < kOuterSumCols; ++c) {
+    if (j0 + c >= args.cols) break;
+    d2_t x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      x[q] = *reinterpret_cast<const d2_t*>(args.src + args.blk[q] + i + (j0 + c) * args.ld);
+    d2_t v[4];
+    if (SIDE == 0) {
+      v[0] = x[2] + x[3];
+      v[1] = v[0] - x[0];
+      v[2] = x[0] - x[2];
+      v[3] = x[1] - v[1];
+    } else {
+      v[0] = x[1] - x[0];
+      v[1] = x[3] - v[0];
+      v[2] = x[3] - x[1];
+      v[3] = v[1] - x[2];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      *reinterpret_cast<d2_t*>(args.dst + t * args.dst_stride + i + (j0 + c) * args.rows) = v[t];
+  }
+}
+
 __global__ __launch_bounds__(256) void scale_kernel(const ScaleArgs args, int chunks_m) {
   const int64_t j = blockIdx.x / chunks_m;
   const int64_t i = (int64_t)(blockIdx.x % chunks_m) * 256 + threadIdx.x;
@@ -224,6 +258,16 @@ hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s) {
   if (gx >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   if (side == 0) hipLaunchKernelGGL(outer_sum_kernel<0>, dim3((unsigned)gx), dim3(256), 0, s, b);
   else hipLaunchKernelGGL(outer_sum_kernel<1>, dim3((unsigned)gx), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_sums(const ChainSumArgs& a, int side, hipStream_t s) {
+  ChainSumArgs b = a;
+  b.chunks_r = (int32_t)((a.rows + kOuterSumRows - 1) / kOuterSumRows);
+  const int64_t gx = (int64_t)b.chunks_r * ((a.cols + kOuterSumCols - 1) / kOuterSumCols);
+  if (gx >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  if (side == 0) hipLaunchKernelGGL(chain_sum_kernel<0>, dim3((unsigned)gx), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL(chain_sum_kernel<1>, dim3((unsigned)gx), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v,
 hipError_t launch_assemble(const AssembleArgs& a, int q2, hipStream_t s);
 hipError_t launch_sums(const SumArgs& a, int nslots, hipStream_t s);
 hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s);   // side 0 A, 1 B
+hipError_t launch_chain_sums(const ChainSumArgs& a, int side, hipStream_t s);   // Winograd's
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 hipError_t launch_transpose(const TransposeArgs& a, hipStream_t s);
 hipError_t launch_pad_copy(const PadArgs& a, hipStream_t s);

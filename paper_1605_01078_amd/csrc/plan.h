@@ -90,6 +90,8 @@ struct FusedArgs {
   double* M;
   int64_t ldm, m_stride;
   int32_t store_m, prod_base;
+  int32_t scheme;               // 0: Strassen's table, 1: Winograd's variant (one term per side)
+  int32_t pad_;
 };
 
 // Classical FP64 GEMM on the all-products kernel's load path (levels = 0).
@@ -127,6 +129,12 @@ struct OuterSumArgs {
   int64_t blk[4];
   int32_t chunks_r;     // row chunks per column group (set by the launcher)
 };
+
+// Winograd's variant, staged outer level: the four chain sums of one side (S1..S4 of A, T1..T4
+// of B) over the four outer blocks of src (rows x cols each, leading dimension ld, at
+// src + blk[q]) into slots of rows x cols (leading dimension rows) at dst + s * dst_stride.
+// Same layout requirements as OuterSumArgs.
+typedef OuterSumArgs ChainSumArgs;
 
 // Block-padded copy.  Pad (unpad = 0): dst (dst_rows x dst_cols, leading dimension ld_d) gets
 // src (rows x cols, ld_s) with source row block b (rows [b*rb, b*rb + rb)) placed at destination
@@ -225,6 +233,22 @@ constexpr QProduct kOneLevel[7] = {
     {2, 1, 2, {{0, 1}, {1, 1}}, {{3, 1}, {0, 0}}, {{1, 1}, {0, -1}}},    // (A00+A01) B11
     {2, 2, 1, {{2, 1}, {0, -1}}, {{0, 1}, {1, 1}}, {{3, 1}, {0, 0}}},    // (A10-A00)(B00+B01)
     {2, 2, 1, {{1, 1}, {3, -1}}, {{2, 1}, {3, 1}}, {{0, 1}, {0, 0}}},    // (A01-A11)(B10+B11)
+};
+
+// Winograd's variant of the one-level table: operand 0..3 is quadrant q of A (B); 4..7 are the
+// chain sums S1 = A10 + A11, S2 = S1 - A00, S3 = A00 - A10, S4 = A01 - S2 (for B:
+// T1 = B01 - B00, T2 = B11 - T1, T3 = B11 - B01, T4 = T2 - B10); every C quadrant each product
+// reaches, with its sign.  C00 = M1 + M2, C01 = M1 + M3 + M5 + M6, C10 = M1 - M4 + M6 + M7,
+// C11 = M1 + M5 + M6 + M7.
+struct WProduct { int8_t a, b, nc; QTerm c[4]; };
+constexpr WProduct kWinograd[7] = {
+    {0, 0, 4, {{0, 1}, {1, 1}, {2, 1}, {3, 1}}},   // M1 = A00 B00
+    {1, 2, 1, {{0, 1}, {0, 0}, {0, 0}, {0, 0}}},   // M2 = A01 B10
+    {7, 3, 1, {{1, 1}, {0, 0}, {0, 0}, {0, 0}}},   // M3 = S4 B11
+    {3, 7, 1, {{2, -1}, {0, 0}, {0, 0}, {0, 0}}},  // M4 = A11 T4
+    {4, 4, 2, {{1, 1}, {3, 1}, {0, 0}, {0, 0}}},   // M5 = S1 T1
+    {5, 5, 3, {{1, 1}, {2, 1}, {3, 1}, {0, 0}}},   // M6 = S2 T2
+    {6, 6, 2, {{2, 1}, {3, 1}, {0, 0}, {0, 0}}},   // M7 = S3 T3
 };
 
 struct Term { int row, col, sign; };

@@ -291,3 +291,19 @@ def test_three_level_workspace():
     assert sx.workspace_size(m, n, k, 3, "abc") == want
     out = ctypes.c_size_t()
     assert sx.lib().strassen_workspace_size(64, 64, 64, 3, 1, ctypes.byref(out)) == -5
+
+
+def test_winograd_entry_point_checks_and_workspace():
+    L = sx.lib()
+    fake = 1 << 20
+    for levels in (0, 3):
+        assert L.strassen_dgemm_winograd(64, 64, 64, 1.0, fake, 64, fake, 64, 1.0, fake, 64,
+                                         levels, None) == -12
+    assert L.strassen_dgemm_winograd(64, 64, 64, 1.0, fake, 63, fake, 64, 1.0, fake, 64, 1,
+                                     None) == -6
+    r32 = lambda x: _cdiv(x, 32) * 32
+    assert sx.workspace_size_winograd(4096, 4096, 4096, 1) == 0
+    assert sx.workspace_size_winograd(4096, 4096, 4096, 2) == 8 * 8 * r32(2048 * 2048)
+    m, n, k = 1001, 998, 777
+    mp, kp = 2 * 2 * _cdiv(_cdiv(m, 2), 2), 2 * 2 * _cdiv(_cdiv(k, 2), 2)
+    assert sx.workspace_size_winograd(m, n, k, 1) == 8 * (r32(mp * kp) + r32(kp * n) + r32(mp * n))
