@@ -9,6 +9,7 @@ Contents
   oracle_dgemm(A, B, C, alpha, beta)        plain definition (Sec. 2.1/2.2)
   oracle_strassen(A, B, C, alpha, beta, L)  recursive textbook Strassen (Sec. 3.1-3.2)
   oracle_winograd(A, B, C, alpha, beta, L)  recursive Winograd variant (Strassen-like scheme)
+  oracle_lu_nopiv(A)                        LU without pivoting, plain elimination
   oracle_dgemm_dot2(...)                    compensated reference (error yardstick)
   tables                                    the paper's operation tables (Fig. one-level,
                                             Fig. two-level via the Kronecker rule)
@@ -48,6 +49,8 @@ def _load():
         lib.oracle_strassen.restype = ctypes.c_int
         lib.oracle_winograd.argtypes = sig + [ctypes.c_int]
         lib.oracle_winograd.restype = ctypes.c_int
+        lib.oracle_lu_nopiv.argtypes = [i64, ptr, i64]
+        lib.oracle_lu_nopiv.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -94,6 +97,15 @@ def oracle_strassen(A, B, C, alpha=1.0, beta=1.0, levels=1):
 def oracle_winograd(A, B, C, alpha=1.0, beta=1.0, levels=1):
     """C := alpha*(A*B by `levels` levels of Winograd's variant) + beta*C in place."""
     return _call(_load().oracle_winograd, A, B, C, alpha, beta, int(levels))
+
+
+def oracle_lu_nopiv(A):
+    """A = L U in place (no pivoting); returns 0, or p + 1 if pivot p was exactly zero."""
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("square matrix expected")
+    pa, lda = _colmajor(A, "A")
+    return _load().oracle_lu_nopiv(n, pa, lda)
 
 
 def fortran(X, ld=None):

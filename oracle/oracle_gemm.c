@@ -16,6 +16,8 @@
  *                      paper's references and future work): seven products whose
  *                      operand sums and C sums reuse one another (15 additions per
  *                      level instead of 18), same padding and base case.
+ *   oracle_lu_nopiv  — LU factorization without pivoting, plain elimination (the
+ *                      rank-k-update algorithm of the paper's future work, Sec. 6).
  *   oracle_strassen  — classic recursive Strassen (Sec. 3.2), each level being the
  *                      seven operations of Fig. "All operations for one-level
  *                      Strassen" (Sec. 3.1) written out with explicit temporaries.
@@ -261,6 +263,32 @@ int oracle_winograd(int64_t m, int64_t n, int64_t k, double alpha,
     scale_add(m, n, alpha, P, m, beta, C, ldc);
     free(P);
     return rc;
+}
+
+/* ---- LU factorization without pivoting ------------------------------------ */
+
+/* A = L U in place for the n x n matrix A (column-major, lda): L unit lower
+ * triangular below the diagonal, U upper triangular on and above it, by the
+ * plain right-looking elimination: for each p, the multipliers
+ * l_ip = a_ip / a_pp (i > p) replace column p below the diagonal, then
+ * a_ij := a_ij - l_ip a_pj for i, j > p.  No pivoting: the leading principal
+ * minors must be nonzero (as in a diagonally dominant matrix).  Returns p + 1
+ * if the pivot a_pp is exactly zero (A is then partly factored), else 0. */
+int oracle_lu_nopiv(int64_t n, double *A, int64_t lda)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        const double piv = A[p + p * lda];
+        if (piv == 0.0) return (int)(p + 1);
+        for (int64_t i = p + 1; i < n; ++i) A[i + p * lda] = A[i + p * lda] / piv;
+#pragma omp parallel for schedule(static)
+        for (int64_t j = p + 1; j < n; ++j) {
+            const double u = A[p + j * lda];
+            double *col = A + j * lda;
+            const double *l = A + p * lda;
+            for (int64_t i = p + 1; i < n; ++i) col[i] = col[i] - l[i] * u;
+        }
+    }
+    return 0;
 }
 
 /* Compensated dot products (Ogita, Rump and Oishi's Dot2: TwoProduct by
