@@ -67,13 +67,14 @@ def parse():
                    help="rounds of the round-robin member timing (median per member)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
-    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep", "levels"],
+    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep", "levels", "lu"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
                         "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
                         "one persistent graph launch; selector: the committed network's choice "
                         "against exhaustive timing on held-out shapes; sweep: every member on the "
                         "square sizes 2048..16384 and the rank-k shapes; levels: three levels "
-                        "against two and classical at 32768; each prints one JSON line")
+                        "against two and classical at 32768; lu: LU without pivoting with "
+                        "Strassen rank-k updates; each prints one JSON line")
     p.add_argument("--shapes", type=int, default=200,
                    help="selector suite: held-out shapes timed exhaustively")
     p.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -551,6 +552,101 @@ def levels_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def lu_suite(args):
+    """LU factorization without pivoting (strassen_dgetrf_nopiv) of a diagonally dominant n x n
+    matrix (default 16384; entries uniform[-1, 1] plus n on the diagonal), rank-nb updates with
+    0 (classical), 1, 2 and 3 levels of Strassen, and two block widths: round-robin event timing
+    (median of --reps), rate = (2/3) n^3 / t, the rank-nb update products of the blocked loop
+    timed on their own, and the backward error ||A - L U|| / ||A|| on sampled columns."""
+    import torch
+    import paper_1605_01078_amd as sx
+    from oracle import rel_fro
+    n = args.n
+    stream = torch.cuda.current_stream()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=g)
+    A0.diagonal().add_(float(n))
+    A0 = A0.t()
+    A = torch.empty_like(A0.t()).t()   # column-major work copy
+    flops = 2.0 / 3.0 * n ** 3
+    runs = {f"nb{nb}_L{lev}": (nb, lev) for nb in (2048, 4096) for lev in (0, 1, 2, 3)}
+    times = {key: [] for key in runs}
+
+    def one(nb, lev):
+        A.copy_(A0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sx.getrf_nopiv(A, nb, lev, stream)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+    for nb, lev in runs.values():
+        one(nb, lev)
+    for _ in range(args.reps):
+        for key, (nb, lev) in runs.items():
+            times[key].append(one(nb, lev))
+    out_runs = {}
+    for key in runs:
+        ms = float(np.median(times[key]))
+        out_runs[key] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
+        log(f"  LU n={n} {key}: {ms:8.3f} ms  {out_runs[key]['tflops']:6.2f} TF")
+    for nb in (2048, 4096):
+        base = out_runs[f"nb{nb}_L0"]["ms"]
+        for lev in (1, 2, 3):
+            out_runs[f"nb{nb}_L{lev}"]["speedup_vs_classical_updates"] = round(base / out_runs[f"nb{nb}_L{lev}"]["ms"], 4)
+    # the rank-nb updates of the blocked loop on their own: C (r x r) -= A (r x nb) B (nb x r)
+    # for r = n - nb, n - 2 nb, ..., timed one by one (event pairs) and summed
+    updates = {}
+    for nb in (2048, 4096):
+        shapes = [n - j - nb for j in range(0, n - nb, nb)]
+        for lev in (0, 1, 2, 3):
+            tot = []
+            for _ in range(args.reps):
+                t = 0.0
+                for r in shapes:
+                    Au, Bu, Cu = A[:r, :nb], A0[:nb, :r], A[r - r:r, n - r:]
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    sx.dgemm(Au, Bu, Cu, -1.0, 1.0, lev, "abc", stream)
+                    e1.record(stream)
+                    e1.synchronize()
+                    t += e0.elapsed_time(e1)
+                tot.append(t)
+            ms = float(np.median(tot))
+            uflops = sum(2.0 * r * r * nb for r in shapes)
+            updates[f"nb{nb}_L{lev}"] = {"ms": round(ms, 3),
+                                         "tflops": round(uflops / (ms * 1e-3) * 1e-12, 2)}
+            log(f"  rank-{nb} updates L={lev}: {ms:8.3f} ms")
+        for lev in (1, 2, 3):
+            updates[f"nb{nb}_L{lev}"]["speedup_vs_classical"] = round(
+                updates[f"nb{nb}_L0"]["ms"] / updates[f"nb{nb}_L{lev}"]["ms"], 4)
+    best = min(out_runs, key=lambda key: out_runs[key]["ms"])
+    # backward error of the best run on sampled columns
+    nb, lev = runs[best]
+    cols = np.sort(np.random.default_rng(0).choice(n, size=4, replace=False))
+    idx = torch.as_tensor(cols, device="cuda")
+    A.copy_(A0)
+    sx.getrf_nopiv(A, nb, lev, stream)
+    torch.cuda.synchronize()
+    F = sx.to_host(A)
+    L = np.tril(F, -1) + np.eye(n)
+    err = float(rel_fro(L @ np.triu(F)[:, cols], A0[:, idx].cpu().numpy()))
+    del F, L
+    out = {"metric": "LU factorization rate (2/3 n^3 / t) with Strassen rank-k updates",
+           "value": out_runs[best]["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"strassen_dgetrf_nopiv n={n}, diagonally dominant "
+                                  f"(uniform[-1,1] + n I), best {best}", "n": n},
+           "runs": out_runs,
+           "rank_nb_updates": updates,
+           "parity": {"backward_error": err, "tolerance": n * 2.0 ** -53, "run": best,
+                      "columns": [int(c) for c in cols], "pass": err <= n * 2.0 ** -53}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -579,6 +675,9 @@ def main():
         return
     if args.suite == "levels":
         levels_suite(args)
+        return
+    if args.suite == "lu":
+        lu_suite(args)
         return
     if args.copy_calibration:
         copy_calibration()

@@ -153,6 +153,25 @@ int strassen_dgemm_winograd(int64_t m, int64_t n, int64_t k, double alpha,
 int strassen_workspace_size_winograd(int64_t m, int64_t n, int64_t k, int levels, size_t *bytes);
 
 /*
+ * strassen_dgetrf_nopiv — LU factorization without pivoting, A = L U in place (L unit lower
+ * triangular, stored below the diagonal; U upper triangular, on and above it), with Strassen in
+ * its rank-k updates: the blocked algorithms under LAPACK cast their work as rank-k updates,
+ * and the paper's future work (Sec. 6) asks how ABC Strassen can accelerate them.  Right-looking
+ * blocked LU with block width nb (a positive multiple of 64; nb >= n makes it fully
+ * recursive): per block column the panel is factored (recursively, halving its width down to
+ * 64 columns), the block row to its right is solved against the panel's unit lower triangle
+ * (recursively), and the trailing matrix gets the rank-nb update A22 := A22 - L21 U12 through
+ * strassen_dgemm.  Every update with min(m, n) >= 2048 and k >= 1024 runs with `levels` levels
+ * (0..3; -1: strassen_select chooses per update), smaller ones classical.  A is an n x n
+ * column-major device matrix (lda >= max(1, n)).  No pivoting: every leading principal minor
+ * must be nonzero (e.g. a diagonally dominant matrix); a zero pivot is not detected and yields
+ * infinities or NaNs.  Uses the workspace of the products it calls.  Asynchronous on `stream`.
+ * Returns 0 or -i (n=1 A=2 lda=3 nb=4 levels=5), or a positive error of a product.
+ */
+int strassen_dgetrf_nopiv(int64_t n, double *A, int64_t lda, int64_t nb, int levels,
+                          void *stream);
+
+/*
  * strassen_gemm — the full dgemm interface of Sec. 2.2 with transposes:
  *   C := alpha * op(A) * op(B) + beta * C,   op(X) = X (trans 'N'/'n') or X^T ('T'/'t'/'C'/'c')
  * op(A) is m x k (A is m x k with lda >= max(1,m), or k x m with lda >= max(1,k) when

@@ -48,6 +48,8 @@ def lib():
         L.strassen_workspace_size_winograd.argtypes = [i64, i64, i64, ci,
                                                        ctypes.POINTER(ctypes.c_size_t)]
         L.strassen_workspace_size_winograd.restype = ci
+        L.strassen_dgetrf_nopiv.argtypes = [i64, vp, i64, i64, ci, vp]
+        L.strassen_dgetrf_nopiv.restype = ci
         L.strassen_dgemm_noalloc.argtypes = gemm + [vp]
         L.strassen_dgemm_noalloc.restype = ci
         L.strassen_gemm_ex.argtypes = gemm + [ci, ci, ci, vp]
@@ -244,6 +246,17 @@ def workspace_size_winograd(m, n, k, levels):
     out = ctypes.c_size_t(0)
     check(lib().strassen_workspace_size_winograd(m, n, k, levels, ctypes.byref(out)))
     return out.value
+
+
+def getrf_nopiv(A, nb=1024, levels=1, stream=None):
+    """LU factorization without pivoting of the square column-major device matrix A in place
+    (unit lower L below the diagonal, U on and above), rank-nb updates with `levels` levels of
+    Strassen (-1: the library chooses per update)."""
+    pa, n, n2, lda = _mat(A, "A")
+    if n2 != n:
+        raise ValueError("square matrix expected")
+    check(lib().strassen_dgetrf_nopiv(n, pa, lda, int(nb), int(levels), _stream(stream)))
+    return A
 
 
 def dgemm_noalloc(A, B, C, alpha=1.0, beta=1.0, levels=1, variant="abc", stream=None):

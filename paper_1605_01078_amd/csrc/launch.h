@@ -58,6 +58,13 @@ hipError_t launch_outer_sums(const OuterSumArgs& a, int side, hipStream_t s);   
 hipError_t launch_chain_sums(const ChainSumArgs& a, int side, hipStream_t s);   // Winograd's
 hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 hipError_t launch_transpose(const TransposeArgs& a, hipStream_t s);
+// LU base cases (kernels_lu.hip), w / k <= 64: in-place LU of a w x w block (one workgroup);
+// B := B U^{-1} (upper, one thread per row); B := L^{-1} B (unit lower, one thread per column).
+hipError_t launch_lu_base(double* P, int64_t ld, int w, hipStream_t s);
+hipError_t launch_trsm_rows_upper(const double* U, int64_t ldu, int w, double* B, int64_t ldb,
+                                  int64_t rows, hipStream_t s);
+hipError_t launch_trsm_cols_lower_unit(const double* L, int64_t ldl, int k, double* B,
+                                       int64_t ldb, int64_t cols, hipStream_t s);
 hipError_t launch_pad_copy(const PadArgs& a, hipStream_t s);
 // Matrix-core rate probe (probe_rates.hip): kind 0 FP64, 1 BF16; `out` holds grid * 256 doubles.
 int probe_grid(int cus);

@@ -307,3 +307,15 @@ def test_winograd_entry_point_checks_and_workspace():
     m, n, k = 1001, 998, 777
     mp, kp = 2 * 2 * _cdiv(_cdiv(m, 2), 2), 2 * 2 * _cdiv(_cdiv(k, 2), 2)
     assert sx.workspace_size_winograd(m, n, k, 1) == 8 * (r32(mp * kp) + r32(kp * n) + r32(mp * n))
+
+
+def test_getrf_argument_codes():
+    L = sx.lib()
+    fake = 1 << 20
+    assert L.strassen_dgetrf_nopiv(-1, fake, 4, 64, 0, None) == -1
+    assert L.strassen_dgetrf_nopiv(4, None, 4, 64, 0, None) == -2
+    assert L.strassen_dgetrf_nopiv(4, fake, 3, 64, 0, None) == -3
+    assert L.strassen_dgetrf_nopiv(4, fake, 4, 100, 0, None) == -4
+    assert L.strassen_dgetrf_nopiv(4, fake, 4, 0, 0, None) == -4
+    assert L.strassen_dgetrf_nopiv(4, fake, 4, 64, 4, None) == -5
+    assert L.strassen_dgetrf_nopiv(0, None, 1, 64, 0, None) == 0

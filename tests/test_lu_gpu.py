@@ -1,0 +1,81 @@
+"""LU factorization without pivoting with Strassen in its rank-k updates (strassen_dgetrf_nopiv).
+
+  * A = L0 U0 with small-integer unit-lower L0 and upper U0: the factors are unique and every
+    intermediate of every update (Strassen's included: operand sums of entries |x| <= 4) is an
+    exact integer, so the GPU must return L0 and U0 bit for bit, at every Strassen level;
+  * diagonally dominant reals: the GPU factors agree with the oracle's plain elimination to a
+    relative Frobenius distance of 1e-13, and the backward error ||A - L U|| / ||A|| is of the
+    order of n u;
+  * ragged sizes and block widths; 16384 with Strassen updates on sampled columns of L U.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle_lu_nopiv, rel_fro
+
+torch = pytest.importorskip("torch")
+sx = pytest.importorskip("paper_1605_01078_amd")
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def integer_factors(seed, n):
+    g = np.random.default_rng(seed)
+    L0 = np.tril(g.integers(-2, 3, size=(n, n)).astype(np.float64), -1) + np.eye(n)
+    U0 = np.triu(g.integers(-2, 3, size=(n, n)).astype(np.float64), 1)
+    U0 += np.diag(g.choice([1.0, 2.0, 4.0, -1.0, -2.0], size=n))
+    return L0, U0
+
+
+def factor(A, nb, levels, ld=None):
+    dA = sx.to_device(A, ld=ld)
+    sx.getrf_nopiv(dA, nb, levels)
+    torch.cuda.synchronize()
+    return sx.to_host(dA)
+
+
+@pytest.mark.parametrize("n,nb,levels", [(300, 64, 0), (1000, 128, 0), (1000, 1024, 0),
+                                         (4096, 1024, 1), (4096, 1024, 2), (4096, 4096, 2),
+                                         (3072, 2048, 3)])
+def test_integer_factors_exact(n, nb, levels):
+    print(f"case lu integer n={n} nb={nb} L={levels}", flush=True)
+    L0, U0 = integer_factors(n + levels, n)
+    A = np.asfortranarray(L0 @ U0)
+    F = factor(A, nb, levels)
+    assert np.array_equal(np.tril(F, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(F), U0)
+
+
+@pytest.mark.parametrize("n,nb,levels,ld", [(2048, 512, 0, None), (2048, 2048, 1, None),
+                                            (3001, 1024, 2, 3010), (777, 64, 0, 780)])
+def test_diagonally_dominant_against_oracle(n, nb, levels, ld):
+    print(f"case lu reals n={n} nb={nb} L={levels}", flush=True)
+    g = np.random.default_rng(n)
+    A0 = np.asfortranarray(g.uniform(-1, 1, size=(n, n)) + n * np.eye(n))
+    F = factor(A0, nb, levels, ld)
+    R = A0.copy(order="F")
+    assert oracle_lu_nopiv(R) == 0
+    assert rel_fro(np.tril(F, -1), np.tril(R, -1)) <= 1e-13
+    assert rel_fro(np.triu(F), np.triu(R)) <= 1e-13
+    L, Uf = np.tril(F, -1) + np.eye(n), np.triu(F)
+    assert rel_fro(L @ Uf, A0) <= n * U
+
+
+def test_full_size_16384_backward_error_on_sampled_columns():
+    n, nb = 16384, 4096
+    print(f"case lu full size n={n} nb={nb}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(151)
+    A = torch.empty((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=g)
+    A.diagonal().add_(float(n))
+    A = A.t()   # column-major view
+    cols = np.sort(np.random.default_rng(5).choice(n, size=4, replace=False))
+    idx = torch.as_tensor(cols, device="cuda")
+    A0c = A[:, idx].cpu().numpy()
+    sx.getrf_nopiv(A, nb, 2)
+    torch.cuda.synchronize()
+    F = sx.to_host(A)
+    L = np.tril(F, -1) + np.eye(n)
+    Uc = np.triu(F)[:, cols]
+    assert rel_fro(L @ Uc, A0c) <= n * U
