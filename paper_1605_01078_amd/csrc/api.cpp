@@ -545,7 +545,24 @@ static int run_classical(int64_t m, int64_t n, int64_t k, double alpha, const do
   return 0;
 }
 
-// Block padding (the zero padding of Sec. 3.3 made physical).  Where the all-products layout
+// Naive on the classical kernel: every product is a plain GEMM of its two operands (a
+// temporary of the padded sub-block extent, or one quadrant of A or B); where the partition is
+// exact (m, n, k multiples of 2^L, so every quadrant is a full sub-block), the quadrants keep
+// the classical kernel's layout (even sub-block extents, aligned operands, even leading
+// dimensions) and each product fills the CUs, the products run there.
+static inline int64_t code_row_h(uint8_t c) { return c & 7; }
+static inline int64_t code_col_h(uint8_t c) { return (c >> 3) & 7; }
+
+static bool naive_on_classical(const Plan& p, int64_t m, int64_t n, int64_t k, const double* A,
+                               int64_t lda, const double* B, int64_t ldb, int forced) {
+  if (p.variant != STRASSEN_NAIVE || forced != -1) return false;
+  if (m % p.q != 0 || n % p.q != 0 || k % p.q != 0) return false;
+  if (!classical_size(p.mq, p.nq)) return false;
+  return classical_layout(p.mq, p.kq, A, lda, B, ldb, nullptr, p.ldm) &&
+         8 * 64 * (p.ldm + 1) < (int64_t(1) << 31);
+}
+
+// Block padding (the zero padding of Sec. 3.3 made physical).// Block padding (the zero padding of Sec. 3.3 made physical).  Where the all-products layout
 // does not apply to the operands as given (m or k not a multiple of 2^(L+1), operands not
 // 16-byte aligned, odd leading dimensions) or two-level staging needs n % 4 == 0, ABC runs on
 // copies in which every row (column) block of the 2^L x 2^L partition is stored with an even
@@ -1433,6 +1450,21 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
                                   abp.stage ? wsd + abl.s_off : nullptr, stream, g.M, p.ldm,
                                   p.m_stride))
       return rc;
+  } else if (naive_on_classical(p, m, n, k, A, lda, B, ldb, forced)) {
+    // Naive's products are plain GEMMs on its temporaries (or single quadrants): each runs on the
+    // classical kernel with beta = 0, writing M_r (the same MFMA order as the tile kernel: the
+    // same bits)
+    for (int r = 0; r < p.td->nprod; ++r) {
+      const ProdDesc& d = p.td->prod[r];
+      const double* Ar = (d.flags & 1) ? g.TA + (int64_t)d.tslot_a * p.ta_stride
+                                       : A + code_row_h(d.a[0]) * p.mq + code_col_h(d.a[0]) * p.kq * lda;
+      const double* Br = (d.flags & 2) ? g.TB + (int64_t)d.tslot_b * p.tb_stride
+                                       : B + code_row_h(d.b[0]) * p.kq + code_col_h(d.b[0]) * p.nq * ldb;
+      if (int rc = run_classical(p.mq, p.nq, p.kq, 1.0, Ar, (d.flags & 1) ? p.mq : lda, Br,
+                                 (d.flags & 2) ? p.kq : ldb, 0.0, g.M + (int64_t)r * p.m_stride,
+                                 p.ldm, stream))
+        return rc;
+    }
   } else {
     const int cfg = pick_cfg(p, p.td->nprod, maxt);
     g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));

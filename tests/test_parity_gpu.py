@@ -516,3 +516,27 @@ def test_classical_kernel_bitwise_with_tile_kernel(shape, offset, kind):
     else:
         assert (np.abs(got - oracle_dgemm(A, B, C.copy(order="F"), 1.5, -0.5))
                 <= classical_bound(A, B, C, 1.5, -0.5)).all()
+
+
+@pytest.mark.parametrize("levels,n", [(1, 8192), (2, 16384)])
+def test_naive_on_classical_kernel_bitwise(levels, n):
+    """Naive's products run on the classical kernel where the partition is exact and the products
+    fill the CUs (timing hook: 7^L classical launches); the result stays bitwise that of ABC."""
+    print(f"case naive on classical L={levels} n={n}", flush=True)
+    A, B, C0 = (W.device_uniform(s, n, n) for s in (161, 162, 163))
+    outs = {}
+    sx.timing_enable(True)
+    try:
+        for k_ in sx.KERNEL_KINDS:
+            sx.timing_collect(k_)
+        for variant in ("naive", "abc"):
+            C = C0.clone()
+            sx.dgemm(A, B, C, 1.0, -1.0, levels, variant)
+            torch.cuda.synchronize()
+            outs[variant] = C
+            if variant == "naive":
+                assert sx.timing_collect("classical")[1] == 7 ** levels
+                assert sx.timing_collect("tile")[1] == 0
+    finally:
+        sx.timing_enable(False)
+    assert torch.equal(outs["naive"], outs["abc"])
