@@ -160,6 +160,20 @@ def traffic_summary(args):
     log(json.dumps(out, indent=1))
 
 
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo) and its logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs, {len(os.sched_getaffinity(0))} available)"
+
+
 def timed(fn, reps, stream):
     """Median milliseconds of `reps` calls, each bracketed by events on `stream`."""
     import torch
@@ -909,6 +923,7 @@ def main():
         tc = run_cols(ncols)
         cpu_tflops = 2.0 * n * n * ncols / tc * 1e-12
         cpu = {"value": round(cpu_tflops, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"plain triple-loop oracle (FP64, sequential sum over k) on A {n}x{n} times "
                          f"the first {ncols} columns of B ({2.0 * n * n * ncols:.3e} flops, "
                          f"{tc:.1f} s); rate scaled to TFLOP/s"}
