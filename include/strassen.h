@@ -361,14 +361,19 @@ int strassen_batched_destroy(void *plan);
  *   (the GPU counterpart of the paper's Fig. "tab:breakdown": MFMA time at this library's
  *   rates and efficiencies, launch latency, and HBM time of the extra passes); +inf for
  *   members not offered for dtype.  Host only.
- * strassen_selector_load(params): host array of 4935 floats (the network below) copied into
+ * strassen_selector_load(params): host array of 5383 floats (the network below) copied into
  *   the library; NULL unloads it (back to the model).  -1 if a value is not finite.
+ * strassen_selector_features(m, n, k, dtype, x[11]): the network's input for a shape (host
+ *   only): x[0..2] = (ln s - ln 256) / (ln 20000 - ln 256) for s = m, n, k; x[3] = dtype;
+ *   x[4 + c] = min(ln(t_c / t_best), 1) with t_c = strassen_cost_model's time of member c and
+ *   t_best the smallest of them (1 for members not offered for dtype).  The network scores the
+ *   members from the shape and from where the model ranks them, so it learns where measured
+ *   times depart from the model.  Returns 0 or -i.
  *
- * The network: x = ((ln s - ln 256) / (ln 20000 - ln 256) for s = m, n, k; dtype), then
- * h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), scores = W3 h2 + b3 with W1 64x4, W2 64x64,
- * W3 7x64 (row-major), FP32; parameters flat in the order W1, b1, W2, b2, W3, b3.  Training
- * entry points (device pointers, enqueued on `stream`):
- * strassen_mlp_forward(params, X, n, logits, stream): X n x 4, logits n x 7 (row-major).
+ * The network: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), scores = W3 h2 + b3 with W1 64x11,
+ * W2 64x64, W3 7x64 (row-major), FP32; parameters flat in the order W1, b1, W2, b2, W3, b3.
+ * Training entry points (device pointers, enqueued on `stream`):
+ * strassen_mlp_forward(params, X, n, logits, stream): X n x 11, logits n x 7 (row-major).
  * strassen_mlp_work_size(n, bytes): workspace bytes strassen_mlp_loss_grad needs for n samples.
  * strassen_mlp_loss_grad(params, X, labels, n, work, grad, loss, stream): mean softmax
  *   cross-entropy over the n samples into *loss and its gradient (flat, as params) into grad;
@@ -379,6 +384,7 @@ int strassen_batched_destroy(void *plan);
 int strassen_select(int64_t m, int64_t n, int64_t k, int dtype, int *levels, int *variant);
 int strassen_cost_model(int64_t m, int64_t n, int64_t k, int dtype, double *seconds);
 int strassen_selector_load(const float *params);
+int strassen_selector_features(int64_t m, int64_t n, int64_t k, int dtype, float *x);
 int strassen_mlp_forward(const float *params, const float *X, int n, float *logits, void *stream);
 int strassen_mlp_work_size(int n, size_t *bytes);
 int strassen_mlp_loss_grad(const float *params, const float *X, const int *labels, int n,

@@ -5,30 +5,41 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 The network maps a GEMM shape to scores over the seven members of the family the selector picks
 from (classical; one-level ABC, AB, Naive; two-level ABC, AB, Naive):
 
-    x  = (f(m), f(n), f(k), d)      f(s) = (ln s - ln 256) / (ln 20000 - ln 256),  d = 0 FP64, 1 BF16
-    h1 = relu(W1 x + b1)            W1: 64 x 4
+    x  = (f(m), f(n), f(k), d, r_0 .. r_6)
+                                    f(s) = (ln s - ln 256) / (ln 20000 - ln 256),  d = 0 FP64, 1 BF16,
+                                    r_c = min(ln(t_c / min_j t_j), 1) for the seven members' times
+                                    t_c under a time model supplied by the caller (1 where t_c
+                                    is infinite: a member not offered)
+    h1 = relu(W1 x + b1)            W1: 64 x 11
     h2 = relu(W2 h1 + b2)           W2: 64 x 64
     z  = W3 h2 + b3                 W3: 7 x 64
     loss = mean over the batch of  -log softmax(z)[label]
 
-Parameters are one flat vector in the order W1 (row-major), b1, W2, b2, W3, b3 (4935 values);
+Parameters are one flat vector in the order W1 (row-major), b1, W2, b2, W3, b3 (5383 values);
 the library's kernels take the same layout.  Training uses Adam (Kingma and Ba, 2015):
     m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
     p <- p - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 """
 import numpy as np
 
-D_IN, H, D_OUT = 4, 64, 7
+D_IN, H, D_OUT = 11, 64, 7
 SHAPES = [(H, D_IN), (H,), (H, H), (H,), (D_OUT, H), (D_OUT,)]
-N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)   # 4935
+N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)   # 5383
 LOG_LO, LOG_HI = np.log(256.0), np.log(20000.0)
 
 
-def features(m, n, k, dtype_flag):
-    """Network input for shapes (arrays or scalars); dtype_flag 0 = FP64, 1 = BF16."""
+def features(m, n, k, dtype_flag, model_times):
+    """Network input for shapes (arrays or scalars); dtype_flag 0 = FP64, 1 = BF16;
+    model_times: the seven members' times under the caller's time model (N x 7, +inf for a
+    member not offered)."""
     f = lambda s: (np.log(np.asarray(s, dtype=np.float64)) - LOG_LO) / (LOG_HI - LOG_LO)
     m, n, k, d = np.broadcast_arrays(f(m), f(n), f(k), np.asarray(dtype_flag, dtype=np.float64))
-    return np.stack([m, n, k, d], axis=-1)
+    size = np.stack([m, n, k, d], axis=-1).reshape(-1, 4)
+    t = np.asarray(model_times, dtype=np.float64).reshape(-1, D_OUT)
+    best = t.min(axis=1, keepdims=True)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        r = np.where(np.isfinite(t), np.minimum(np.log(t / best), 1.0), 1.0)
+    return np.concatenate([size, r], axis=1)
 
 
 def unpack(p):
@@ -56,7 +67,7 @@ def init(seed=0):
 
 
 def forward(p, X):
-    """(logits, cache) for a batch X (N x 4)."""
+    """(logits, cache) for a batch X (N x 11)."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
     X = np.asarray(X, dtype=np.float64)
     a1 = X @ W1.T + b1

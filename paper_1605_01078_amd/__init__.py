@@ -36,6 +36,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1605_01078_amd.build`")
+        # torch first: it loads its own HIP runtime under the same soname as the one the library
+        # links, and a process must use one runtime (the library then binds to torch's; loaded
+        # the other way round, torch's device calls can find no device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         i64, dbl, vp, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
         gemm = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, ci, ci]
@@ -100,6 +104,8 @@ def _optional(L):
         "strassen_cost_model": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ci,
                                  ctypes.POINTER(ctypes.c_double)], ci),
         "strassen_selector_load": ([vp], ci),
+        "strassen_selector_features": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ci,
+                                        ctypes.POINTER(ctypes.c_float)], ci),
         "strassen_mlp_forward": ([vp, vp, ci, vp, vp], ci),
         "strassen_mlp_work_size": ([ci, ctypes.POINTER(ctypes.c_size_t)], ci),
         "strassen_mlp_loss_grad": ([vp, vp, vp, ci, vp, vp, vp, vp], ci),

@@ -1,6 +1,6 @@
-// The selector's network (4 -> 64 -> 64 -> 7, ReLU) in FP32: forward, backward and Adam.
+// The selector's network (11 -> 64 -> 64 -> 7, ReLU) in FP32: forward, backward and Adam.
 //
-// Parameters are one flat vector: W1 (64 x 4, row-major), b1, W2 (64 x 64), b2, W3 (7 x 64),
+// Parameters are one flat vector: W1 (64 x 11, row-major), b1, W2 (64 x 64), b2, W3 (7 x 64),
 // b3.  Forward: one thread per sample, parameters staged in LDS.  Backward: one thread per
 // sample for the per-sample error signals, then one thread per parameter summing its gradient
 // over the samples in order (deterministic; no atomics).  Loss: mean softmax cross-entropy.
@@ -12,7 +12,7 @@ namespace smx {
 
 namespace {
 
-constexpr int kIn = 4, kH = 64, kOut = 7;
+constexpr int kIn = kMlpIn, kH = 64, kOut = 7;
 constexpr int kW1 = 0, kB1 = kW1 + kH * kIn, kW2 = kB1 + kH, kB2 = kW2 + kH * kH,
               kW3 = kB2 + kH, kB3 = kW3 + kOut * kH;
 static_assert(kB3 + kOut == kMlpParams, "layout");

@@ -45,7 +45,9 @@ hipError_t launch_batched(const BatchProblem* probs, const BatchItem* items, int
 const void* batched_kernel_fn(bool vec);   // kernel symbols, for graph nodes
 const void* clear_counter_fn();
 // Selector network (kernels_mlp.hip): flat FP32 parameters W1, b1, W2, b2, W3, b3.
-constexpr int kMlpParams = 64 * 4 + 64 + 64 * 64 + 64 + 7 * 64 + 7;
+// Inputs: the shape's four size features and the analytical model's seven time ratios.
+constexpr int kMlpIn = 11;
+constexpr int kMlpParams = 64 * kMlpIn + 64 + 64 * 64 + 64 + 7 * 64 + 7;
 hipError_t launch_mlp_forward(const float* params, const float* X, int n, float* logits,
                               float* A1, float* A2, hipStream_t s);
 hipError_t launch_mlp_backward(const float* params, const float* X, const int* y, int n,

@@ -8,7 +8,7 @@ dtype 0 is FP64 (strassen_dgemm); dtype 1 is BF16 products (strassen_gemm_ex wit
 products, FP64 sums and update), where only the ABC members exist (the others time as +inf).
 
 Data flow:  collect(shapes, dtypes) -> times (N x 7, ms)  ->  labels = argmin
-            train(X, y) -> parameters (4935 floats)      ->  save / strassen_selector_load
+            train(X, y) -> parameters (5383 floats)      ->  save / strassen_selector_load
             evaluate(params, X, times) -> regret of the network, of the analytical model and
             of every fixed member.
 """
@@ -22,18 +22,25 @@ import numpy as np
 from . import check, dgemm, gemm_ex, lib, set_workspace, workspace_size, workspace_size_ex
 
 MEMBERS = [(0, "abc"), (1, "abc"), (1, "ab"), (1, "naive"), (2, "abc"), (2, "ab"), (2, "naive")]
-N_PARAMS = 4935
+D_IN = 11
+N_PARAMS = 64 * D_IN + 64 + 64 * 64 + 64 + 7 * 64 + 7   # 5383
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data")
 WEIGHTS = os.path.join(DATA_DIR, "weights.json")
 TIMINGS = os.path.join(DATA_DIR, "timings.npz")
-LOG_LO, LOG_HI = math.log(256.0), math.log(20000.0)
 
 
 def features(m, n, k, dtype):
-    """Network inputs (N x 4 float32) for arrays of sizes and dtype flags."""
-    f = lambda s: (np.log(np.asarray(s, dtype=np.float64)) - LOG_LO) / (LOG_HI - LOG_LO)
-    m, n, k, d = np.broadcast_arrays(f(m), f(n), f(k), np.asarray(dtype, dtype=np.float64))
-    return np.stack([m, n, k, d], axis=-1).astype(np.float32)
+    """Network inputs (N x 11 float32) for arrays of sizes and dtype flags, from the library's
+    strassen_selector_features: the sizes on a log scale, the dtype flag, and the analytical
+    model's time ratios min(ln(t_c / t_best), 1) of the seven members."""
+    import ctypes
+    m, n, k, d = (np.atleast_1d(np.asarray(a)) for a in np.broadcast_arrays(m, n, k, dtype))
+    out = np.empty((len(m), D_IN), dtype=np.float32)
+    x = (ctypes.c_float * D_IN)()
+    for i in range(len(m)):
+        check(lib().strassen_selector_features(int(m[i]), int(n[i]), int(k[i]), int(d[i]), x))
+        out[i] = x[:]
+    return out
 
 
 def available(dtype):
@@ -113,7 +120,7 @@ def init_params(seed=0):
     """He-uniform weights, zero biases (float32, flat)."""
     g = np.random.default_rng(seed)
     parts = []
-    for shape in [(64, 4), (64,), (64, 64), (64,), (7, 64), (7,)]:
+    for shape in [(64, D_IN), (64,), (64, 64), (64,), (7, 64), (7,)]:
         if len(shape) == 2:
             lim = math.sqrt(6.0 / shape[1])
             parts.append(g.uniform(-lim, lim, size=shape).ravel())
@@ -341,7 +348,7 @@ def main(argv=None):
     times = np.full((len(shapes), 7), np.nan)
     for path in a.inputs:
         z = np.load(path)
-        times[z["index"]] = z["times"]
+        times[z["index"] if "index" in z else np.arange(len(shapes))] = z["times"]
     if np.isnan(times).any():
         raise SystemExit("missing timings for some shapes")
     np.savez_compressed(a.merged, times=times.astype(np.float32))

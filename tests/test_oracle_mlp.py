@@ -9,15 +9,19 @@ from oracle import mlp
 def _batch(seed, n=37):
     g = np.random.default_rng(seed)
     m, nn, k = (np.exp(g.uniform(np.log(256), np.log(20000), n)) for _ in range(3))
-    X = mlp.features(m, nn, k, g.integers(0, 2, n))
+    X = mlp.features(m, nn, k, g.integers(0, 2, n), np.exp(g.uniform(0, 1.5, (n, 7))))
     y = g.integers(0, mlp.D_OUT, n)
     return X, y
 
 
 def test_parameter_count_and_features():
-    assert mlp.N_PARAMS == 64 * 4 + 64 + 64 * 64 + 64 + 7 * 64 + 7 == 4935
-    x = mlp.features(256, 20000, np.sqrt(256 * 20000), 1)
-    assert np.allclose(x, [0.0, 1.0, 0.5, 1.0])
+    assert mlp.N_PARAMS == 64 * 11 + 64 + 64 * 64 + 64 + 7 * 64 + 7 == 5383
+    # sizes at the ends and the geometric middle of the range; the model's best member gets 0,
+    # a member e times slower 1, a slower one or one not offered is clipped at 1
+    e = np.e
+    t = [2.0, 2.0 * np.sqrt(e), 2.0 * e, 2.0 * e * e, np.inf, 2.0 * e ** 0.25, 2.0]
+    x = mlp.features(256, 20000, np.sqrt(256 * 20000), 1, t)
+    assert np.allclose(x, [[0.0, 1.0, 0.5, 1.0, 0.0, 0.5, 1.0, 1.0, 1.0, 0.25, 0.0]], rtol=0, atol=1e-12)
 
 
 def test_gradient_matches_finite_differences():

@@ -46,7 +46,7 @@ def test_select_argument_errors():
     assert L.strassen_select(-1, 1, 1, 0, ctypes.byref(a), ctypes.byref(b)) == -1
     assert L.strassen_select(1, 1, 1, 2, ctypes.byref(a), ctypes.byref(b)) == -4
     assert L.strassen_select(1, 1, 1, 0, None, ctypes.byref(b)) == -5
-    bad = np.full(4935, np.nan, dtype=np.float32)
+    bad = np.full(mlp.N_PARAMS, np.nan, dtype=np.float32)
     assert L.strassen_selector_load(bad.ctypes.data) == -1
     assert L.strassen_selector_load(None) == 0
     sz = ctypes.c_size_t()
@@ -54,11 +54,23 @@ def test_select_argument_errors():
 
 
 def test_features_match_oracle_definition():
-    from oracle import mlp
+    """The library's network input (strassen_selector_features) against the oracle's definition
+    of it, fed the library's analytical model times."""
     g = np.random.default_rng(0)
     m, n, k = (g.integers(256, 20001, 50) for _ in range(3))
     d = g.integers(0, 2, 50)
-    assert np.allclose(S.features(m, n, k, d), mlp.features(m, n, k, d), rtol=0, atol=1e-6)
+    t = np.array([_model(int(a), int(b), int(c), int(e)) for a, b, c, e in zip(m, n, k, d)])
+    got = S.features(m, n, k, d)
+    assert got.shape == (50, mlp.D_IN)
+    assert np.allclose(got, mlp.features(m, n, k, d, t), rtol=0, atol=1e-6)
+    # the model's pick scores 0; BF16 rows mark AB and Naive as not offered
+    assert (got[:, 4:].min(axis=1) == 0).all()
+    assert (got[d == 1][:, [6, 7, 9, 10]] == 1).all()
+    L = sx.lib()
+    x = (ctypes.c_float * 11)()
+    assert L.strassen_selector_features(-1, 1, 1, 0, x) == -1
+    assert L.strassen_selector_features(1, 1, 1, 2, x) == -4
+    assert L.strassen_selector_features(1, 1, 1, 0, None) == -5
 
 
 def test_committed_network_file():
@@ -76,7 +88,7 @@ def test_committed_network_file():
     assert times.shape == (22000, 7)
     # the held-out regret recorded with the weights is the oracle network's on the stored timings
     shapes, dtypes = S.dataset()
-    X = mlp.features(*np.array(shapes[20000:]).T, dtypes[20000:])
+    X = S.features(*np.array(shapes[20000:]).T, dtypes[20000:])
     z, _ = mlp.forward(p.astype(np.float64), X.astype(np.float32).astype(np.float64))
     ch = S.choose(z, dtypes[20000:])
     r = mlp.regret(times[20000:].astype(np.float64), ch)

@@ -19,7 +19,7 @@ def _data(seed, n):
     g = np.random.default_rng(seed)
     m, nn, k = (np.exp(g.uniform(np.log(256), np.log(20000), n)) for _ in range(3))
     d = g.integers(0, 2, n)
-    return mlp.features(m, nn, k, d), g.integers(0, 7, n)
+    return mlp.features(m, nn, k, d, np.exp(g.uniform(0, 1.5, (n, 7)))), g.integers(0, 7, n)
 
 
 def test_forward_matches_oracle():
@@ -74,6 +74,26 @@ def test_installed_network_drives_select():
     try:
         assert S.select(4096, 4096, 4096, 0) == (1, "ab")
         assert S.select(4096, 4096, 4096, 1) == (2, "abc")   # BF16: ABC members only
+    finally:
+        S.uninstall()
+
+
+def test_installed_network_sees_model_features():
+    """A hand-set network scoring member c as -x[4 + c] (minus the model's time ratio) picks
+    the analytical model's member: the inputs reach the inference kernel in their layout."""
+    W1, b1, W2, b2, W3, b3 = (np.zeros(s) for s in mlp.SHAPES)
+    for c in range(7):
+        W1[c, 4 + c] = 1.0
+        W2[c, c] = 1.0
+        W3[c, c] = -1.0
+    p = np.concatenate([a.ravel() for a in (W1, b1, W2, b2, W3, b3)]).astype(np.float32)
+    shapes = [(256, 256, 256, 0), (16384, 16384, 16384, 0), (16383, 16384, 16383, 0),
+              (3000, 12000, 5000, 0), (8192, 8192, 8192, 1), (20000, 300, 20000, 1)]
+    S.uninstall()
+    want = [S.select(*s) for s in shapes]
+    S.install(p)
+    try:
+        assert [S.select(*s) for s in shapes] == want
     finally:
         S.uninstall()
 
