@@ -320,7 +320,7 @@ def batched_suite(args):
     choices = tuned.choices()
     hist = {}
     for lv, cf in choices:
-        key = f"L{lv}_{['tile128', 'tile64', 'all_products'][cf]}"
+        key = f"L{lv}_{['tile128', 'tile64', 'all_products', 'side_stream'][cf]}"
         hist[key] = hist.get(key, 0) + 1
     log(f"autotune: {tune_s:.1f} s, choices {hist}")
     # timed step: the captured graph

@@ -298,7 +298,11 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
  * tile choice (0: 128 x 128, 1: 64 x 64 in the persistent kernel; 2: the problem runs as its own
  * all-products launch(es), one at one level, seven at two with the outer sums in the load,
  * after the persistent kernel, where that kernel's layout applies (strassen_dgemm's conditions),
- * else in the persistent kernel with the tiles a single call would use).  A work item of the
+ * else in the persistent kernel with the tiles a single call would use; 3: the problem runs as
+ * a single call would (the classical, all-products or tile kernel) but with no workspace, on one
+ * of four side streams forked from the caller's stream before the persistent kernel and joined
+ * back after it, so that problems too small to fill the GPU share it; longest first, each to the
+ * side stream with the least work).  A work item of the
  * persistent kernel is one tile position of one problem, on which one workgroup runs all the
  * problem's products; items are handed out longest first through a device counter.  Per problem
  * the result is bitwise that of strassen_dgemm with the same level (every FP64 kernel rounds the
@@ -306,13 +310,14 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
  *
  * strassen_batched_plan(count, m, n, k, levels, cfg, plan): problem sizes (host arrays of
  *   `count`).  levels / cfg (host, may be NULL = all -1): -1 lets the library choose by its rule
- *   (level from min(m, n, k) thresholds; one-level problems above a size threshold as their own
- *   all-products launch, else 64 x 64 tiles when the 128 x 128 grid of a sub-block is small);
+ *   (level from min(m, n, k) thresholds; problems above one size threshold on the side streams
+ *   at level 0 or 1, one-level problems above another as their own all-products launch, else
+ *   64 x 64 tiles when the 128 x 128 grid of a sub-block is small);
  *   the chosen values are written back.  *plan receives an opaque handle (host memory).
  *   Returns 0, -1 count < 0, -2 NULL or negative sizes, -5 / -6 a level / cfg out of range,
  *   -7 plan NULL.  Needs no device.
- * strassen_batched_autotune(plan, sample, seed, stream): times the batch (persistent kernel and
- *   all-products launches) on `sample` problems of the plan (seeded choice; 0 = all) under
+ * strassen_batched_autotune(plan, sample, seed, stream): times the batch (persistent kernel,
+ *   side streams and all-products launches) on `sample` problems of the plan (seeded choice; 0 = all) under
  *   candidate rule thresholds, on zeroed
  *   library-owned buffers of the same shapes, and re-chooses every -1 entry with the fastest
  *   rule.  Synchronises `stream`.  Returns 0, -1, -2, or a positive error.
@@ -325,7 +330,8 @@ int strassen_workspace_size_ex(int64_t m, int64_t n, int64_t k, int levels, int 
  *   a positive error.
  * strassen_batched_capture(...same arguments...): prepares the work list for these operands
  *   and records the launches (counter clear, persistent kernel, then the all-products launches
- *   in problem order) as a HIP graph in the plan,
+ *   in problem order; with side-stream problems, by stream capture, the side streams as parallel
+ *   branches) as a HIP graph in the plan,
  *   without running it.  alpha == 0 / k == 0 problems are refused (STRASSEN_ERR_UNSUPPORTED).
  * strassen_batched_replay(plan, stream): launches the recorded graph on `stream`; every replay
  *   recomputes C from the operands recorded at capture.  A later run or capture on the plan
@@ -405,8 +411,12 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
  *   5: as 4, with the two-level outer operand sums staged wherever n % 4 == 0 (the workspace,
  *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise).
  * The default (-1) uses the all-products kernel wherever it applies and stages as described
- * at strassen_dgemm.  For strassen_gemm_ex, 0 / 1 force the BF16 product kernel's 128 x 128 /
- * 128 x 64 workgroup tiles (default: 128 x 64 where 128 x 128 tiles would number fewer than 512).
+ * at strassen_dgemm.  For strassen_gemm_ex, 0 / 1 / 2 force the BF16 product kernel's
+ * 128 x 128 / 128 x 64 / 256 x 256 workgroup tiles; 256 x 256 (eight waves of 128 x 64) applies
+ * to BF16 products (not bf16x3) where every tile is whole: sub-blocks of multiples of 256 rows
+ * and columns lying wholly inside C, C 16-byte aligned with even ldc (elsewhere 2 means
+ * 128 x 128).  Default: 256 x 256 where it applies and gives at least 256 tiles, else 128 x 128
+ * where those number at least 512, else 128 x 64.
  * Results do not depend on the configuration (bitwise).  The environment variable
  * STRASSEN_TILE_CFG sets the initial value.  Returns 0 or -1 (cfg out of range).
  */

@@ -395,7 +395,7 @@ class Batched:
 
     shapes: list of (m, n, k); levels / cfg: per-problem lists with -1 = library choice
     (None = all -1); cfg 0 / 1: 128 x 128 / 64 x 64 tiles of the persistent kernel, 2: the
-    problem's own all-products launch(es)."""
+    problem's own all-products launch(es), 3: its own single-call launches on a side stream."""
 
     def __init__(self, shapes, levels=None, cfg=None):
         self.count = len(shapes)

@@ -3,12 +3,19 @@
 //
 // Every problem gets a Strassen level and a tile shape.  Entries given as -1 follow a rule,
 //   level = 2 if min(m, n, k) >= t2, else 1 if min(m, n, k) >= t1, else 0;
-//   tile  = its own all-products launch (one level, min(m, n, k) >= t_ap), else
+//   tile  = its own launches on a side stream (min(m, n, k) >= t_own; level at most 1), else
+//           its own all-products launch (one level, min(m, n, k) >= t_ap), else
 //           64 x 64 if the 128 x 128 grid of one sub-block has fewer than `small` tiles,
 //           else 128 x 128;
-// whose thresholds the autotuner picks by timing the batch itself (persistent kernel and
-// all-products launches) on a sample of its problems: the quantity that matters is the batch's
-// time, not one problem's latency.
+// whose thresholds the autotuner picks by timing the batch itself (persistent kernel, side
+// streams and all-products launches) on a sample of its problems: the quantity that matters is
+// the batch's time, not one problem's latency.
+//
+// Side streams: problems of tile choice kBatchOwn run as ordinary single calls (the classical
+// kernel, the all-products kernel or the tile kernel, as strassen_dgemm would choose them, with
+// no workspace) spread over kBranches streams forked from the caller's stream and joined back
+// into it, concurrently with the persistent kernel: several problems that each fill part of the
+// GPU then share it.  A captured graph keeps the fork and join as parallel branches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,9 +37,22 @@ struct Rule {
   int64_t t2 = std::numeric_limits<int64_t>::max();   // for two levels
   int64_t small = 0;                                  // 128-tile count below which tiles are 64
   int64_t t_ap = std::numeric_limits<int64_t>::max(); // min dimension for an all-products launch
+  int64_t t_own = std::numeric_limits<int64_t>::max(); // min dimension for side-stream launches
 };
 
 constexpr int kBatchAllProducts = 2;   // problem tile choice: its own all-products launch(es)
+constexpr int kBatchOwn = 3;           // its own single-call launches on a side stream
+constexpr int kBranches = 4;           // side streams (the GPU's hardware queues per process)
+
+// A problem run on a side stream.
+struct OwnLaunch {
+  int64_t m, n, k, lda, ldb, ldc;
+  const double* A;
+  const double* B;
+  double* C;
+  int level;
+  double cost;
+};
 
 struct BatchedPlan {
   int count = 0;
@@ -48,6 +68,11 @@ struct BatchedPlan {
   size_t cap_probs = 0, cap_items = 0;
   int n_items = 0;
   std::vector<ApLaunch> ap;   // all-products launches of the problems that have them, in order
+  std::vector<OwnLaunch> own; // side-stream problems, longest first
+  hipStream_t branch[kBranches] = {};
+  hipStream_t cap = nullptr;   // the stream graph capture records on (the caller's may be the null stream)
+  hipEvent_t fork = nullptr, join[kBranches] = {};
+  double alpha = 1.0, beta = 1.0;
   bool vec = true;
   int grid = 0;
   hipGraph_t graph = nullptr;
@@ -59,6 +84,11 @@ static void apply_rule(const Rule& r, int64_t m, int64_t n, int64_t k, int* leve
   const int64_t mn = std::min(m, std::min(n, k));
   if (set_level) *level = mn >= r.t2 ? 2 : (mn >= r.t1 ? 1 : 0);
   if (set_cfg) {
+    if (mn >= r.t_own) {
+      *cfg = kBatchOwn;
+      if (set_level && *level > 1) *level = 1;   // side streams share no workspace: no staging
+      return;
+    }
     const int64_t q = int64_t(1) << *level;
     const int64_t tiles128 = cdiv(cdiv(m, q), 128) * cdiv(cdiv(n, q), 128);
     *cfg = *level == 1 && mn >= r.t_ap ? kBatchAllProducts : (tiles128 < r.small ? 1 : 0);
@@ -74,6 +104,16 @@ static void drop_graph(BatchedPlan* p) {
 
 static void free_device(BatchedPlan* p) {
   drop_graph(p);
+  for (int b = 0; b < kBranches; ++b) {
+    if (p->branch[b]) (void)hipStreamDestroy(p->branch[b]);
+    if (p->join[b]) (void)hipEventDestroy(p->join[b]);
+    p->branch[b] = nullptr;
+    p->join[b] = nullptr;
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  p->fork = nullptr;
+  p->cap = nullptr;
   if (p->d_probs) (void)hipFree(p->d_probs);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);
@@ -89,11 +129,12 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
                       const double* const* B, const int64_t* ldb, double* const* C,
                       const int64_t* ldc, double alpha, double beta,
                       std::vector<BatchProblem>* probs, std::vector<BatchItem>* items,
-                      std::vector<ApLaunch>* ap, bool* vec) {
+                      std::vector<ApLaunch>* ap, std::vector<OwnLaunch>* own, bool* vec) {
   const TableDev* tabs = host_tables();
   probs->clear();
   items->clear();
   ap->clear();
+  own->clear();
   *vec = true;
   std::vector<double> cost;
   for (int i = 0; i < p.count; ++i) {
@@ -102,6 +143,12 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
     const int L = p.level[i];
     const int64_t q = int64_t(1) << L;
     int cfg = p.cfg[i];
+    if (cfg == kBatchOwn) {
+      const double c = (double)tabs[table_id(L, false)].nprod * (double)cdiv(m, q) *
+                       (double)cdiv(n, q) * (double)cdiv(k, q);
+      own->push_back({m, n, k, lda[i], ldb[i], ldc[i], A[i], B[i], C[i], L, c});
+      continue;
+    }
     if (cfg == kBatchAllProducts) {
       if (all_products_ok(m, k, A[i], lda[i], B[i], ldb[i], C[i], ldc[i], L)) {
         std::vector<ApLaunch> mine;
@@ -155,6 +202,8 @@ static int build_work(const BatchedPlan& p, const double* const* A, const int64_
   std::vector<BatchItem> sorted(items->size());
   for (size_t i = 0; i < order.size(); ++i) sorted[i] = (*items)[order[i]];
   items->swap(sorted);
+  std::stable_sort(own->begin(), own->end(),
+                   [](const OwnLaunch& a, const OwnLaunch& b) { return a.cost > b.cost; });
   if (items->size() >= (size_t)std::numeric_limits<int32_t>::max())
     return fail(STRASSEN_ERR_UNSUPPORTED, "batched: too many work items");
   return 0;
@@ -188,6 +237,14 @@ static int upload(BatchedPlan* p, const std::vector<BatchProblem>& probs,
     p->dev = dev;
   }
   if (!p->d_counter) SMX_HIP(hipMalloc(&p->d_counter, 256));
+  if (!p->fork) {
+    SMX_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+    SMX_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));   // default priority
+    for (int b = 0; b < kBranches; ++b) {
+      SMX_HIP(hipStreamCreateWithFlags(&p->branch[b], hipStreamNonBlocking));   // default priority
+      SMX_HIP(hipEventCreateWithFlags(&p->join[b], hipEventDisableTiming));
+    }
+  }
   if (p->cap_probs < probs.size()) {
     if (p->d_probs) SMX_HIP(hipFree(p->d_probs));
     p->d_probs = nullptr;
@@ -232,19 +289,33 @@ static int scale_only(const BatchedPlan& p, double* const* C, const int64_t* ldc
   return 0;
 }
 
-// The batch's launches for the uploaded work: the persistent kernel over the items (after its
-// counter clear), then the all-products launches in problem order.
-static hipError_t launch_work(const BatchedPlan& p, hipStream_t s) {
-  if (p.n_items > 0) {
-    const hipError_t e =
-        launch_batched(p.d_probs, p.d_items, p.n_items, p.d_counter, p.vec, p.grid, s);
-    if (e != hipSuccess) return e;
+// The batch's launches for the uploaded work: the side streams forked from s, the persistent
+// kernel over the items (after its counter clear) and the all-products launches in problem
+// order on s, then the side streams joined back into s.  Side-stream problems go, longest
+// first, to the stream with the least work so far.
+static int launch_work(const BatchedPlan& p, hipStream_t s) {
+  double load[kBranches] = {};
+  if (!p.own.empty()) {
+    SMX_HIP(hipEventRecord(p.fork, s));
+    for (int b = 0; b < kBranches; ++b) SMX_HIP(hipStreamWaitEvent(p.branch[b], p.fork, 0));
+    const WsSource none{true, nullptr, 0, "no workspace (batched side streams)", nullptr};
+    for (const OwnLaunch& o : p.own) {
+      const int b = (int)(std::min_element(load, load + kBranches) - load);
+      load[b] += o.cost;
+      if (int rc = dgemm(o.m, o.n, o.k, p.alpha, o.A, o.lda, o.B, o.ldb, p.beta, o.C, o.ldc,
+                         o.level, STRASSEN_ABC, none, p.branch[b]))
+        return rc;
+    }
   }
-  for (const ApLaunch& l : p.ap) {
-    const hipError_t e = launch_all_products(l.f, l.na, l.nb, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  if (p.n_items > 0)
+    SMX_HIP(launch_batched(p.d_probs, p.d_items, p.n_items, p.d_counter, p.vec, p.grid, s));
+  for (const ApLaunch& l : p.ap) SMX_HIP(launch_all_products(l.f, l.na, l.nb, s));
+  if (!p.own.empty())
+    for (int b = 0; b < kBranches; ++b) {
+      SMX_HIP(hipEventRecord(p.join[b], p.branch[b]));
+      SMX_HIP(hipStreamWaitEvent(s, p.join[b], 0));
+    }
+  return 0;
 }
 
 static int run_plan(BatchedPlan* p, const double* const* A, const int64_t* lda,
@@ -256,16 +327,19 @@ static int run_plan(BatchedPlan* p, const double* const* A, const int64_t* lda,
   std::vector<BatchProblem> probs;
   std::vector<BatchItem> items;
   std::vector<ApLaunch> ap;
+  std::vector<OwnLaunch> own;
   bool vec = true;
-  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &ap, &vec))
+  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &ap, &own, &vec))
     return rc;
   if (int rc = scale_only(*p, C, ldc, alpha, beta, s)) return rc;
   drop_graph(p);   // the buffers a recorded graph reads are about to change
   if (int rc = upload(p, probs, items, s)) return rc;
   p->vec = vec;
   p->ap = std::move(ap);
-  SMX_HIP(launch_work(*p, s));
-  return 0;
+  p->own = std::move(own);
+  p->alpha = alpha;
+  p->beta = beta;
+  return launch_work(*p, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -321,6 +395,7 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
   const int64_t t2s[] = {inf, 4096, 3072, 2048};
   const int64_t smalls[] = {0, 4, 16};
   const int64_t t_aps[] = {3072, 2048, 1536, 1024};
+  const int64_t t_owns[] = {0, 512, 1024, 2048};
   Rule best = p->rule;
   float best_ms = std::numeric_limits<float>::max();
   int rc = 0;
@@ -334,8 +409,8 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
                   s);
     for (int rep = 0; rep < 3 && rc == 0 && e == hipSuccess; ++rep) {
       e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = launch_work(sp, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) rc = launch_work(sp, s);
+      if (e == hipSuccess && rc == 0) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ts[rep], e0, e1);
     }
@@ -371,6 +446,15 @@ static int autotune(BatchedPlan* p, int sample, uint64_t seed, hipStream_t s) {
       r.t_ap = ta;
       try_rule(r);
     }
+  // then problems from t_own up on the side streams (levels 0 / 1 by t1), the rest as before
+  const Rule base2 = best;
+  for (int64_t t1 : t1s)
+    for (int64_t to : t_owns) {
+      Rule r = base2;
+      r.t1 = t1;
+      r.t_own = to;
+      try_rule(r);
+    }
   free_device(&sp);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -402,13 +486,36 @@ static int capture(BatchedPlan* p, const double* const* A, const int64_t* lda,
   std::vector<BatchProblem> probs;
   std::vector<BatchItem> items;
   std::vector<ApLaunch> ap;
+  std::vector<OwnLaunch> own;
   bool vec = true;
-  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &ap, &vec))
+  if (int rc = build_work(*p, A, lda, B, ldb, C, ldc, alpha, beta, &probs, &items, &ap, &own, &vec))
     return rc;
   drop_graph(p);
   if (int rc = upload(p, probs, items, s)) return rc;
   p->vec = vec;
   p->ap = std::move(ap);
+  p->own = std::move(own);
+  p->alpha = alpha;
+  p->beta = beta;
+  if (!p->own.empty()) {
+    // side streams: the launches are recorded by stream capture on the plan's own stream (the
+    // fork and join events make the side streams branches of the graph); the library's kernel
+    // timing is suspended meanwhile
+    SMX_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    suspend_timing(true);
+    const int rc = launch_work(*p, p->cap);
+    suspend_timing(false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (rc != 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched capture");
+    p->graph = g;
+    SMX_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return 0;
+  }
   SMX_HIP(hipGraphCreate(&p->graph, 0));
   hipGraphNode_t clear_node = nullptr, run_node = nullptr;
   void* clear_args[] = {&p->d_counter};
@@ -467,8 +574,8 @@ int strassen_batched_plan(int count, const int64_t* m, const int64_t* n, const i
     if (levels[i] < -1 || levels[i] > smx::kMaxLevels)
       return smx::fail(-5, "problem %d: level %d not in -1..%d", i, levels[i], smx::kMaxLevels);
   for (int i = 0; cfg && i < count; ++i)
-    if (cfg[i] < -1 || cfg[i] > smx::kBatchAllProducts)
-      return smx::fail(-6, "problem %d: tile %d not in -1..%d", i, cfg[i], smx::kBatchAllProducts);
+    if (cfg[i] < -1 || cfg[i] > smx::kBatchOwn)
+      return smx::fail(-6, "problem %d: tile %d not in -1..%d", i, cfg[i], smx::kBatchOwn);
   auto* p = new smx::BatchedPlan;
   p->count = count;
   p->m.assign(m, m + count);

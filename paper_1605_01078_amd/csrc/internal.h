@@ -46,6 +46,10 @@ struct WsSource {
 // else library-owned under the current limit.
 WsSource default_workspace();
 
+// Suspends (true) or resumes the kernel-timing event pairs on the calling thread (launches
+// recorded into a graph by stream capture must not carry them).
+void suspend_timing(bool on);
+
 // C := alpha*A*B + beta*C (strassen_dgemm) with its workspace taken from `ws`.
 int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,

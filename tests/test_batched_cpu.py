@@ -38,7 +38,7 @@ def test_plan_argument_errors():
     assert L.strassen_batched_plan(2, None, n, k, None, None, ctypes.byref(plan)) == -2
     assert L.strassen_batched_plan(2, i64(4, -1), n, k, None, None, ctypes.byref(plan)) == -2
     assert L.strassen_batched_plan(2, m, n, k, ci(0, 3), None, ctypes.byref(plan)) == -5
-    assert L.strassen_batched_plan(2, m, n, k, None, ci(3, 0), ctypes.byref(plan)) == -6
+    assert L.strassen_batched_plan(2, m, n, k, None, ci(4, 0), ctypes.byref(plan)) == -6
     assert L.strassen_batched_plan(2, m, n, k, None, ci(0, -2), ctypes.byref(plan)) == -6
     assert L.strassen_batched_plan(2, m, n, k, None, None, None) == -7
     assert L.strassen_batched_plan(2, m, n, k, ci(1, 0), ci(2, 2), ctypes.byref(plan)) == 0

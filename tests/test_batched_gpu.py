@@ -1,5 +1,6 @@
-"""Batched mode on the GPU: every problem of a batch (persistent-kernel tiles or its own
-all-products launches) equals (bitwise) the single call with the same level and tile choice;
+"""Batched mode on the GPU: every problem of a batch (persistent-kernel tiles, its own
+all-products launches, or its own launches on a side stream) equals (bitwise) the single call
+with the same level and tile choice;
 graph replays equal the eager run; the autotuner's choices are valid and run correctly;
 scale-only problems."""
 import numpy as np
@@ -40,8 +41,9 @@ def _operands(shapes, seed):
 
 
 def _single(A, B, C, alpha, beta, level, cfg):
-    # batched tile choice 2 (own all-products launches) = tile configuration 4 of a single call
-    sx.set_tile_config(4 if cfg == 2 else cfg)
+    # batched tile choice 2 (own all-products launches) = tile configuration 4 of a single call;
+    # 3 (side streams) = the default dispatch
+    sx.set_tile_config({2: 4, 3: -1}.get(cfg, cfg))
     try:
         dC = sx.to_device(C)
         sx.dgemm(sx.to_device(A), sx.to_device(B), dC, alpha, beta, level, "abc")
@@ -109,8 +111,9 @@ def test_batched_autotune():
     b = sx.Batched(shapes)
     b.autotune(sample=0, seed=3)
     ch = b.choices()
-    assert all(lv in (0, 1, 2) and cf in (0, 1, 2) for lv, cf in ch)
+    assert all(lv in (0, 1, 2) and cf in (0, 1, 2, 3) for lv, cf in ch)
     assert all(cf != 2 or lv == 1 for lv, cf in ch)     # the rule gives own launches to L1 only
+    assert all(cf != 3 or lv <= 1 for lv, cf in ch)     # side streams: no staging workspace
     dA = [sx.to_device(A) for A, _, _ in ops]
     dB = [sx.to_device(B) for _, B, _ in ops]
     dC = [sx.to_device(C) for _, _, C in ops]
@@ -164,6 +167,44 @@ def test_batched_all_products_launches():
         ref = oracle_dgemm(A, B, C.copy(order="F"), 0.75, -1.25)
         assert rel_fro(want[i], ref) <= TOL[levels[i]]
     b.capture(dA, dB, dC, 0.75, -1.25)
+    for rep in range(3):
+        for c, c0 in zip(dC, C0):      # eager work between replays: reset C
+            c.copy_(c0)
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        for i, c in enumerate(dC):
+            assert np.array_equal(sx.to_host(c), want[i]), (rep, i)
+    b.close()
+
+
+def test_batched_side_streams():
+    """Problems on side streams (tile choice 3: their own single-call launches without
+    workspace, spread over streams forked from and joined into the caller's) beside
+    persistent-kernel and all-products problems: the classical kernel, the all-products kernel,
+    the tile kernel for ragged shapes (where a single call would pad: bitwise the same), two
+    levels with the outer sums in the load; eager run and graph replays equal single calls."""
+    shapes = [(4096, 2048, 512), (1024, 1024, 1024), (1024, 704, 512), (301, 259, 271),
+              (512, 512, 1024), (768, 640, 512), (130, 70, 200), (640, 640, 640), (2048, 1024, 768)]
+    levels = [0, 1, 1, 1, 2, 0, 0, 1, 0]
+    cfg = [3, 3, 3, 3, 3, 3, 0, 2, 3]
+    print(f"case batched side streams {shapes}", flush=True)
+    ops = _operands(shapes, 900)
+    b = sx.Batched(shapes, levels, cfg)
+    assert b.choices() == list(zip(levels, cfg))
+    dA = [sx.to_device(A) for A, _, _ in ops]
+    dB = [sx.to_device(B) for _, B, _ in ops]
+    C0 = [sx.to_device(C) for _, _, C in ops]
+    dC = [c.clone() for c in C0]
+    b.run(dA, dB, dC, -0.75, 1.5)
+    torch.cuda.synchronize()
+    want = [_single(A, B, C, -0.75, 1.5, lv, cf) for (A, B, C), lv, cf in zip(ops, levels, cfg)]
+    for i, c in enumerate(dC):
+        assert np.array_equal(sx.to_host(c), want[i]), (i, shapes[i])
+        A, B, C = ops[i]
+        ref = oracle_dgemm(A, B, C.copy(order="F"), -0.75, 1.5)
+        assert rel_fro(want[i], ref) <= TOL[levels[i]]
+    b.capture(dA, dB, dC, -0.75, 1.5)
     for rep in range(3):
         for c, c0 in zip(dC, C0):      # eager work between replays: reset C
             c.copy_(c0)
