@@ -171,34 +171,46 @@ __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args, int nslo
 // ---------------------------------------------------------------------------------------------
 // BF16 product kernel.
 // ---------------------------------------------------------------------------------------------
-// Tiles: BM x BN = 128 x BN (BN 128 or 64), 4 waves of 64 x BN/2 (4 x BN/32 blocks of 16 x 16
-// MFMA), k step BK (bf16 elements).  Stage s holds the tiles of stream position s: A hi, B hi
-// (, A lo, B lo), A tiles BM rows and B tiles BN rows of BK values, 16-byte chunks XOR-swizzled
-// by row pair.  The 128 x 64 form doubles the workgroups where 128 x 128 tiles would leave CUs
-// with one workgroup (the two-level products), at 1.5 times the LDS reads per MFMA.
-template <bool X3, int BK, int NS, int BN>
+// Tiles: BM x BN per workgroup, NWM x NWN waves, each wave a WTM x WTN block (WTM / 16 x WTN / 16
+// blocks of 16 x 16 MFMA), k step BK (bf16 elements).  Stage s holds the tiles of stream
+// position s: A hi, B hi (, A lo, B lo), A tiles BM rows and B tiles BN rows of BK values,
+// 16-byte chunks XOR-swizzled by row (swz).  LDS reads per MFMA fall with the wave block's size:
+// (WTM + WTN) / (WTM WTN) chunks per flop, so the 256 x 256 form (eight waves of 128 x 64) reads
+// three quarters of what the 128 x 128 form (four waves of 64 x 64) reads per flop, and the
+// 128 x 64 form (four waves of 64 x 32) half again as much; the smaller forms give more
+// workgroups where the product's sub-blocks are small.
+template <bool X3, int BK, int NS, int BM, int BN, int NWM, int NWN, bool EDGE>
 struct Bf16Gemm {
-  static constexpr int BM = 128;
+  static constexpr int NW = NWM * NWN;                 // waves
+  static constexpr int WTM = BM / NWM, WTN = BN / NWN; // wave block
+  static constexpr int NFM = WTM / 16, NFN = WTN / 16; // 16 x 16 MFMA blocks per wave
   static constexpr int CPR = BK / 8;                  // 16-byte chunks per tile row
   static constexpr int TILE_A = BM * BK * 2;          // bytes of one A tile
   static constexpr int TILE_B = BN * BK * 2;          // bytes of one B tile
   static constexpr int PAIR = TILE_A + TILE_B;         // one A and one B tile
   static constexpr int STAGE_B = (X3 ? 2 : 1) * PAIR;
-  static constexpr int LPA = TILE_A / 4096;           // 64-lane x 16-byte loads per wave, A tile
-  static constexpr int LPB = TILE_B / 4096;           // B tile
+  static constexpr int ROUND = NW * 1024;             // bytes of one load by every wave
+  static constexpr int LPA = TILE_A / ROUND;          // 64-lane x 16-byte loads per wave, A tile
+  static constexpr int LPB = TILE_B / ROUND;          // B tile
   static constexpr int IPW = (X3 ? 2 : 1) * (LPA + LPB);   // loads per wave and step
-  static constexpr int NFB = BN / 32;                 // 16-column blocks per wave
   static constexpr int KK = BK / 32;                  // MFMA k sub-steps per step
   static constexpr int LDS_B = NS * STAGE_B;
   static_assert(LDS_B <= 160 * 1024, "LDS");
   static_assert(BK == 32 || BK == 64, "k step");
-  static_assert((BN == 128 || BN == 64) && LPB >= 1, "tile columns");
+  static_assert(LPA >= 1 && LPB >= 1 && TILE_A % ROUND == 0 && TILE_B % ROUND == 0, "load split");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave block");
 
-  __device__ static void run(const Bf16Args& args, char* lds) {
+  // 16-byte chunk swizzle of tile row r: the chunk index XOR-ed with the row pair.  A fragment
+  // read (one chunk of 16 consecutive rows per quarter-wave) is then free of bank conflicts for
+  // rows of 64 and 128 bytes (k steps 32 and 64), as the bank-conflict counter shows for both
+  // on gfx950; XOR-ing with r / 4 instead conflicts 2-way at 64-byte rows.
+  __device__ static int swz(int r) { return (r >> 1) & (CPR - 1); }
+
+  __device__ __attribute__((always_inline)) static void run(const Bf16Args& args, char* lds) {
     const TableDev& tab = g_tables_bf16[args.tab];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % NWM, wn = wave / NWM;
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
     int ti, tj;
     tile_coords(logical, args.tiles_m, args.tiles_n, ti, tj);
@@ -206,18 +218,19 @@ struct Bf16Gemm {
     const int nk = (int)(args.kpad / BK);
     const int nprod = tab.nprod;
 
-    // Lane byte offsets inside a product slot for load jj of a tile (part wave + 4 jj):
+    // Lane byte offsets inside a product slot for load jj of a tile (part wave + NW jj):
     // position p = 64 part + lane is row p / CPR, stored chunk p % CPR = logical chunk ^ swizzle.
-    auto lane_off = [&](int jj, int64_t rc0) {
-      const int p = (wave + 4 * jj) * 64 + lane;
-      const int row = p / CPR, pc = p % CPR, c = pc ^ ((row >> 1) & (CPR - 1));
-      return (uint32_t)(2 * ((rc0 + row) * args.kpad + c * 8));
+    // Rows past the slot's padded extent (a tile that overhangs it) load as zero.
+    auto lane_off = [&](int jj, int64_t rc0, int64_t rows) {
+      const int p = (wave + NW * jj) * 64 + lane;
+      const int row = p / CPR, pc = p % CPR, c = pc ^ swz(row);
+      return rc0 + row < rows ? (uint32_t)(2 * ((rc0 + row) * args.kpad + c * 8)) : kOOB;
     };
     uint32_t off_a[LPA], off_b[LPB];
 #pragma unroll
-    for (int jj = 0; jj < LPA; ++jj) off_a[jj] = lane_off(jj, row0);
+    for (int jj = 0; jj < LPA; ++jj) off_a[jj] = lane_off(jj, row0, args.rows_a);
 #pragma unroll
-    for (int jj = 0; jj < LPB; ++jj) off_b[jj] = lane_off(jj, col0);
+    for (int jj = 0; jj < LPB; ++jj) off_b[jj] = lane_off(jj, col0, args.rows_b);
     // the load stream: product ri, k step ki, and the slot bases of product ri (uniform)
     int ri = 0, ki = 0;
     const uint16_t* base[4];   // A hi, B hi, A lo, B lo of product ri
@@ -243,10 +256,10 @@ struct Bf16Gemm {
       for (int h = 0; h < (X3 ? 2 : 1); ++h) {   // hi tiles, then lo tiles
 #pragma unroll
         for (int jj = 0; jj < LPA; ++jj)
-          load(2 * h, sb + h * PAIR + (wave + 4 * jj) * 1024, off_a[jj]);
+          load(2 * h, sb + h * PAIR + (wave + NW * jj) * 1024, off_a[jj]);
 #pragma unroll
         for (int jj = 0; jj < LPB; ++jj)
-          load(2 * h + 1, sb + h * PAIR + TILE_A + (wave + 4 * jj) * 1024, off_b[jj]);
+          load(2 * h + 1, sb + h * PAIR + TILE_A + (wave + NW * jj) * 1024, off_b[jj]);
       }
       if (++ki == nk) {
         ki = 0;
@@ -254,52 +267,69 @@ struct Bf16Gemm {
       }
     };
 
-    // fragment reads: rows (A) / columns (B) 16 f + lane % 16 of the wave's 64, chunk 4 kk + g
+    // fragment reads: rows (A) / columns (B) 16 f + lane % 16 of the wave's block, chunk 4 kk + g
     const int g = lane >> 4, li = lane & 15;
     auto frag = [&](const char* tile, int rr, int chunk) {
-      const int pc = chunk ^ ((rr >> 1) & (CPR - 1));
+      const int pc = chunk ^ swz(rr);
       return *reinterpret_cast<const bf8_t*>(tile + rr * (2 * BK) + pc * 16);
     };
 
-    f4_t acc[4][NFB];
+    f4_t acc[NFM][NFN];
     auto zero = [&]() {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < NFM; ++a)
 #pragma unroll
-        for (int b = 0; b < NFB; ++b) acc[a][b] = (f4_t){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NFN; ++b) acc[a][b] = (f4_t){0.f, 0.f, 0.f, 0.f};
     };
+    // one k sub-step at a time: its fragments, then its MFMAs (fragments of one sub-step live)
     auto compute = [&](int stage) {
       const char* sb = lds + stage * STAGE_B;
-      bf8_t ah[KK][4], bh[KK][NFB], al[KK][4], bl[KK][NFB];
 #pragma unroll
       for (int kk = 0; kk < KK; ++kk) {
+        bf8_t ah[NFM], bh[NFN], al[NFM], bl[NFN];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          ah[kk][f] = frag(sb, wm * 64 + 16 * f + li, 4 * kk + g);
-          if (X3) al[kk][f] = frag(sb + PAIR, wm * 64 + 16 * f + li, 4 * kk + g);
+        for (int f = 0; f < NFM; ++f) {
+          ah[f] = frag(sb, wm * WTM + 16 * f + li, 4 * kk + g);
+          if (X3) al[f] = frag(sb + PAIR, wm * WTM + 16 * f + li, 4 * kk + g);
         }
 #pragma unroll
-        for (int f = 0; f < NFB; ++f) {
-          bh[kk][f] = frag(sb + TILE_A, wn * (BN / 2) + 16 * f + li, 4 * kk + g);
-          if (X3) bl[kk][f] = frag(sb + PAIR + TILE_A, wn * (BN / 2) + 16 * f + li, 4 * kk + g);
+        for (int f = 0; f < NFN; ++f) {
+          bh[f] = frag(sb + TILE_A, wn * WTN + 16 * f + li, 4 * kk + g);
+          if (X3) bl[f] = frag(sb + PAIR + TILE_A, wn * WTN + 16 * f + li, 4 * kk + g);
         }
-      }
 #pragma unroll
-      for (int kk = 0; kk < KK; ++kk)
+        for (int fm = 0; fm < NFM; ++fm)
 #pragma unroll
-        for (int fm = 0; fm < 4; ++fm)
-#pragma unroll
-          for (int fn = 0; fn < NFB; ++fn) {
-            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kk][fm], bh[kk][fn], acc[fm][fn], 0, 0, 0);
+          for (int fn = 0; fn < NFN; ++fn) {
+            acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fm], bh[fn], acc[fm][fn], 0, 0, 0);
             if (X3) {
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[kk][fm], bl[kk][fn], acc[fm][fn], 0, 0, 0);
-              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[kk][fm], bh[kk][fn], acc[fm][fn], 0, 0, 0);
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fm], bl[fn], acc[fm][fn], 0, 0, 0);
+              acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[fm], bh[fn], acc[fm][fn], 0, 0, 0);
             }
           }
+      }
     };
 
+    // The C update of one element: FP64, or FP32 (C rounded to FP32, the update in FP32).  The
+    // empty asm keeps the product's conversion inside the destination loop: hoisted out of it,
+    // the FP64 copies of every accumulator would need twice the accumulators' registers.
+    auto update = [&](double c, float mv, double ag, bool first) {
+      asm volatile("" : "+v"(mv));
+      if (args.c_f64) return c_update(c, (double)mv, ag, args.beta, first);
+      const float ag32 = (float)ag, b32 = (float)args.beta;
+      float c32 = (float)c;
+      if (first) c32 = args.beta == 0.0 ? ag32 * mv : __builtin_fmaf(ag32, mv, b32 * c32);
+      else c32 = __builtin_fmaf(ag32, mv, c32);
+      return (double)c32;
+    };
     // Epilogue of product r: lane l, element e of block (fm, fn) is tile row
-    // 64 wm + 16 fm + 4 (l / 16) + e, column (BN / 2) wn + 16 fn + l % 16.
+    // WTM wm + 16 fm + 4 (l / 16) + e, column WTN wn + 16 fn + l % 16.  Its byte offset is the
+    // lane's base (row WTM wm + 4 (l / 16), column WTN wn + l % 16) plus 8 (16 fm + e), an
+    // instruction immediate, plus 128 fn ldc, a scalar, so no per-element offset stays live.
+    // Where the workgroup's block of this destination lies wholly inside C and its row pairs
+    // are 16-byte aligned (vec_c), rows e = 0, 1 and 2, 3 move as 16-byte pairs; else element
+    // by element, masked.  Without EDGE the launch guarantees the former for every block.
+    const uint32_t e_base = (uint32_t)(8 * (wm * WTM + 4 * g + (int64_t)(wn * WTN + li) * args.ldc));
     auto epilogue = [&](int r) {
       const ProdDesc& pd = tab.prod[r];
       const int64_t ldc = args.ldc;
@@ -313,33 +343,44 @@ struct Bf16Gemm {
         const int64_t clim = min64(args.nq, args.n - cj * args.nq) - col0;
         const __amdgpu_buffer_rsrc_t rs =
             make_rsrc(args.C + (ci * args.mq + row0) + (cj * args.nq + col0) * ldc);
+        if (!EDGE || (args.vec_c && rlim >= BM && clim >= BN)) {
 #pragma unroll
-        for (int fm = 0; fm < 4; ++fm) {
+          for (int fm = 0; fm < NFM; ++fm) {
 #pragma unroll
-          for (int fn = 0; fn < NFB; ++fn) {
-            const int cl = wn * (BN / 2) + 16 * fn + li;
+            for (int fn = 0; fn < NFN; ++fn) {
+              const uint32_t so = (uint32_t)(128 * fn * ldc);
+#pragma unroll
+              for (int e = 0; e < 4; e += 2) {
+                const uint32_t off = e_base + 8 * (16 * fm + e);
+                d2_t c = {0.0, 0.0};
+                if (read_c)
+                  c = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, so, 0));
+                c.x = update(c.x, acc[fm][fn][e], ag, first);
+                c.y = update(c.y, acc[fm][fn][e + 1], ag, first);
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, c), rs, off, so, 0);
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the C traffic of one row block together
+          }
+          continue;
+        }
+#pragma unroll
+        for (int fm = 0; fm < NFM; ++fm) {
+#pragma unroll
+          for (int fn = 0; fn < NFN; ++fn) {
+            const uint32_t so = (uint32_t)(128 * fn * ldc);
+            const bool col_ok = wn * WTN + 16 * fn + li < clim;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const int rl = wm * 64 + 16 * fm + 4 * g + e;
-              const bool ok = rl < rlim && cl < clim;
-              const uint32_t off = (uint32_t)(8 * (rl + (int64_t)cl * ldc));
-              double c = __builtin_bit_cast(
-                  double, __builtin_amdgcn_raw_buffer_load_b64(rs, (ok && read_c) ? off : kOOB, 0, 0));
-              const float mv = acc[fm][fn][e];
-              double out;
-              if (args.c_f64) {
-                out = c_update(c, (double)mv, ag, args.beta, first);
-              } else {
-                const float ag32 = (float)ag, b32 = (float)args.beta;
-                float c32 = (float)c;
-                if (first) c32 = args.beta == 0.0 ? ag32 * mv : __builtin_fmaf(ag32, mv, b32 * c32);
-                else c32 = __builtin_fmaf(ag32, mv, c32);
-                out = (double)c32;
-              }
-              __builtin_amdgcn_raw_buffer_store_b64(as_u2(out), rs, ok ? off : kOOB, 0, 0);
+              const bool ok = col_ok && wm * WTM + 16 * fm + 4 * g + e < rlim;
+              const uint32_t off = e_base + 8 * (16 * fm + e);
+              const double c = __builtin_bit_cast(
+                  double, __builtin_amdgcn_raw_buffer_load_b64(rs, (ok && read_c) ? off : kOOB, so, 0));
+              const double out = update(c, acc[fm][fn][e], ag, first);
+              __builtin_amdgcn_raw_buffer_store_b64(as_u2(out), rs, ok ? off : kOOB, so, 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
-          __builtin_amdgcn_sched_barrier(0);   // keep the C traffic of one row block together
         }
       }
     };
@@ -365,9 +406,9 @@ struct Bf16Gemm {
   }
 };
 
-template <bool X3, int BK, int NS, int WPC, int BN>
-__global__ __launch_bounds__(256, WPC) void bf16_gemm_kernel(const Bf16Args args) {
-  using K = Bf16Gemm<X3, BK, NS, BN>;
+template <bool X3, int BK, int NS, int WPC, int BM, int BN, int NWM, int NWN, bool EDGE>
+__global__ __launch_bounds__(64 * NWM * NWN, WPC) void bf16_gemm_kernel(const Bf16Args args) {
+  using K = Bf16Gemm<X3, BK, NS, BM, BN, NWM, NWN, EDGE>;
   __shared__ __attribute__((aligned(16))) char lds[K::LDS_B];
   K::run(args, lds);
 }
@@ -386,15 +427,23 @@ hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
 }
 
 hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s) {
-  const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n)), block(256);
-  // two workgroups per CU (at most 64 KB of LDS each): one hides the other's LDS latency and
-  // barriers
-  if (a.bn == 64) {
-    if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 64>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 64>), grid, block, 0, s, a);
-  } else {
-    if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128>), grid, block, 0, s, a);
+  const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n));
+  // 128 x 128 and 128 x 64: four waves, two workgroups per CU (at most 64 KB of LDS each), one
+  // hiding the other's LDS latency and barriers; 256 x 256: eight waves (two per SIMD), one
+  // workgroup per CU, two stages of k step 64 in 128 KB of LDS
+  switch (a.shape) {
+    case 2:   // whole tiles only (the host checks), FP32-accumulated BF16 products only
+      if (a.x3) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 1, 256, 256, 2, 4, false>), grid, dim3(512), 0, s, a);
+      break;
+    case 1:
+      if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128, 64, 2, 2, true>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128, 64, 2, 2, true>), grid, dim3(256), 0, s, a);
+      break;
+    default:
+      if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128, 128, 2, 2, true>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128, 128, 2, 2, true>), grid, dim3(256), 0, s, a);
+      break;
   }
   return hipGetLastError();
 }
