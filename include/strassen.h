@@ -411,12 +411,8 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
  *   5: as 4, with the two-level outer operand sums staged wherever n % 4 == 0 (the workspace,
  *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise).
  * The default (-1) uses the all-products kernel wherever it applies and stages as described
- * at strassen_dgemm.  For strassen_gemm_ex, 0 / 1 / 2 force the BF16 product kernel's
- * 128 x 128 / 128 x 64 / 256 x 256 workgroup tiles; 256 x 256 (eight waves of 128 x 64) applies
- * to BF16 products (not bf16x3) where every tile is whole: sub-blocks of multiples of 256 rows
- * and columns lying wholly inside C, C 16-byte aligned with even ldc (elsewhere 2 means
- * 128 x 128).  Default: 256 x 256 where it applies and gives at least 256 tiles, else 128 x 128
- * where those number at least 512, else 128 x 64.
+ * at strassen_dgemm.  For strassen_gemm_ex, 0 / 1 force the BF16 product kernel's 128 x 128 /
+ * 128 x 64 workgroup tiles (default: 128 x 64 where 128 x 128 tiles would number fewer than 512).
  * Results do not depend on the configuration (bitwise).  The environment variable
  * STRASSEN_TILE_CFG sets the initial value.  Returns 0 or -1 (cfg out of range).
  */

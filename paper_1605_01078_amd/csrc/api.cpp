@@ -1613,26 +1613,14 @@ int gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   g.x3 = p.x3;
   g.c_f64 = c_prec == STRASSEN_PREC_F64;
   g.vec_c = aligned16(C) && ldc % 2 == 0 && p.mq % 2 == 0;
-  g.rows_a = (int32_t)p.mp;
-  g.rows_b = (int32_t)p.np;
-  // Workgroup tiles: 256 x 256 (BF16 products) where every tile is whole (sub-blocks of
-  // multiples of 256 that lie wholly inside C, 16-byte aligned C pairs) and they alone give every
-  // CU a workgroup; else 128 x 128 where those give every CU two; else 128 x 64.  Tile
-  // configuration 0 / 1 force 128 x 128 / 128 x 64, 2 forces 256 x 256 where it applies.
+  // 128 x 64 workgroup tiles where 128 x 128 ones would not give every CU two workgroups
+  // (tile configuration 0 / 1 force 128 x 128 / 128 x 64)
   {
     const int forced = g_forced_cfg.load(std::memory_order_relaxed);
-    const int64_t q = int64_t(1) << levels;
-    const bool whole256 = !p.x3 && g.vec_c && p.mq % 256 == 0 && p.nq % 256 == 0 &&
-                          m == q * p.mq && n == q * p.nq && 8 * 256 * ldc < lim;
-    const int64_t t256 = (p.mp / 256) * (p.np / 256), t128 = (p.mp / 128) * (p.np / 128);
-    if (forced == kCfg64) g.shape = 1;
-    else if (forced == kCfg128) g.shape = 0;
-    else if (forced == 2 && whole256) g.shape = 2;
-    else if (forced == 2) g.shape = 0;
-    else g.shape = whole256 && t256 >= 256 ? 2 : (t128 >= 512 ? 0 : 1);
-    const int bm = g.shape == 2 ? 256 : 128, bn = g.shape == 2 ? 256 : (g.shape == 1 ? 64 : 128);
-    g.tiles_m = (int32_t)cdiv(p.mp, bm);
-    g.tiles_n = (int32_t)cdiv(p.np, bn);
+    const int64_t t128 = (p.mp / 128) * (p.np / 128);
+    g.shape = forced == kCfg64 || (forced != kCfg128 && t128 < 512) ? 1 : 0;
+    g.tiles_m = (int32_t)(p.mp / 128);
+    g.tiles_n = (int32_t)(p.np / (g.shape == 1 ? 64 : 128));
   }
   SMX_LAUNCH(STRASSEN_KERNEL_BF16, stream, launch_bf16_gemm(g, stream));
   return 0;

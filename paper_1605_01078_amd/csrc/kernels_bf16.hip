@@ -174,12 +174,13 @@ __global__ __launch_bounds__(256) void cast_kernel(const CastArgs args, int nslo
 // Tiles: BM x BN per workgroup, NWM x NWN waves, each wave a WTM x WTN block (WTM / 16 x WTN / 16
 // blocks of 16 x 16 MFMA), k step BK (bf16 elements).  Stage s holds the tiles of stream
 // position s: A hi, B hi (, A lo, B lo), A tiles BM rows and B tiles BN rows of BK values,
-// 16-byte chunks XOR-swizzled by row (swz).  LDS reads per MFMA fall with the wave block's size:
-// (WTM + WTN) / (WTM WTN) chunks per flop, so the 256 x 256 form (eight waves of 128 x 64) reads
-// three quarters of what the 128 x 128 form (four waves of 64 x 64) reads per flop, and the
-// 128 x 64 form (four waves of 64 x 32) half again as much; the smaller forms give more
-// workgroups where the product's sub-blocks are small.
-template <bool X3, int BK, int NS, int BM, int BN, int NWM, int NWN, bool EDGE>
+// 16-byte chunks XOR-swizzled by row (swz).  The 128 x 128 form runs four waves of 64 x 64; the
+// 128 x 64 form (four waves of 64 x 32, half again the LDS reads per flop) doubles the
+// workgroups where the product's sub-blocks are small.  (A 256 x 256 form of eight waves of
+// 128 x 64, three quarters of the LDS reads per flop, measured no faster: at 8192 its LDS was
+// active 18% of the time, free of bank conflicts, while its waves waited on memory counters
+// for about half of theirs.)
+template <bool X3, int BK, int NS, int BM, int BN, int NWM, int NWN>
 struct Bf16Gemm {
   static constexpr int NW = NWM * NWN;                 // waves
   static constexpr int WTM = BM / NWM, WTN = BN / NWN; // wave block
@@ -220,17 +221,16 @@ struct Bf16Gemm {
 
     // Lane byte offsets inside a product slot for load jj of a tile (part wave + NW jj):
     // position p = 64 part + lane is row p / CPR, stored chunk p % CPR = logical chunk ^ swizzle.
-    // Rows past the slot's padded extent (a tile that overhangs it) load as zero.
-    auto lane_off = [&](int jj, int64_t rc0, int64_t rows) {
+    auto lane_off = [&](int jj, int64_t rc0) {
       const int p = (wave + NW * jj) * 64 + lane;
       const int row = p / CPR, pc = p % CPR, c = pc ^ swz(row);
-      return rc0 + row < rows ? (uint32_t)(2 * ((rc0 + row) * args.kpad + c * 8)) : kOOB;
+      return (uint32_t)(2 * ((rc0 + row) * args.kpad + c * 8));
     };
     uint32_t off_a[LPA], off_b[LPB];
 #pragma unroll
-    for (int jj = 0; jj < LPA; ++jj) off_a[jj] = lane_off(jj, row0, args.rows_a);
+    for (int jj = 0; jj < LPA; ++jj) off_a[jj] = lane_off(jj, row0);
 #pragma unroll
-    for (int jj = 0; jj < LPB; ++jj) off_b[jj] = lane_off(jj, col0, args.rows_b);
+    for (int jj = 0; jj < LPB; ++jj) off_b[jj] = lane_off(jj, col0);
     // the load stream: product ri, k step ki, and the slot bases of product ri (uniform)
     int ri = 0, ki = 0;
     const uint16_t* base[4];   // A hi, B hi, A lo, B lo of product ri
@@ -328,7 +328,7 @@ struct Bf16Gemm {
     // instruction immediate, plus 128 fn ldc, a scalar, so no per-element offset stays live.
     // Where the workgroup's block of this destination lies wholly inside C and its row pairs
     // are 16-byte aligned (vec_c), rows e = 0, 1 and 2, 3 move as 16-byte pairs; else element
-    // by element, masked.  Without EDGE the launch guarantees the former for every block.
+    // by element, masked.
     const uint32_t e_base = (uint32_t)(8 * (wm * WTM + 4 * g + (int64_t)(wn * WTN + li) * args.ldc));
     auto epilogue = [&](int r) {
       const ProdDesc& pd = tab.prod[r];
@@ -343,7 +343,7 @@ struct Bf16Gemm {
         const int64_t clim = min64(args.nq, args.n - cj * args.nq) - col0;
         const __amdgpu_buffer_rsrc_t rs =
             make_rsrc(args.C + (ci * args.mq + row0) + (cj * args.nq + col0) * ldc);
-        if (!EDGE || (args.vec_c && rlim >= BM && clim >= BN)) {
+        if (args.vec_c && rlim >= BM && clim >= BN) {
 #pragma unroll
           for (int fm = 0; fm < NFM; ++fm) {
 #pragma unroll
@@ -406,9 +406,9 @@ struct Bf16Gemm {
   }
 };
 
-template <bool X3, int BK, int NS, int WPC, int BM, int BN, int NWM, int NWN, bool EDGE>
+template <bool X3, int BK, int NS, int WPC, int BM, int BN, int NWM, int NWN>
 __global__ __launch_bounds__(64 * NWM * NWN, WPC) void bf16_gemm_kernel(const Bf16Args args) {
-  using K = Bf16Gemm<X3, BK, NS, BM, BN, NWM, NWN, EDGE>;
+  using K = Bf16Gemm<X3, BK, NS, BM, BN, NWM, NWN>;
   __shared__ __attribute__((aligned(16))) char lds[K::LDS_B];
   K::run(args, lds);
 }
@@ -428,22 +428,14 @@ hipError_t launch_cast(const CastArgs& a, int nslots, hipStream_t s) {
 
 hipError_t launch_bf16_gemm(const Bf16Args& a, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.tiles_m * a.tiles_n));
-  // 128 x 128 and 128 x 64: four waves, two workgroups per CU (at most 64 KB of LDS each), one
-  // hiding the other's LDS latency and barriers; 256 x 256: eight waves (two per SIMD), one
-  // workgroup per CU, two stages of k step 64 in 128 KB of LDS
-  switch (a.shape) {
-    case 2:   // whole tiles only (the host checks), FP32-accumulated BF16 products only
-      if (a.x3) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 1, 256, 256, 2, 4, false>), grid, dim3(512), 0, s, a);
-      break;
-    case 1:
-      if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128, 64, 2, 2, true>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128, 64, 2, 2, true>), grid, dim3(256), 0, s, a);
-      break;
-    default:
-      if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128, 128, 2, 2, true>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128, 128, 2, 2, true>), grid, dim3(256), 0, s, a);
-      break;
+  // four waves, two workgroups per CU (at most 64 KB of LDS each), one hiding the other's LDS
+  // latency and barriers
+  if (a.shape == 1) {
+    if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128, 64, 2, 2>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128, 64, 2, 2>), grid, dim3(256), 0, s, a);
+  } else {
+    if (a.x3) hipLaunchKernelGGL((bf16_gemm_kernel<true, 32, 2, 2, 128, 128, 2, 2>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((bf16_gemm_kernel<false, 64, 2, 2, 128, 128, 2, 2>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -191,9 +191,8 @@ struct Bf16Args {
   int32_t tab, tiles_m, tiles_n;
   int32_t x3;                   // 1: bf16x3 (hi*hi + hi*lo + lo*hi)
   int32_t c_f64;                // 1: C update in FP64, 0: in FP32
-  int32_t shape;                // workgroup tile: 0 = 128 x 128, 1 = 128 x 64, 2 = 256 x 256
+  int32_t shape;                // workgroup tile: 0 = 128 x 128, 1 = 128 x 64
   int32_t vec_c;                // 1: C 16-byte aligned, ldc and the sub-block rows even
-  int32_t rows_a, rows_b;       // padded rows of an A-side / B-side slot (tiles may overhang)
 };
 
 // Batched mode: one problem (its tile-kernel arguments and tile shape) and one work item.

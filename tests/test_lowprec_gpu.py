@@ -115,33 +115,6 @@ def test_product_tile_widths_bitwise(levels, compute):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("levels,shape", [(0, (512, 768, 390)), (1, (1024, 512, 390)),
-                                          (2, (1024, 1024, 200)), (0, (4096, 4096, 256))])
-def test_product_tile_256_bitwise(levels, shape):
-    """The 256 x 256 workgroup tiles of eight waves (BF16 products, whole tiles only: forced by
-    tile configuration 2 at small sizes, chosen by default from 16 x 16 tiles per sub-block)
-    give the bits of the 128 x 128 tiles, and the mode oracle's bound holds."""
-    m, n, k = shape
-    print(f"case tile 256 L={levels} {shape}", flush=True)
-    A, B, C = W.problem(92, m, n, k, "uniform")
-    dA, dB = sx.to_device(A), sx.to_device(B)
-    for mode in (("bf16", "f64", "f32"), ("bf16", "f32", "f64")):
-        outs = []
-        try:
-            for cfg in (0, 2 if m < 4096 else -1):
-                sx.set_tile_config(cfg)
-                dC = sx.to_device(C)
-                sx.gemm_ex(dA, dB, dC, 0.75, -0.5, levels, *mode)
-                torch.cuda.synchronize()
-                outs.append(sx.to_host(dC))
-        finally:
-            sx.set_tile_config(-1)
-        assert np.array_equal(outs[0], outs[1]), mode
-        if m < 4096:
-            ref, bound = gemm_lowprec(A, B, C, 0.75, -0.5, levels, *mode)
-            assert (np.abs(outs[1] - ref) <= bound).all(), mode
-
-
 def _bf16_bits(x32):
     """Upper 16 bits of float32 values that are exact bf16 values."""
     return (np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
