@@ -783,10 +783,14 @@ def main():
         # (levels, variant, tile configuration); two-level ABC as the paper defines it, without
         # workspace (outer sums formed in the load: configuration 4), beside the default form
         # that stages the outer operand sums in workspace
+        # (the staged form once more under a workspace cap that holds one outer product's two
+        # sum slots, m/2 x k/2 and k/2 x n/2 doubles, but not all ten: one product at a time)
+        one_slots = 8 * 2 * (n // 2) * (n // 2)
         members = {"L0_abc": (0, "abc", -1), "L1_abc": (1, "abc", -1), "L1_ab": (1, "ab", -1),
                    "L1_naive": (1, "naive", -1), "L2_abc": (2, "abc", 4),
-                   "L2_abc_staged": (2, "abc", -1), "L2_ab": (2, "ab", -1),
-                   "L2_naive": (2, "naive", -1),
+                   "L2_abc_staged": (2, "abc", -1),
+                   "L2_abc_staged_one_at_a_time": (2, "abc", -1, one_slots + (1 << 20)),
+                   "L2_ab": (2, "ab", -1), "L2_naive": (2, "naive", -1),
                    # Winograd's variant (ABC; two levels with staged outer chain sums)
                    "L1_winograd": (1, "winograd", -1), "L2_winograd": (2, "winograd", -1)}
 
@@ -795,7 +799,9 @@ def main():
                 f = lambda: torch.matmul(Ac, Bc, out=Cv)
                 cfg = -1
             else:
-                lev, var, cfg = members[key]
+                lev, var, cfg = members[key][:3]
+                if len(members[key]) > 3:
+                    sx.set_workspace_limit(members[key][3])
                 if var == "winograd":
                     f = lambda: sx.dgemm_winograd(A, B, Cw, 1.0, 1.0, lev, stream)
                 else:
@@ -812,6 +818,8 @@ def main():
             finally:
                 if cfg >= 0:
                     sx.set_tile_config(-1)
+                if key != "vendor" and len(members[key]) > 3:
+                    sx.set_workspace_limit(0)
             return e0.elapsed_time(e1)
 
         keys = list(members) + ["vendor"]
@@ -831,6 +839,9 @@ def main():
                 vendor = entry
             else:
                 variants[key] = entry
+                if key.startswith("L2_abc"):   # the workspace each two-level ABC form used
+                    entry["workspace_bytes"] = {"L2_abc": 0, "L2_abc_staged": sx.workspace_size(n, n, n, 2, "abc"),
+                                                "L2_abc_staged_one_at_a_time": one_slots}[key]
             log(f"  {key:16s}: {ms:8.3f} ms  {entry['tflops']:6.2f} TF  x{entry['speedup_vs_classical']:.3f}")
         del Cv, Ac, Bc
         # a size that does not split evenly (n - 1: every sub-block extent odd), classical, the

@@ -104,7 +104,11 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * table over the 2 x 2 outer blocks, formed once by a streaming pass; the seven outer products
  * then run the one-level fused kernel on them and update C in place, bitwise as without
  * staging): by default where (m/2)(n/2) >= 2048^2 and k >= 2048 and a library-owned or large
- * enough caller workspace is available; otherwise the sums are formed in the load.
+ * enough caller workspace is available.  A workspace (the caller's, or the library's under
+ * strassen_set_workspace_limit) too small for the ten sums but holding one m/2 x k/2 and one
+ * k/2 x n/2 slot (a fifth of it) stages one outer product's sums at a time, just before its
+ * launch (each sum still formed once; the same bits); smaller still, the sums are formed in
+ * the load.
  * ABC at levels >= 1 runs on block-padded copies of the operands that do not fit the fused
  * kernel's layout (m or k not a multiple of 2^(L+1), an operand not 16-byte aligned or with an
  * odd leading dimension; B and C also where staging needs n % 4 == 0): every sub-block of the
@@ -225,7 +229,8 @@ int strassen_dgemm_noalloc(int64_t m, int64_t n, int64_t k, double alpha,
  * doubles); otherwise the block-padded copies (A as mp x kp, B as kp x n', C as mp x n' where
  * it is copied; mp = 2^L * (ceil(m/2^L) rounded up to even), kp likewise, n' = n rounded up to
  * 4 where staging needs it; each rounded up to 32 doubles) plus the staging buffers of the
- * padded problem.  A smaller caller workspace only turns staging or the copies off.
+ * padded problem.  A smaller caller workspace stages one outer product at a time (see above),
+ * or turns staging or the copies off.
  * Returns 0 or -i as strassen_dgemm does for the same argument (m=1 n=2 k=3 levels=4
  * variant=5 bytes=6).
  */

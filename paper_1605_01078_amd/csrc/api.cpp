@@ -343,17 +343,27 @@ static bool all_products_applies(int64_t m, int64_t k, const double* A, int64_t 
 // side in the one-level table) are formed once by a streaming pass into workspace slots, and
 // each outer product then runs the one-level all-products kernel on its staged (or single-term)
 // operands.  Every sum is rounded as in the unstaged kernel, so results are bitwise the same.
+// Per outer product (one_at_a_time): where the workspace cannot hold all ten sums, one slot per
+// side is refilled before each outer product that needs it (each sum formed once as before;
+// the pass reads the sum's two blocks instead of all four once per side: 15 block passes per
+// side instead of 9, for a fifth of the workspace).
 struct StagePlan {
   int na_slots = 0, nb_slots = 0;
   int slot_a[7], slot_b[7];
   int64_t ta_stride = 0, tb_stride = 0, total = 0;   // doubles
+  bool one_at_a_time = false;
 };
 
-static StagePlan make_stage_plan(const Plan& p) {
+static StagePlan make_stage_plan(const Plan& p, bool one_at_a_time = false) {
   StagePlan sp;
+  sp.one_at_a_time = one_at_a_time;
   for (int R = 0; R < 7; ++R) {
-    sp.slot_a[R] = kOneLevel[R].na == 2 ? sp.na_slots++ : -1;
-    sp.slot_b[R] = kOneLevel[R].nb == 2 ? sp.nb_slots++ : -1;
+    sp.slot_a[R] = kOneLevel[R].na == 2 ? (one_at_a_time ? 0 : sp.na_slots++) : -1;
+    sp.slot_b[R] = kOneLevel[R].nb == 2 ? (one_at_a_time ? 0 : sp.nb_slots++) : -1;
+  }
+  if (one_at_a_time) {
+    sp.na_slots = 1;
+    sp.nb_slots = 1;
   }
   sp.ta_stride = round_up(4 * p.mq * p.kq, 32);
   sp.tb_stride = round_up(4 * p.kq * p.nq, 32);
@@ -371,10 +381,11 @@ static bool staging_applies(int64_t m, int64_t n, int64_t k, int levels) {
 
 // The all-products launches of ABC: one at one level; at two, one per outer product of the
 // one-level table, in order.  `stage` (two levels only, may be null) holds the staged outer
-// sums as laid out by make_stage_plan.
+// sums as laid out by make_stage_plan(p, one_at_a_time).
 static int build_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
                               int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
-                              double beta, const double* stage, std::vector<ApLaunch>* out) {
+                              double beta, const double* stage, std::vector<ApLaunch>* out,
+                              bool one_at_a_time = false) {
   out->clear();
   FusedArgs f;
   std::memset(&f, 0, sizeof f);
@@ -409,7 +420,7 @@ static int build_all_products(const Plan& p, const double* A, int64_t lda, const
     if (kOneLevel[R].a[0].sign != 1 || kOneLevel[R].b[0].sign != 1)
       return fail(STRASSEN_ERR_UNSUPPORTED, "outer product %d: first term negative", R);
   StagePlan sp;
-  if (stage) sp = make_stage_plan(p);
+  if (stage) sp = make_stage_plan(p, one_at_a_time);
   bool touched[4] = {false, false, false, false};
   for (int R = 0; R < 7; ++R) {
     const QProduct& P = kOneLevel[R];
@@ -461,19 +472,22 @@ static int build_all_products(const Plan& p, const double* A, int64_t lda, const
 }
 
 // ABC through the all-products kernel; at two levels with `stage` (may be null) the outer
-// operand sums are first formed into it by two streaming launches.
+// operand sums are first formed into it by two streaming launches, or (one_at_a_time) each
+// outer product's sums just before its launch.
 static int run_all_products(const Plan& p, const double* A, int64_t lda, const double* B,
                             int64_t ldb, double* C, int64_t ldc, int64_t n, double alpha,
                             double beta, double* stage, hipStream_t stream,
-                            double* M = nullptr, int64_t ldm = 0, int64_t m_stride = 0) {
+                            double* M = nullptr, int64_t ldm = 0, int64_t m_stride = 0,
+                            bool one_at_a_time = false) {
   std::vector<ApLaunch> launches;
+  const bool staged = p.levels == 2 && stage;
   if (int rc = build_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta,
-                                  p.levels == 2 ? stage : nullptr, &launches))
+                                  staged ? stage : nullptr, &launches, one_at_a_time))
     return rc;
-  if (p.levels == 2 && stage) {
-    const StagePlan sp = make_stage_plan(p);
+  const StagePlan sp = make_stage_plan(p, one_at_a_time);
+  OuterSumArgs oa, ob;
+  if (staged) {
     const int64_t om = 2 * p.mq, on = 2 * p.nq, ok = 2 * p.kq;
-    OuterSumArgs oa, ob;
     std::memset(&oa, 0, sizeof oa);
     std::memset(&ob, 0, sizeof ob);
     oa.src = A;
@@ -492,10 +506,19 @@ static int run_all_products(const Plan& p, const double* A, int64_t lda, const d
       oa.blk[q] = (q >> 1) * om + (q & 1) * ok * lda;
       ob.blk[q] = (q >> 1) * ok + (q & 1) * on * ldb;
     }
-    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
-    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
+    if (!one_at_a_time) {
+      SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
+      SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
+    }
   }
   for (size_t i = 0; i < launches.size(); ++i) {
+    if (staged && one_at_a_time) {   // this outer product's sums into the two slots
+      oa.single = ob.single = (int32_t)i + 1;
+      if (sp.slot_a[i] >= 0)
+        SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
+      if (sp.slot_b[i] >= 0)
+        SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
+    }
     ApLaunch l = launches[i];
     if (M) {   // the AB form: launch i holds products 7i .. 7i + 6 of the table
       l.f.store_m = 1;
@@ -580,6 +603,7 @@ struct PadPlan {
   bool stage;                       // two-level staged outer sums on the padded problem
   bool ok;                          // the padded layout fits the kernel's 32-bit lane offsets
   int64_t a_off, b_off, c_off, s_off, total;   // workspace layout (doubles)
+  int64_t total_one;                // the same with one outer product's sums staged at a time
 };
 
 static PadPlan make_pad_plan(int64_t m, int64_t n, int64_t k, int levels, const double* A,
@@ -616,14 +640,19 @@ static PadPlan make_pad_plan(int64_t m, int64_t n, int64_t k, int levels, const 
   pp.b_off = take(pp.pb, pp.kp * pp.np);
   pp.c_off = take(pp.pc, pp.mp * pp.np);
   pp.s_off = off;
-  if (pp.stage) off += make_stage_plan(make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC)).total;
-  pp.total = off;
+  pp.total = pp.total_one = off;
+  if (pp.stage) {
+    const Plan sp = make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC);
+    pp.total = off + make_stage_plan(sp).total;
+    pp.total_one = off + make_stage_plan(sp, true).total;
+  }
   return pp;
 }
 
 static int run_padded(const PadPlan& pp, int levels, int64_t m, int64_t n, int64_t k,
                       double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                      double beta, double* C, int64_t ldc, double* ws, hipStream_t stream) {
+                      double beta, double* C, int64_t ldc, double* ws, hipStream_t stream,
+                      bool one_at_a_time = false) {
   auto copy = [&](const double* src, int64_t ld_s, int64_t rows, int64_t cols, int64_t rb,
                   int64_t rb_e, int64_t cb, int64_t cb_e, double* dst, int64_t ld_d,
                   int64_t dst_rows, int64_t dst_cols, int unpad) {
@@ -677,7 +706,8 @@ static int run_padded(const PadPlan& pp, int levels, int64_t m, int64_t n, int64
   } else {
     const Plan p = make_plan(pp.mp, pp.np, pp.kp, levels, STRASSEN_ABC);
     if (int rc = run_all_products(p, Ap, lda_p, Bp, ldb_p, Cp, ldc_p, pp.np, alpha, beta,
-                                  pp.stage ? ws + pp.s_off : nullptr, stream))
+                                  pp.stage ? ws + pp.s_off : nullptr, stream, nullptr, 0, 0,
+                                  one_at_a_time))
       return rc;
   }
   if (pp.pc)
@@ -1281,10 +1311,14 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
       }
     }
     PadPlan pp;
-    bool padded = false;
+    bool padded = false, pad_one = false;   // pad_one: staging one outer product at a time
     if (all_products && levels >= 1) {
       pp = make_pad_plan(m, n, k, levels, A, lda, B, ldb, C, ldc, forced);
-      padded = (pp.pa || pp.pb || pp.pc) && pp.ok && wsrc.fits((size_t)pp.total * sizeof(double));
+      const bool copies = (pp.pa || pp.pb || pp.pc) && pp.ok;
+      padded = copies && wsrc.fits((size_t)pp.total * sizeof(double));
+      if (copies && !padded && pp.stage && forced == -1 &&
+          wsrc.fits((size_t)pp.total_one * sizeof(double)))
+        padded = pad_one = true;
     }
     const bool in_place = all_products && all_products_applies(m, k, A, lda, B, ldb, C, ldc, levels);
     const bool tile_ok = tile_offsets_fit(lda, ldb, ldc, 0);
@@ -1293,10 +1327,11 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
     if (int rc = device_ready(&dev)) return rc;
     if (padded) {
       void* ws = nullptr;
-      const int rc = get_workspace(wsrc, dev, (size_t)pp.total * sizeof(double), &ws);
+      const int rc = get_workspace(wsrc, dev,
+                                   (size_t)(pad_one ? pp.total_one : pp.total) * sizeof(double), &ws);
       if (rc == 0)
         return run_padded(pp, levels, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                          static_cast<double*>(ws), stream);
+                          static_cast<double*>(ws), stream, pad_one);
       // the library-owned allocation failed: the workspace-free path below (same result)
       if (wsrc.fixed) return rc;
       if (!in_place && !tile_ok) return tile_offsets_error();
@@ -1307,9 +1342,15 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
       const bool want = levels == 2 && n % 4 == 0 &&
                         (forced == kCfgAllStaged ||
                          (forced == -1 && staging_applies(m, n, k, levels)));
+      bool one = false;
       if (want) {
-        const size_t bytes = (size_t)make_stage_plan(p).total * sizeof(double);
-        // a workspace too small for the staging buffers: form the sums in the load
+        size_t bytes = (size_t)make_stage_plan(p).total * sizeof(double);
+        // a workspace too small for all ten sums: one outer product's at a time; too small for
+        // those too: form the sums in the load
+        if (forced != kCfgAllStaged && !wsrc.fits(bytes)) {
+          one = true;
+          bytes = (size_t)make_stage_plan(p, true).total * sizeof(double);
+        }
         if (forced == kCfgAllStaged || wsrc.fits(bytes)) {
           void* ws = nullptr;
           if (int rc = get_workspace(wsrc, dev, bytes, &ws)) {
@@ -1320,7 +1361,8 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
           }
         }
       }
-      return run_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta, stage, stream);
+      return run_all_products(p, A, lda, B, ldb, C, ldc, n, alpha, beta, stage, stream, nullptr,
+                              0, 0, one);
     }
     const int cfg = pick_cfg(p, 1, maxt);
     g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));

@@ -128,13 +128,20 @@ __global__ __launch_bounds__(256) void outer_sum_kernel(const OuterSumArgs args)
   const int64_t i = (int64_t)(blockIdx.x % args.chunks_r) * kOuterSumRows + 2 * threadIdx.x;
   const int64_t j0 = (int64_t)(blockIdx.x / args.chunks_r) * kOuterSumCols;
   if (i >= args.rows) return;
+  // the blocks the requested sums read (all four, or the two terms of one product's sum)
+  int need = 15;
+  if (args.single > 0) {
+    const QProduct& P = kOneLevel[args.single - 1];
+    need = SIDE == 0 ? (1 << P.a[0].q) | (1 << P.a[1].q) : (1 << P.b[0].q) | (1 << P.b[1].q);
+  }
   d2_t x[4][kOuterSumCols];
 #pragma unroll
   for (int c = 0; c < kOuterSumCols; ++c) {
     if (j0 + c < args.cols) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        x[q][c] = *reinterpret_cast<const d2_t*>(args.src + args.blk[q] + i + (j0 + c) * args.ld);
+        if ((need >> q) & 1)
+          x[q][c] = *reinterpret_cast<const d2_t*>(args.src + args.blk[q] + i + (j0 + c) * args.ld);
     }
   }
   int slot = 0;
@@ -142,9 +149,10 @@ __global__ __launch_bounds__(256) void outer_sum_kernel(const OuterSumArgs args)
   for (int r = 0; r < 7; ++r) {
     const QProduct& P = kOneLevel[r];
     if ((SIDE == 0 ? P.na : P.nb) != 2) continue;
+    if (args.single > 0 && r != args.single - 1) continue;
     const QTerm t0 = SIDE == 0 ? P.a[0] : P.b[0], t1 = SIDE == 0 ? P.a[1] : P.b[1];
     const double s1 = t1.sign;
-    double* d = args.dst + slot * args.dst_stride + i;
+    double* d = args.dst + (args.single > 0 ? 0 : slot) * args.dst_stride + i;
 #pragma unroll
     for (int c = 0; c < kOuterSumCols; ++c) {
       if (j0 + c < args.cols) {

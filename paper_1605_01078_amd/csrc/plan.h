@@ -128,6 +128,8 @@ struct OuterSumArgs {
   int64_t ld, rows, cols, dst_stride;
   int64_t blk[4];
   int32_t chunks_r;     // row chunks per column group (set by the launcher)
+  int32_t single;       // 0: every two-term sum of the side, each into its slot; r + 1: only
+                        // the sum of outer product r, into slot 0 (only its two blocks read)
 };
 
 // Winograd's variant, staged outer level: the four chain sums of one side (S1..S4 of A, T1..T4

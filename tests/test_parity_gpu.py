@@ -208,6 +208,48 @@ def test_workspace_limit_abc_falls_back_ab_refuses(levels):
     assert np.array_equal(run(A, B, C, 0.5, -1.5, levels, "ab"), free)
 
 
+@pytest.mark.parametrize("shape,limits", [((4096, 4096, 4096), (100 << 20, 10 << 20)),
+                                          ((4095, 4100, 4090), (600 << 20, 300 << 20))])
+def test_staging_one_outer_product_at_a_time(shape, limits):
+    """Two-level ABC where staging applies (in place, and on block-padded copies): a workspace
+    cap that holds one outer product's sums but not all ten stages them product by product
+    (ten sum passes instead of two), a smaller one forms them in the load (none); every form
+    gives the same bits, and sampled columns match the oracle."""
+    m, n, k = shape
+    print(f"case staging one at a time {shape}", flush=True)
+    A, B, C = W.problem(14, m, n, k, "uniform")
+    dA, dB = sx.to_device(A), sx.to_device(B)
+
+    def passes():
+        for kind in sx.KERNEL_KINDS:
+            sx.timing_collect(kind)
+        sx.timing_enable(True)
+        try:
+            dC = sx.to_device(C)
+            sx.dgemm(dA, dB, dC, 0.5, -1.25, 2, "abc")
+            torch.cuda.synchronize()
+        finally:
+            sx.timing_enable(False)
+        return sx.to_host(dC), sx.timing_collect("outer_sums")[1]
+
+    full, n_full = passes()
+    assert n_full == 2
+    outs = []
+    try:
+        for limit, want in zip(limits, (10, 0)):
+            sx.set_workspace_limit(limit)
+            got, n_sums = passes()
+            assert n_sums == want, (limit, n_sums)
+            outs.append(got)
+    finally:
+        sx.set_workspace_limit(0)
+    for got in outs:
+        assert np.array_equal(got, full)
+    cols = np.array([0, 1, n // 2, n - 1])
+    ref = oracle_dgemm(A, np.asfortranarray(B[:, cols]), np.asfortranarray(C[:, cols]), 0.5, -1.25)
+    assert rel_fro(full[:, cols], ref) <= 1e-11
+
+
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("levels", [0, 1, 2])
 def test_every_tile_config_bitwise_and_exact(cfg, levels):
