@@ -10,6 +10,7 @@ Contents
   oracle_strassen(A, B, C, alpha, beta, L)  recursive textbook Strassen (Sec. 3.1-3.2)
   oracle_winograd(A, B, C, alpha, beta, L)  recursive Winograd variant (Strassen-like scheme)
   oracle_lu_nopiv(A)                        LU without pivoting, plain elimination
+  oracle_cholesky_lower(A)                  Cholesky A = L L^T, plain right-looking
   oracle_dgemm_dot2(...)                    compensated reference (error yardstick)
   tables                                    the paper's operation tables (Fig. one-level,
                                             Fig. two-level via the Kronecker rule)
@@ -51,6 +52,8 @@ def _load():
         lib.oracle_winograd.restype = ctypes.c_int
         lib.oracle_lu_nopiv.argtypes = [i64, ptr, i64]
         lib.oracle_lu_nopiv.restype = ctypes.c_int
+        lib.oracle_cholesky_lower.argtypes = [i64, ptr, i64]
+        lib.oracle_cholesky_lower.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -106,6 +109,16 @@ def oracle_lu_nopiv(A):
         raise ValueError("square matrix expected")
     pa, lda = _colmajor(A, "A")
     return _load().oracle_lu_nopiv(n, pa, lda)
+
+
+def oracle_cholesky_lower(A):
+    """A = L L^T in place, L in the lower triangle (the strict upper triangle is neither read
+    nor written); returns 0, or p + 1 if the pivot of column p was not positive."""
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("square matrix expected")
+    pa, lda = _colmajor(A, "A")
+    return _load().oracle_cholesky_lower(n, pa, lda)
 
 
 def fortran(X, ld=None):

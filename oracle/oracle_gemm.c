@@ -26,6 +26,7 @@
  *                      The base case is oracle_dgemm's summation.
  */
 #include <stdint.h>
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -286,6 +287,32 @@ int oracle_lu_nopiv(int64_t n, double *A, int64_t lda)
             double *col = A + j * lda;
             const double *l = A + p * lda;
             for (int64_t i = p + 1; i < n; ++i) col[i] = col[i] - l[i] * u;
+        }
+    }
+    return 0;
+}
+
+/* A = L L^T in place for the symmetric positive definite n x n matrix A
+ * (column-major, lda; only the lower triangle is read and written): the plain
+ * right-looking Cholesky factorization.  For each p: l_pp = sqrt(a_pp), the
+ * column below is divided by it (l_ip = a_ip / l_pp, i > p), then the
+ * trailing lower triangle is reduced, a_ij := a_ij - l_ip l_jp for i >= j > p.
+ * Returns p + 1 if a_pp is not positive (the leading minor of order p + 1 is
+ * not positive definite; A is then partly factored), else 0. */
+int oracle_cholesky_lower(int64_t n, double *A, int64_t lda)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        const double d = A[p + p * lda];
+        if (!(d > 0.0)) return (int)(p + 1);
+        const double l = sqrt(d);
+        A[p + p * lda] = l;
+        for (int64_t i = p + 1; i < n; ++i) A[i + p * lda] = A[i + p * lda] / l;
+#pragma omp parallel for schedule(static)
+        for (int64_t j = p + 1; j < n; ++j) {
+            const double ljp = A[j + p * lda];
+            double *col = A + j * lda;
+            const double *lp = A + p * lda;
+            for (int64_t i = j; i < n; ++i) col[i] = col[i] - lp[i] * ljp;
         }
     }
     return 0;
