@@ -67,7 +67,7 @@ def parse():
                    help="rounds of the round-robin member timing (median per member)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
-    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep", "levels", "lu"],
+    p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep", "levels", "lu", "cholesky"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
                         "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
                         "one persistent graph launch; selector: the committed network's choice "
@@ -566,6 +566,69 @@ def levels_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def cholesky_suite(args):
+    """Cholesky factorization (strassen_dpotrf_lower) of a symmetric positive definite n x n
+    matrix (default 16384; X X^T / n + I with X uniform[-1, 1]), block columns of 2048, trailing
+    updates with 0 (classical), 1, 2 and 3 levels of Strassen: round-robin event timing (median
+    of --reps), rate = n^3 / 3 / t, and the backward error ||A - L L^T|| / ||A|| on sampled
+    columns."""
+    import torch
+    import paper_1605_01078_amd as sx
+    from oracle import rel_fro
+    n, nb = args.n, 2048
+    stream = torch.cuda.current_stream()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    X = torch.empty((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=g)
+    A0 = torch.matmul(X, X.t()).div_(float(n))
+    A0.diagonal().add_(1.0)
+    del X
+    A = torch.empty_like(A0).t()   # column-major work matrix (A0 is symmetric: same values)
+    flops = n ** 3 / 3.0
+    runs = {f"nb{nb}_L{lev}": lev for lev in (0, 1, 2, 3)}
+    times = {key: [] for key in runs}
+
+    def one(lev):
+        A.t().copy_(A0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        info = sx.potrf_lower(A, nb, lev, stream)
+        e1.record(stream)
+        e1.synchronize()
+        if info != 0:
+            raise SystemExit(f"Cholesky reported info {info}")
+        return e0.elapsed_time(e1)
+    for lev in runs.values():
+        one(lev)
+    for _ in range(args.reps):
+        for key, lev in runs.items():
+            times[key].append(one(lev))
+    out_runs = {}
+    for key in runs:
+        ms = float(np.median(times[key]))
+        out_runs[key] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
+        log(f"  Cholesky n={n} {key}: {ms:8.3f} ms  {out_runs[key]['tflops']:6.2f} TF")
+    base = out_runs[f"nb{nb}_L0"]["ms"]
+    for lev in (1, 2, 3):
+        out_runs[f"nb{nb}_L{lev}"]["speedup_vs_classical_updates"] = round(base / out_runs[f"nb{nb}_L{lev}"]["ms"], 4)
+    best = min(out_runs, key=lambda key: out_runs[key]["ms"])
+    one(runs[best])
+    torch.cuda.synchronize()
+    cols = np.sort(np.random.default_rng(0).choice(n, size=4, replace=False))
+    L = np.tril(sx.to_host(A))
+    err = float(rel_fro(L @ L[cols, :].T, A0[:, torch.as_tensor(cols, device="cuda")].cpu().numpy()))
+    del L
+    out = {"metric": "Cholesky factorization rate (n^3 / 3 / t) with Strassen trailing updates",
+           "value": out_runs[best]["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"strassen_dpotrf_lower n={n}, X X^T / n + I with X "
+                                  f"uniform[-1,1], block columns {nb}, best {best}", "n": n},
+           "runs": out_runs,
+           "backward_error": {"value": err, "columns": cols.tolist(), "run": best}}
+    print(json.dumps(out), flush=True)
+
+
 def lu_suite(args):
     """LU factorization without pivoting (strassen_dgetrf_nopiv) of a diagonally dominant n x n
     matrix (default 16384; entries uniform[-1, 1] plus n on the diagonal), rank-nb updates with
@@ -680,6 +743,9 @@ def main():
         return
     if args.suite == "batched":
         batched_suite(args)
+        return
+    if args.suite == "cholesky":
+        cholesky_suite(args)
         return
     if args.suite == "selector":
         selector_suite(args)

@@ -176,6 +176,28 @@ int strassen_dgetrf_nopiv(int64_t n, double *A, int64_t lda, int64_t nb, int lev
                           void *stream);
 
 /*
+ * strassen_dpotrf_lower — Cholesky factorization A = L L^T of the symmetric positive definite
+ * n x n matrix A (column-major, device memory; only the lower triangle is read, and L overwrites
+ * it; the strict upper triangle is not touched), with Strassen in its trailing updates (the
+ * rank-k updates of LAPACK's blocked algorithms that the paper's future work, Sec. 6, points
+ * at).  Right-looking, block columns of nb (a positive multiple of 64): the diagonal block is
+ * factored recursively (64-column base kernel), L21 := A21 L11^{-T} by a recursive triangular
+ * solve, and the trailing lower triangle receives A22 -= L21 L21^T in block columns of at most
+ * 2048: below each diagonal block one GEMM through the library (levels: 0..3 for the updates
+ * with min(m, n) >= 2048 and k >= 1024, -1 = strassen_select per update; smaller ones
+ * classical), each diagonal block a product into a scratch block whose lower triangle is
+ * subtracted.  *info (host, may be NULL) receives 0, or j + 1 when the leading minor of order
+ * j + 1 is not positive definite (the first non-positive pivot; the factorization then
+ * continues with NaN).  Enqueued on `stream`; returns after it completes (reading info
+ * synchronises the stream).  Uses the library workspace (as strassen_gemm with a transposed
+ * operand) and a scratch block of 2048^2 doubles per device, kept until process exit.
+ * Returns 0, -1 n < 0, -2 A NULL, -3 lda < max(1, n), -4 nb not a positive multiple of 64,
+ * -5 levels not in -1..3, or a positive error.
+ */
+int strassen_dpotrf_lower(int64_t n, double *A, int64_t lda, int64_t nb, int levels,
+                          int64_t *info, void *stream);
+
+/*
  * strassen_gemm — the full dgemm interface of Sec. 2.2 with transposes:
  *   C := alpha * op(A) * op(B) + beta * C,   op(X) = X (trans 'N'/'n') or X^T ('T'/'t'/'C'/'c')
  * op(A) is m x k (A is m x k with lda >= max(1,m), or k x m with lda >= max(1,k) when

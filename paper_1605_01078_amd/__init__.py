@@ -54,6 +54,8 @@ def lib():
         L.strassen_workspace_size_winograd.restype = ci
         L.strassen_dgetrf_nopiv.argtypes = [i64, vp, i64, i64, ci, vp]
         L.strassen_dgetrf_nopiv.restype = ci
+        L.strassen_dpotrf_lower.argtypes = [i64, vp, i64, i64, ci, ctypes.POINTER(i64), vp]
+        L.strassen_dpotrf_lower.restype = ci
         L.strassen_dgemm_noalloc.argtypes = gemm + [vp]
         L.strassen_dgemm_noalloc.restype = ci
         L.strassen_gemm_ex.argtypes = gemm + [ci, ci, ci, vp]
@@ -252,6 +254,20 @@ def workspace_size_winograd(m, n, k, levels):
     out = ctypes.c_size_t(0)
     check(lib().strassen_workspace_size_winograd(m, n, k, levels, ctypes.byref(out)))
     return out.value
+
+
+def potrf_lower(A, nb=1024, levels=1, stream=None):
+    """Cholesky factorization A = L L^T in place (strassen_dpotrf_lower): L overwrites the lower
+    triangle of the square column-major device matrix A (the strict upper triangle is left as
+    it is).  Returns info: 0, or j + 1 if the leading minor of order j + 1 is not positive
+    definite."""
+    a, m, n, lda = _mat(A, "A")
+    if m != n:
+        raise ValueError("A must be square")
+    info = ctypes.c_int64(0)
+    check(lib().strassen_dpotrf_lower(n, a, lda, int(nb), int(levels), ctypes.byref(info),
+                                      _stream(stream)))
+    return info.value
 
 
 def getrf_nopiv(A, nb=1024, levels=1, stream=None):

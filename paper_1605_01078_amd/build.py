@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstrassen.so")
 BLAS_LIB = os.path.join(HERE, "libstrassen_blas.so")
 SOURCES = ["kernels_fp64.hip", "fused_fp64.hip", "classical_fp64.hip", "kernels_bf16.hip", "kernels_batched.hip", "kernels_mlp.hip",
-           "probe_rates.hip", "noalloc.hip", "kernels_lu.hip", "lu.cpp",
+           "probe_rates.hip", "noalloc.hip", "kernels_lu.hip", "lu.cpp", "cholesky.cpp",
            "tables.cpp", "api.cpp", "batched.cpp", "selector.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

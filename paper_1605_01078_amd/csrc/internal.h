@@ -55,6 +55,11 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
           int variant, const WsSource& ws, hipStream_t stream);
 
+// C := alpha*op(A)*op(B) + beta*C (strassen_gemm; op = N, T or C) with its workspace from `ws`.
+int gemm_t(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+           int64_t ldc, int levels, int variant, const WsSource& ws, hipStream_t stream);
+
 // One launch of the all-products kernel (operand terms per side: na, nb).
 struct ApLaunch {
   FusedArgs f;

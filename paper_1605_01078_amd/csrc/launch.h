@@ -62,6 +62,12 @@ hipError_t launch_scale(const ScaleArgs& a, hipStream_t s);
 hipError_t launch_transpose(const TransposeArgs& a, hipStream_t s);
 // LU base cases (kernels_lu.hip), w / k <= 64: in-place LU of a w x w block (one workgroup);
 // B := B U^{-1} (upper, one thread per row); B := L^{-1} B (unit lower, one thread per column).
+hipError_t launch_chol_base(double* P, int64_t ld, int w, int* info, int col0, hipStream_t s);
+hipError_t launch_sub_lower(double* C, int64_t ldc, const double* W, int64_t ldw, int64_t n,
+                            hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_trsm_rows_lower_t(const double* L, int64_t ldl, int w, double* B, int64_t ldb,
+                                    int64_t rows, hipStream_t s);
 hipError_t launch_lu_base(double* P, int64_t ld, int w, hipStream_t s);
 hipError_t launch_trsm_rows_upper(const double* U, int64_t ldu, int w, double* B, int64_t ldb,
                                   int64_t rows, hipStream_t s);

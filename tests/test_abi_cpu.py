@@ -319,3 +319,19 @@ def test_getrf_argument_codes():
     assert L.strassen_dgetrf_nopiv(4, fake, 4, 0, 0, None) == -4
     assert L.strassen_dgetrf_nopiv(4, fake, 4, 64, 4, None) == -5
     assert L.strassen_dgetrf_nopiv(0, None, 1, 64, 0, None) == 0
+
+
+def test_potrf_argument_errors():
+    """strassen_dpotrf_lower rejects bad arguments on the host (no device needed)."""
+    L = sx.lib()
+    info = ctypes.c_int64(-7)
+    buf = (ctypes.c_double * 64)()
+    assert L.strassen_dpotrf_lower(-1, buf, 8, 64, 0, ctypes.byref(info), None) == -1
+    assert L.strassen_dpotrf_lower(8, None, 8, 64, 0, ctypes.byref(info), None) == -2
+    assert L.strassen_dpotrf_lower(8, buf, 7, 64, 0, ctypes.byref(info), None) == -3
+    assert L.strassen_dpotrf_lower(8, buf, 8, 48, 0, ctypes.byref(info), None) == -4
+    assert L.strassen_dpotrf_lower(8, buf, 8, 0, 0, ctypes.byref(info), None) == -4
+    assert L.strassen_dpotrf_lower(8, buf, 8, 64, 4, ctypes.byref(info), None) == -5
+    assert L.strassen_dpotrf_lower(0, None, 1, 64, 0, ctypes.byref(info), None) == 0
+    assert info.value == 0
+    assert L.strassen_dpotrf_lower(0, None, 1, 64, 0, None, None) == 0
