@@ -65,47 +65,6 @@ __device__ __attribute__((always_inline)) inline void static_for(F&& f) {
   }
 }
 
-// In-place LU of the w x w block at P (w <= 64) by one wave, lane i holding row i in
-// registers: for each p the pivot row is published through LDS, lane i > p forms its
-// multiplier a_ip / a_pp and reduces a_ij (j > p) by it times a_pj.  One wave: the LDS
-// publications need no workgroup barrier, only the wave's own ordering.
-__global__ __launch_bounds__(64) void lu_base_kernel(double* P, int64_t ld, int w) {
-  __shared__ __attribute__((aligned(16))) double prow[kLuB];
-  const int lane = threadIdx.x;
-  const int ln = std::min(lane, w - 1);
-  double a[kLuB];
-#pragma unroll
-  for (int j = 0; j < kLuB; ++j) {
-    const double v = P[ln + (int64_t)std::min(j, w - 1) * ld];
-    a[j] = (lane < w && j < w) ? v : 0.0;
-  }
-  static_for<0, kLuB>([&](auto step) {
-    constexpr int p = decltype(step)::value;
-    if (p < w) {   // (uniform)
-      if (lane == p) {
-#pragma unroll
-        for (int j = p; j < kLuB; ++j) prow[j] = a[j];
-      }
-      __syncthreads();   // one wave: orders the row's publication before its reads
-      const double piv = prow[p];
-      if (lane > p) {
-        const double l = a[p] / piv;
-        a[p] = l;
-        stream_pairs<(p + 1) / 2>(prow, [&](int j, double upj) {
-          if (j > p) {
-            const double prod = l * upj;
-            a[j] = a[j] - prod;
-          }
-        });
-      }
-      __syncthreads();   // every lane has read the row before the next one is published
-    }
-  });
-#pragma unroll
-  for (int j = 0; j < kLuB; ++j)
-    if (lane < w && j < w) P[lane + (int64_t)j * ld] = a[j];
-}
-
 // 64-bit DPP broadcast of lane Q of each group of four lanes to the whole group.
 template <int Q>
 __device__ __attribute__((always_inline)) inline double quad_bcast(double v) {
@@ -114,6 +73,54 @@ __device__ __attribute__((always_inline)) inline double quad_bcast(double v) {
   const uint32_t lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, ctrl, 0xf, 0xf, false);
   const uint32_t hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), ctrl, 0xf, 0xf, false);
   return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+// In-place LU of the w x w block at P (w <= 64) by a workgroup of 256 threads, four lanes per
+// row: lane q of row i's group holds a_ij for the 16 columns j = q (mod 4) in registers.  For
+// each p the pivot row is published through LDS (two buffers, so one barrier per step), the lane
+// holding a_ip (i > p) forms the multiplier a_ip / a_pp, a DPP broadcast hands it to the group,
+// and each lane reduces its own a_ij (j > p) by it times a_pj: the operations of plain
+// elimination, in its order, for every entry.
+__global__ __launch_bounds__(256) void lu_base_kernel(double* P, int64_t ld, int w) {
+  constexpr int kPer = kLuB / 4;
+  __shared__ double prow[2][kLuB];
+  const int tid = threadIdx.x, row = tid >> 2, q = tid & 3;
+  const int rc = std::min(row, w - 1);
+  double a[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int j = 4 * k + q;
+    const double v = P[rc + (int64_t)std::min(j, w - 1) * ld];
+    a[k] = (row < w && j < w) ? v : 0.0;
+  }
+  static_for<0, kLuB>([&](auto step) {
+    constexpr int p = decltype(step)::value, q0 = p % 4, k0 = p / 4, b = p % 2;
+    if (p < w) {   // (uniform)
+      if (row == p) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) prow[b][4 * k + q] = a[k];
+      }
+      __syncthreads();   // the pivot row is published; the buffer of step p - 1 stays intact
+      const double l = quad_bcast<q0>(a[k0] / prow[b][p]);   // a_ip / a_pp, from lane q0
+      if (row > p) {
+        if (q == q0) a[k0] = l;
+        if (q > q0) {
+          const double prod = l * prow[b][4 * k0 + q];
+          a[k0] = a[k0] - prod;
+        }
+#pragma unroll
+        for (int k = k0 + 1; k < kPer; ++k) {
+          const double prod = l * prow[b][4 * k + q];
+          a[k] = a[k] - prod;
+        }
+      }
+    }
+  });
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int j = 4 * k + q;
+    if (row < w && j < w) P[row + (int64_t)j * ld] = a[k];
+  }
 }
 
 // X (rows x w) := X U^{-1} with U upper triangular w x w (w <= 64; unit: ones on the diagonal,
@@ -317,7 +324,7 @@ hipError_t launch_trsm_rows_lower_t(const double* L, int64_t ldl, int w, double*
 
 hipError_t launch_lu_base(double* P, int64_t ld, int w, hipStream_t s) {
   if (w < 1 || w > kLuB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lu_base_kernel, dim3(1), dim3(64), 0, s, P, ld, w);
+  hipLaunchKernelGGL(lu_base_kernel, dim3(1), dim3(256), 0, s, P, ld, w);
   return hipGetLastError();
 }
 
