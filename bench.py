@@ -67,6 +67,10 @@ def parse():
                    help="rounds of the round-robin member timing (median per member)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain copy kernel of known size first (for HBM counter scaling)")
+    p.add_argument("--factor-runs", default=None,
+                   help="lu / cholesky suites: comma-separated runs to time (e.g. nb2048_L1) "
+                        "instead of all of them; the LU suite then skips its separate timing "
+                        "of the rank-nb updates")
     p.add_argument("--suite", default="headline", choices=["headline", "precision", "batched", "selector", "sweep", "levels", "lu", "cholesky"],
                    help="headline: the FP64 step above; precision: the reduced-precision mode "
                         "table (m=n=k=--n, default 8192 for this suite); batched: 512 GEMMs in "
@@ -566,6 +570,17 @@ def levels_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def pick_runs(args, runs):
+    """The factorization runs --factor-runs names (all of them without the option)."""
+    if not args.factor_runs:
+        return runs
+    want = [key.strip() for key in args.factor_runs.split(",") if key.strip()]
+    bad = [key for key in want if key not in runs]
+    if bad or not want:
+        raise SystemExit(f"--factor-runs: unknown run(s) {bad}; known: {sorted(runs)}")
+    return {key: runs[key] for key in want}
+
+
 def cholesky_suite(args):
     """Cholesky factorization (strassen_dpotrf_lower) of a symmetric positive definite n x n
     matrix (default 16384; X X^T / n + I with X uniform[-1, 1]), block columns of 2048, trailing
@@ -585,7 +600,7 @@ def cholesky_suite(args):
     del X
     A = torch.empty_like(A0).t()   # column-major work matrix (A0 is symmetric: same values)
     flops = n ** 3 / 3.0
-    runs = {f"nb{nb}_L{lev}": lev for lev in (0, 1, 2, 3)}
+    runs = pick_runs(args, {f"nb{nb}_L{lev}": lev for lev in (0, 1, 2, 3)})
     times = {key: [] for key in runs}
 
     def one(lev):
@@ -609,9 +624,11 @@ def cholesky_suite(args):
         ms = float(np.median(times[key]))
         out_runs[key] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
         log(f"  Cholesky n={n} {key}: {ms:8.3f} ms  {out_runs[key]['tflops']:6.2f} TF")
-    base = out_runs[f"nb{nb}_L0"]["ms"]
-    for lev in (1, 2, 3):
-        out_runs[f"nb{nb}_L{lev}"]["speedup_vs_classical_updates"] = round(base / out_runs[f"nb{nb}_L{lev}"]["ms"], 4)
+    if f"nb{nb}_L0" in out_runs:
+        base = out_runs[f"nb{nb}_L0"]["ms"]
+        for lev in (1, 2, 3):
+            if f"nb{nb}_L{lev}" in out_runs:
+                out_runs[f"nb{nb}_L{lev}"]["speedup_vs_classical_updates"] = round(base / out_runs[f"nb{nb}_L{lev}"]["ms"], 4)
     best = min(out_runs, key=lambda key: out_runs[key]["ms"])
     one(runs[best])
     torch.cuda.synchronize()
@@ -647,7 +664,7 @@ def lu_suite(args):
     A0 = A0.t()
     A = torch.empty_like(A0.t()).t()   # column-major work copy
     flops = 2.0 / 3.0 * n ** 3
-    runs = {f"nb{nb}_L{lev}": (nb, lev) for nb in (2048, 4096) for lev in (0, 1, 2, 3)}
+    runs = pick_runs(args, {f"nb{nb}_L{lev}": (nb, lev) for nb in (2048, 4096) for lev in (0, 1, 2, 3)})
     times = {key: [] for key in runs}
 
     def one(nb, lev):
@@ -670,13 +687,16 @@ def lu_suite(args):
         out_runs[key] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) * 1e-12, 2)}
         log(f"  LU n={n} {key}: {ms:8.3f} ms  {out_runs[key]['tflops']:6.2f} TF")
     for nb in (2048, 4096):
+        if f"nb{nb}_L0" not in out_runs:
+            continue
         base = out_runs[f"nb{nb}_L0"]["ms"]
         for lev in (1, 2, 3):
-            out_runs[f"nb{nb}_L{lev}"]["speedup_vs_classical_updates"] = round(base / out_runs[f"nb{nb}_L{lev}"]["ms"], 4)
+            if f"nb{nb}_L{lev}" in out_runs:
+                out_runs[f"nb{nb}_L{lev}"]["speedup_vs_classical_updates"] = round(base / out_runs[f"nb{nb}_L{lev}"]["ms"], 4)
     # the rank-nb updates of the blocked loop on their own: C (r x r) -= A (r x nb) B (nb x r)
     # for r = n - nb, n - 2 nb, ..., timed one by one (event pairs) and summed
     updates = {}
-    for nb in (2048, 4096):
+    for nb in (() if args.factor_runs else (2048, 4096)):
         shapes = [n - j - nb for j in range(0, n - nb, nb)]
         for lev in (0, 1, 2, 3):
             tot = []
