@@ -47,6 +47,23 @@ def test_integer_factors_exact(n, nb, levels):
     assert np.array_equal(np.triu(F), U0)
 
 
+@pytest.mark.parametrize("levels", [3, -1])
+def test_integer_factors_exact_with_strassen_inside_the_panel(levels):
+    # n = 8192, nb = 4096: the second block column's panel holds a 2048 x 2048 x 2048 update,
+    # large enough for Strassen (three levels, or the selector's choice); A = L0 U0 is formed on
+    # the GPU (integers below 2^15: exact in any order)
+    n, nb = 8192, 4096
+    print(f"case lu integer panel-strassen n={n} nb={nb} L={levels}", flush=True)
+    L0, U0 = integer_factors(n + 5, n)
+    dA = torch.matmul(torch.as_tensor(L0, device="cuda"), torch.as_tensor(U0, device="cuda"))
+    dA = dA.t().contiguous().t()   # column-major
+    sx.getrf_nopiv(dA, nb, levels)
+    torch.cuda.synchronize()
+    F = sx.to_host(dA)
+    assert np.array_equal(np.tril(F, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(F), U0)
+
+
 @pytest.mark.parametrize("n,nb,levels,ld", [(2048, 512, 0, None), (2048, 2048, 1, None),
                                             (3001, 1024, 2, 3010), (777, 64, 0, 780)])
 def test_diagonally_dominant_against_oracle(n, nb, levels, ld):
