@@ -1713,6 +1713,48 @@ static bool trans_code(char t, bool* out) {
   return true;
 }
 
+// C := alpha*A*B^T + beta*C (levels 0) on the general tile kernel reading B^T in place: where
+// the classical product runs on that kernel anyway (problems too small for the classical
+// kernel's 256 x 128 tiles), this saves the packing launch and gives the same bits.
+static int run_tile_tb(int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                       int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, hipStream_t stream) {
+  if (!tile_offsets_fit(lda, ldb, ldc, 0)) return tile_offsets_error();
+  const Plan p = make_plan(m, n, k, 0, STRASSEN_ABC);
+  GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.mq = p.mq;
+  g.nq = p.nq;
+  g.kq = p.kq;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.tab = p.tab;
+  g.tb = 1;
+  const int maxt = table_maxt(*p.td);
+  // 16-byte loads: A row pairs (m even), B^T column pairs (n even)
+  const bool vec = aligned16(A) && aligned16(B) && lda % 2 == 0 && ldb % 2 == 0 && m % 2 == 0 &&
+                   n % 2 == 0;
+  int dev = 0;
+  if (int rc = device_ready(&dev)) return rc;
+  const int cfg = pick_cfg(p, 1, maxt);
+  g.tiles_m = (int32_t)cdiv(p.mq, cfg_bm(cfg));
+  g.tiles_n = (int32_t)cdiv(p.nq, cfg_bn(cfg));
+  const int64_t grid = (int64_t)g.tiles_m * g.tiles_n;
+  if (grid >= (int64_t(1) << 30)) return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
+  g.mode = kModeABC;
+  SMX_LAUNCH(STRASSEN_KERNEL_TILE, stream, launch_fp64_tile(g, cfg, maxt, vec, (int)grid, stream));
+  return 0;
+}
+
 int gemm_t(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
            int64_t ldc, int levels, int variant, const WsSource& wsrc, hipStream_t stream) {
@@ -1745,6 +1787,8 @@ int gemm_t(char transa, char transb, int64_t m, int64_t n, int64_t k, double alp
     return dgemm(m, n, k, alpha, ta ? nullptr : A, la, tb ? nullptr : B, lb, beta, C, ldc,
                  levels, variant, wsrc, stream);
   }
+  if (!ta && levels == 0 && !classical_size(m, n) && g_forced_cfg.load() < kCfgAll)
+    return run_tile_tb(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream);
   // packed operands: op(A) as m x k with ld round_up(m, 2), op(B) as k x n with ld round_up(k, 2)
   const int64_t lda_p = round_up(m, 2), ldb_p = round_up(k, 2);
   const int64_t a_elems = ta ? round_up(lda_p * k, 32) : 0;

@@ -22,9 +22,9 @@ __constant__ TableDev g_tables[kNumTables];
 // workgroups ever update the same C element, so no atomics and a fixed update order); StoreM
 // mode computes one (product, tile) pair per workgroup and writes M_r to its temporary.
 // ---------------------------------------------------------------------------------------------
-template <int BM, int BN, int BK, int MAXT, bool VEC, int WPE, int MODE>
+template <int BM, int BN, int BK, int MAXT, bool VEC, int WPE, int MODE, bool TB = false>
 __global__ __launch_bounds__(256, WPE) void fp64_tile_kernel(const GemmArgs args) {
-  using Tile = Fp64Tile<BM, BN, BK, MAXT, VEC>;
+  using Tile = Fp64Tile<BM, BN, BK, MAXT, VEC, TB>;
   __shared__ double lds[Tile::LDS_DOUBLES];
   const TableDev& tab = g_tables[args.tab];
   const int T = args.tiles_m * args.tiles_n;
@@ -219,6 +219,13 @@ hipError_t upload_tables(const TableDev* tabs) {
 template <int BM, int BN, int BK, int WPE, int MODE>
 static void launch_mode(const GemmArgs& a, int maxt, bool vec, dim3 g, hipStream_t s) {
   const dim3 b(256);
+  if constexpr (MODE == kModeABC) {
+    if (a.tb) {   // B given transposed: one-term products (host-checked)
+      if (vec) hipLaunchKernelGGL((fp64_tile_kernel<BM, BN, BK, 1, true, WPE, MODE, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((fp64_tile_kernel<BM, BN, BK, 1, false, WPE, MODE, true>), g, b, 0, s, a);
+      return;
+    }
+  }
   if (vec) {
     if (maxt == 1) hipLaunchKernelGGL((fp64_tile_kernel<BM, BN, BK, 1, true, WPE, MODE>), g, b, 0, s, a);
     else if (maxt == 2) hipLaunchKernelGGL((fp64_tile_kernel<BM, BN, BK, 2, true, WPE, MODE>), g, b, 0, s, a);

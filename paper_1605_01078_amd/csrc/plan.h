@@ -64,6 +64,8 @@ struct GemmArgs {
   int32_t mode;         // kModeABC: a workgroup owns one tile position in every C sub-block and
                         //           runs every product; kModeStoreM: one (product, tile) each
   int32_t prod_begin;   // StoreM: first product of this launch
+  int32_t tb;           // B given transposed: op(B)(p, j) at B[j + p * ldb] (ABC, one-term
+                        // products only)
 };
 
 // Arguments of the all-products kernel: one launch computes the seven products of the one-level

@@ -104,7 +104,10 @@ __device__ __forceinline__ void tile_coords(int t, int tiles_m, int tiles_n, int
   tj = w / gsize;
 }
 
-template <int BM, int BN, int BK, int MAXT, bool VEC>
+// TB: B is given transposed (op(B) = B^T, element (p, j) of op(B) at B[j + p * ldb]); the tile
+// of op(B) is then loaded along its columns (contiguous in memory) and written to the same LDS
+// layout, so the product is bitwise that of a packed transposed copy.
+template <int BM, int BN, int BK, int MAXT, bool VEC, bool TB = false>
 struct Fp64Tile {
   static constexpr int NT = 256;
   static constexpr int A_TPC = BM / 2;       // threads per A tile column (2 rows each)
@@ -113,6 +116,9 @@ struct Fp64Tile {
   static constexpr int B_TPC = BK / 2;       // threads per B tile column (2 k each)
   static constexpr int B_CPP = NT / B_TPC;
   static constexpr int B_PASSES = BN / B_CPP;
+  static constexpr int BT_TPR = BN / 2;      // TB: threads per k row of the B tile (2 columns each)
+  static constexpr int BT_RPP = NT / BT_TPR; // TB: k rows per load pass
+  static constexpr int BT_PASSES = TB ? BK / BT_RPP : 1;
   static constexpr int LDA_S = BM;
   static constexpr int LDB_S = BN + 1;
   static constexpr int WM = BM / 2, WN = BN / 2;
@@ -122,6 +128,7 @@ struct Fp64Tile {
   static_assert(A_PASSES >= 1 && B_PASSES >= 1 && BK % 8 == 0 && A_CPP * A_PASSES == BK &&
                     B_CPP * B_PASSES == BN,
                 "tile shape");
+  static_assert(!TB || (BT_RPP >= 1 && BK % BT_RPP == 0 && MAXT == 1), "tile shape (transposed B)");
 
   typedef d4_t Acc[FM][FN];
 
@@ -156,6 +163,7 @@ struct Fp64Tile {
     const int wm = wave & 1, wn = wave >> 1;
     const int a_row = 2 * (tid % A_TPC), a_col = tid / A_TPC;
     const int b_k = 2 * (tid % B_TPC), b_col = tid / B_TPC;
+    const int bt_j = 2 * (tid % BT_TPR), bt_k = tid / BT_TPR;   // TB
 
     // ---- per-term (wave-uniform) setup: base pointer of the tile, valid extents, sign ----
     const double* a_base[NA];
@@ -192,12 +200,13 @@ struct Fp64Tile {
       } else {
         const uint8_t c = pd.b[s];
         const int64_t bp = code_row(c), bj = code_col(c);
-        b_base[s] = args.B + bp * args.kq + bj * args.nq * args.ldb;
+        b_base[s] = TB ? args.B + bj * args.nq + bp * args.kq * args.ldb
+                       : args.B + bp * args.kq + bj * args.nq * args.ldb;
         b_cv[s] = (int)min64(BN, min64(args.nq, args.n - bj * args.nq) - col0);
         b_klim[s] = min64(args.kq, args.k - bp * args.kq);
         b_sg[s] = code_neg(c) ? -1.0 : 1.0;
       }
-      b_base[s] += col0 * ldb_e;
+      b_base[s] += TB ? col0 : col0 * ldb_e;
     }
     const int nk = (int)((args.kq + BK - 1) / BK);
 
@@ -209,8 +218,12 @@ struct Fp64Tile {
 #pragma unroll
     for (int p = 0; p < B_PASSES; ++p)
       ob[p] = (uint32_t)(8 * (b_k + (int64_t)(b_col + p * B_CPP) * ldb_e));
+    uint32_t obt[BT_PASSES];
+#pragma unroll
+    for (int p = 0; p < BT_PASSES; ++p)
+      obt[p] = (uint32_t)(8 * (bt_j + (int64_t)(bt_k + p * BT_RPP) * args.ldb));
 
-    d2_t ra[NA][A_PASSES], rb[NB][B_PASSES];
+    d2_t ra[NA][A_PASSES], rb[NB][TB ? BT_PASSES : B_PASSES];
 
     // Global loads of k step kt for every term.  Buffer loads: an out-of-range position (fringe
     // of the matrix or of its sub-block, or a k step past the end) gets an offset past the
@@ -237,6 +250,25 @@ struct Fp64Tile {
     };
     auto load_b = [&](int kt) {
       const int64_t kb = (int64_t)kt * BK;
+      if constexpr (TB) {   // column pairs (j, j + 1) of one k row: contiguous in memory
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+          const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb * args.ldb);
+          const int kv = (int)min64(BK, b_klim[s] - kb);
+          const bool c0 = bt_j < b_cv[s], c1 = bt_j + 1 < b_cv[s];
+#pragma unroll
+          for (int p = 0; p < BT_PASSES; ++p) {
+            const bool kok = bt_k + p * BT_RPP < kv;
+            if (VEC) {
+              rb[s][p] = load2(rs, (kok && c0) ? obt[p] : kOOB);
+            } else {
+              rb[s][p] = (d2_t){load1(rs, (kok && c0) ? obt[p] : kOOB),
+                                load1(rs, (kok && c1) ? obt[p] + 8 : kOOB)};
+            }
+          }
+        }
+        return;
+      }
 #pragma unroll
       for (int s = 0; s < NB; ++s) {
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(b_base[s] + kb);
@@ -276,6 +308,22 @@ struct Fp64Tile {
       }
     };
     auto store_b = [&](int buf) {
+      if constexpr (TB) {
+#pragma unroll
+        for (int p = 0; p < BT_PASSES; ++p) {
+          double xs[NB], ys[NB];
+#pragma unroll
+          for (int s = 0; s < NB; ++s) {
+            xs[s] = rb[s][p].x;
+            ys[s] = rb[s][p].y;
+          }
+          const double v0 = signed_sum<NB>(b_sg, xs), v1 = signed_sum<NB>(b_sg, ys);
+          double* row = &Bs[buf * B_STAGE + (bt_k + p * BT_RPP) * LDB_S + bt_j];
+          row[0] = v0;
+          row[1] = v1;
+        }
+        return;
+      }
 #pragma unroll
       for (int p = 0; p < B_PASSES; ++p) {
         double xs[NB], ys[NB];

@@ -59,6 +59,32 @@ def test_gemm_transposes_bitwise_with_dgemm(ta, tb, levels):
     assert err <= (1e-11 if levels == 2 else 1e-12)
 
 
+@pytest.mark.parametrize("m,n,k,ldb_extra,shift", [(64, 64, 64, 0, 0), (130, 66, 17, 0, 0),
+                                                   (255, 129, 300, 1, 0), (1, 1, 1, 0, 0),
+                                                   (512, 300, 1000, 0, 1), (700, 1000, 64, 3, 1)])
+def test_transposed_b_read_in_place_by_the_tile_kernel(m, n, k, ldb_extra, shift):
+    # classical products too small for the classical kernel read op(B) = B^T in place on the
+    # tile kernel (16-byte pairs where n, ldb and B's alignment allow, else element by element,
+    # shift = 1: B one element past a 16-byte boundary); the same bits as the product on an
+    # explicit transposed copy, exact on integers
+    print(f"case gemm NT in place {m}x{n}x{k} ldb+{ldb_extra} shift {shift}", flush=True)
+    for kind in ("integer", "uniform"):
+        A, B, C = W.problem(103, m, n, k, kind)
+        Bt = np.asfortranarray(B.T)
+        buf = torch.zeros(((n + ldb_extra) * k + 2,), dtype=torch.float64, device="cuda")
+        dBt = buf[shift:shift + (n + ldb_extra) * k].view(k, n + ldb_extra).t()[:n, :]
+        dBt.copy_(torch.as_tensor(Bt, device="cuda"))
+        dC = sx.to_device(C)
+        sx.gemm(sx.to_device(A), dBt, dC, 0.75, -1.25, "N", "T", 0, "abc")
+        ref_c = sx.to_device(C)
+        sx.dgemm(sx.to_device(A), sx.to_device(B), ref_c, 0.75, -1.25, 0, "abc")
+        torch.cuda.synchronize()
+        got = sx.to_host(dC)
+        assert np.array_equal(got, sx.to_host(ref_c))
+        if kind == "integer":
+            assert np.array_equal(got, oracle_dgemm(A, B, C.copy(order="F"), 0.75, -1.25))
+
+
 def test_gemm_member_chosen_by_library():
     m, n, k = 2048, 2048, 2048
     print("case gemm levels=-1", flush=True)
