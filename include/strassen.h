@@ -207,9 +207,12 @@ int strassen_dpotrf_lower(int64_t n, double *A, int64_t lda, int64_t nb, int lev
  * into workspace first (a tiled copy, the counterpart of BLIS's packing of a transposed block;
  * round_up(m, 2) * k or round_up(k, 2) * n doubles, each rounded up to 32), and the member then
  * runs on the packed operands with the remaining workspace; untransposed calls are exactly
- * strassen_dgemm.  The packed operands need workspace even for ABC: STRASSEN_ERR_ALLOC when the
- * caller workspace or the workspace limit cannot hold them.  The result is bitwise that of
- * strassen_dgemm on the explicitly transposed matrices.
+ * strassen_dgemm.  One exception packs nothing: A untransposed, B transposed, levels 0 and a
+ * problem below the classical kernel's size (fewer than 256 of its 256 x 128 tiles) — the
+ * general tile kernel then reads B^T in place (no workspace).  Otherwise the packed operands need
+ * workspace even for ABC: STRASSEN_ERR_ALLOC when the caller workspace or the workspace limit
+ * cannot hold them.  The result is bitwise that of strassen_dgemm on the explicitly transposed
+ * matrices.
  * Argument positions for -i: transa=1 transb=2 m=3 n=4 k=5 alpha=6 A=7 lda=8 B=9 ldb=10
  * beta=11 C=12 ldc=13 levels=14 variant=15.
  */
