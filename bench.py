@@ -872,7 +872,10 @@ def main():
         # (the staged form once more under a workspace cap that holds one outer product's two
         # sum slots, m/2 x k/2 and k/2 x n/2 doubles, but not all ten: one product at a time)
         one_slots = 8 * 2 * (n // 2) * (n // 2)
-        members = {"L0_abc": (0, "abc", -1), "L1_abc": (1, "abc", -1), "L1_ab": (1, "ab", -1),
+        # one level: the default stages the five sums per side and runs the products on the
+        # classical kernel; configuration 4 forces the workspace-free all-products form
+        members = {"L0_abc": (0, "abc", -1), "L1_abc": (1, "abc", -1),
+                   "L1_abc_all_products": (1, "abc", 4), "L1_ab": (1, "ab", -1),
                    "L1_naive": (1, "naive", -1), "L2_abc": (2, "abc", 4),
                    "L2_abc_staged": (2, "abc", -1),
                    "L2_abc_staged_one_at_a_time": (2, "abc", -1, one_slots + (1 << 20)),
@@ -925,8 +928,10 @@ def main():
                 vendor = entry
             else:
                 variants[key] = entry
-                if key.startswith("L2_abc"):   # the workspace each two-level ABC form used
-                    entry["workspace_bytes"] = {"L2_abc": 0, "L2_abc_staged": sx.workspace_size(n, n, n, 2, "abc"),
+                if key.startswith("L2_abc") or key.startswith("L1_abc"):   # workspace each ABC form used
+                    entry["workspace_bytes"] = {"L1_abc": sx.workspace_size(n, n, n, 1, "abc"),
+                                                "L1_abc_all_products": 0, "L2_abc": 0,
+                                                "L2_abc_staged": sx.workspace_size(n, n, n, 2, "abc"),
                                                 "L2_abc_staged_one_at_a_time": one_slots}[key]
             log(f"  {key:16s}: {ms:8.3f} ms  {entry['tflops']:6.2f} TF  x{entry['speedup_vs_classical']:.3f}")
         del Cv, Ac, Bc

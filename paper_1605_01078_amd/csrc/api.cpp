@@ -354,7 +354,9 @@ struct StagePlan {
   bool one_at_a_time = false;
 };
 
-static StagePlan make_stage_plan(const Plan& p, bool one_at_a_time = false) {
+// blocks: sub-blocks per staged block along each side's extent product (4 for the outer
+// blocks of two levels, 2 x 2 inner sub-blocks; 1 for the quadrants of one level).
+static StagePlan make_stage_plan(const Plan& p, bool one_at_a_time = false, int64_t blocks = 4) {
   StagePlan sp;
   sp.one_at_a_time = one_at_a_time;
   for (int R = 0; R < 7; ++R) {
@@ -365,8 +367,8 @@ static StagePlan make_stage_plan(const Plan& p, bool one_at_a_time = false) {
     sp.na_slots = 1;
     sp.nb_slots = 1;
   }
-  sp.ta_stride = round_up(4 * p.mq * p.kq, 32);
-  sp.tb_stride = round_up(4 * p.kq * p.nq, 32);
+  sp.ta_stride = round_up(blocks * p.mq * p.kq, 32);
+  sp.tb_stride = round_up(blocks * p.kq * p.nq, 32);
   sp.total = sp.na_slots * sp.ta_stride + sp.nb_slots * sp.tb_stride;
   return sp;
 }
@@ -568,6 +570,89 @@ static int run_classical(int64_t m, int64_t n, int64_t k, double alpha, const do
   if ((int64_t)c.tiles_m * c.tiles_n >= (int64_t(1) << 30))
     return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
   SMX_LAUNCH(STRASSEN_KERNEL_CLASSICAL, stream, launch_classical(c, stream));
+  return 0;
+}
+
+// One-level ABC on the classical kernel: the operand sums of the one-level table staged in
+// workspace (the outer-sum kernel over the four quadrants), then one classical launch per
+// product in product order, each adding its product to its one or two C quadrants (beta at a
+// quadrant's first update).  Every C element receives the operations of the all-products
+// kernel (same sums, same MFMA k order, the same updates in product order): the same bits.  It
+// applies where the quadrants are exact halves the classical kernel takes as they are (m and k
+// multiples of 4, n even, its layout) and each product fills the GPU with its 256 x 128 tiles.
+static bool staged_classical_applies(int64_t m, int64_t n, int64_t k, const double* A,
+                                     int64_t lda, const double* B, int64_t ldb, const double* C,
+                                     int64_t ldc) {
+  return m % 4 == 0 && k % 4 == 0 && n % 2 == 0 && classical_size(m / 2, n / 2) &&
+         classical_layout(m / 2, k / 2, A, lda, B, ldb, C, ldc);
+}
+
+static int run_staged_classical(const Plan& p, const double* A, int64_t lda, const double* B,
+                                int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                                double* stage, bool one_at_a_time, hipStream_t stream) {
+  const int64_t om = p.mq, on = p.nq, okk = p.kq;   // the quadrants
+  const StagePlan sp = make_stage_plan(p, one_at_a_time, 1);
+  OuterSumArgs oa, ob;
+  std::memset(&oa, 0, sizeof oa);
+  std::memset(&ob, 0, sizeof ob);
+  oa.src = A;
+  oa.dst = stage;
+  oa.ld = lda;
+  oa.rows = om;
+  oa.cols = okk;
+  oa.dst_stride = sp.ta_stride;
+  ob.src = B;
+  ob.dst = stage + sp.na_slots * sp.ta_stride;
+  ob.ld = ldb;
+  ob.rows = okk;
+  ob.cols = on;
+  ob.dst_stride = sp.tb_stride;
+  for (int q = 0; q < 4; ++q) {
+    oa.blk[q] = (q >> 1) * om + (q & 1) * okk * lda;
+    ob.blk[q] = (q >> 1) * okk + (q & 1) * on * ldb;
+  }
+  if (!one_at_a_time) {
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
+    SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
+  }
+  bool touched[4] = {false, false, false, false};
+  for (int r = 0; r < 7; ++r) {
+    const QProduct& P = kOneLevel[r];
+    if (one_at_a_time) {   // this product's sums into the two slots
+      oa.single = ob.single = r + 1;
+      if (P.na == 2) SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(oa, 0, stream));
+      if (P.nb == 2) SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_outer_sums(ob, 1, stream));
+    }
+    ClassicalArgs c;
+    std::memset(&c, 0, sizeof c);
+    // a one-term side is its quadrant (first terms have sign +1)
+    c.A = P.na == 2 ? oa.dst + (int64_t)sp.slot_a[r] * sp.ta_stride : A + oa.blk[P.a[0].q];
+    c.lda = P.na == 2 ? om : lda;
+    c.B = P.nb == 2 ? ob.dst + (int64_t)sp.slot_b[r] * sp.tb_stride : B + ob.blk[P.b[0].q];
+    c.ldb = P.nb == 2 ? okk : ldb;
+    double* dst[2] = {nullptr, nullptr};
+    double ag[2] = {0.0, 0.0};
+    for (int d = 0; d < P.nc; ++d) {
+      const int q = P.c[d].q;
+      dst[d] = C + (q >> 1) * om + (q & 1) * on * ldc;
+      ag[d] = P.c[d].sign > 0 ? alpha : -alpha;
+      if (touched[q]) c.not_first |= 1 << d;
+      touched[q] = true;
+    }
+    c.C = dst[0];
+    c.alpha = ag[0];
+    c.C2 = dst[1];
+    c.alpha2 = ag[1];
+    c.extra = P.nc - 1;
+    c.beta = beta;
+    c.ldc = ldc;
+    c.m = om;
+    c.n = on;
+    c.k = okk;
+    c.tiles_m = (int32_t)cdiv(om, 256);
+    c.tiles_n = (int32_t)cdiv(on, 128);
+    SMX_LAUNCH(STRASSEN_KERNEL_CLASSICAL, stream, launch_classical(c, stream));
+  }
   return 0;
 }
 
@@ -1258,7 +1343,10 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
   if (levels == 3) return dgemm_l3(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, wsrc, stream);
   const Plan p = make_plan(m, n, k, levels, variant);
   const int64_t tiles_limit = 1ll << 30;
-  const int forced = g_forced_cfg.load(std::memory_order_relaxed);
+  // configuration 6 forces the staged one-level route and is the default otherwise
+  const int forced_cfg = g_forced_cfg.load(std::memory_order_relaxed);
+  const bool force_staged_classical = forced_cfg == kCfgClassicalStaged;
+  const int forced = force_staged_classical ? -1 : forced_cfg;
 
   GemmArgs g;
   std::memset(&g, 0, sizeof g);
@@ -1308,6 +1396,27 @@ int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_
                             static_cast<double*>(ws), stream);
         if (wsrc.fixed) return rc;
         g_last_error.clear();   // the library-owned allocation failed: the tile kernel
+      }
+    }
+    // one level: the sums staged and the products on the classical kernel where that applies
+    // and the workspace holds the ten sums (else one product's two at a time); without the
+    // workspace, the all-products kernel below (the same bits)
+    if (levels == 1 && forced == -1 && staged_classical_applies(m, n, k, A, lda, B, ldb, C, ldc)) {
+      const size_t all = (size_t)make_stage_plan(p, false, 1).total * sizeof(double);
+      const size_t one = (size_t)make_stage_plan(p, true, 1).total * sizeof(double);
+      const bool use_one = !wsrc.fits(all);
+      if (wsrc.fits(use_one ? one : all)) {
+        int dev = 0;
+        if (int rc = device_ready(&dev)) return rc;
+        void* ws = nullptr;
+        const int rc = get_workspace(wsrc, dev, use_one ? one : all, &ws);
+        if (rc == 0)
+          return run_staged_classical(p, A, lda, B, ldb, C, ldc, alpha, beta,
+                                      static_cast<double*>(ws), use_one, stream);
+        if (force_staged_classical || wsrc.fixed) return rc;
+        g_last_error.clear();   // the library-owned allocation failed: the all-products kernel
+      } else if (force_staged_classical) {
+        return fail(STRASSEN_ERR_ALLOC, "one-level staged sums need %zu bytes of workspace", one);
       }
     }
     PadPlan pp;
@@ -1697,6 +1806,8 @@ size_t workspace_bytes(int64_t m, int64_t n, int64_t k, int levels, int variant)
       bytes = (size_t)pp.total * sizeof(double);
     else if (staging_applies(m, n, k, levels))
       bytes = (size_t)make_stage_plan(p).total * sizeof(double);
+    else if (levels == 1 && m % 4 == 0 && k % 4 == 0 && n % 2 == 0 && classical_size(m / 2, n / 2))
+      bytes = (size_t)make_stage_plan(p, false, 1).total * sizeof(double);   // staged sums
   }
   return bytes;
 }
@@ -1787,7 +1898,8 @@ int gemm_t(char transa, char transb, int64_t m, int64_t n, int64_t k, double alp
     return dgemm(m, n, k, alpha, ta ? nullptr : A, la, tb ? nullptr : B, lb, beta, C, ldc,
                  levels, variant, wsrc, stream);
   }
-  if (!ta && levels == 0 && !classical_size(m, n) && g_forced_cfg.load() < kCfgAll)
+  const int fcfg = g_forced_cfg.load();
+  if (!ta && levels == 0 && !classical_size(m, n) && (fcfg < kCfgAll || fcfg == kCfgClassicalStaged))
     return run_tile_tb(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream);
   // packed operands: op(A) as m x k with ld round_up(m, 2), op(B) as k x n with ld round_up(k, 2)
   const int64_t lda_p = round_up(m, 2), ldb_p = round_up(k, 2);

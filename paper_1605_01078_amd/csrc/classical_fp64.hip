@@ -19,7 +19,10 @@
 // row 64 wm + 32 fb + 2 (l % 16) + fm, column 64 wn + 16 fn + l / 16 + 4 e, and a C row pair is
 // one 16-byte access.  Every C element therefore receives exactly the FP64 operations of the
 // general tile kernel at levels = 0 (bitwise the same result), then one update
-// c = fma(alpha, acc, beta*c) (alpha*acc when beta = 0: C is not read).
+// c = fma(alpha, acc, beta*c) (alpha*acc when beta = 0: C is not read).  One-level ABC runs its
+// seven products on this kernel with a second destination: the product is then added to each
+// of its (at most two) C quadrants, with the quadrant's coefficient, the first update of a
+// quadrant applying beta: the C update of the all-products kernel, one product per launch.
 //
 // Requirements (checked by the host): m and k even, A, B, C 16-byte aligned, even leading
 // dimensions, 8 * 64 * ldc < 2^31 and 8 * 8 * ldb < 2^31.
@@ -199,11 +202,15 @@ struct Classical {
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
-    // ---- epilogue: C row pairs, read once (unless beta == 0), updated, written once ----
+    // ---- epilogue: C row pairs of each destination, read once (unless its first update has
+    // beta == 0), updated, written once ----
     const int64_t ldc = args.ldc;
-    const double alpha = args.alpha, beta = args.beta;
-    const bool read_c = beta != 0.0;
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(args.C + i0 + (j0 + 64 * wn) * ldc);
+    const double beta = args.beta;
+    for (int d = 0; d <= args.extra; ++d) {
+    const double alpha = d == 0 ? args.alpha : args.alpha2;
+    const bool first = !((args.not_first >> d) & 1);
+    const bool read_c = !(first && beta == 0.0);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc((d == 0 ? args.C : args.C2) + i0 + (j0 + 64 * wn) * ldc);
 #pragma unroll
     for (int fb = 0; fb < FMB; ++fb) {
       const int er = 64 * wm + 32 * fb + 2 * (lane & 15);
@@ -217,11 +224,12 @@ struct Classical {
           const uint32_t off = (uint32_t)(8 * (er + (int64_t)ec * ldc));
           d2_t c = __builtin_bit_cast(
               d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (ok && read_c) ? off : kOOB, 0, 0));
-          c.x = c_update(c.x, acc[fb][0][fn][e], alpha, beta, true);
-          c.y = c_update(c.y, acc[fb][1][fn][e], alpha, beta, true);
+          c.x = c_update(c.x, acc[fb][0][fn][e], alpha, beta, first);
+          c.y = c_update(c.y, acc[fb][1][fn][e], alpha, beta, first);
           __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, c), rs, ok ? off : kOOB,
                                                  0, 0);
         }
+    }
     }
   }
 };

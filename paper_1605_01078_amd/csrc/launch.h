@@ -14,7 +14,8 @@ enum TileCfg : int {
   kCfg128w1 = 3,   // 128 x 128, BK 16, one workgroup per CU (512 registers per lane)
   kCfgAll = 4,     // ABC with levels >= 1: the all-products kernel (where its layout applies)
   kCfgAllStaged = 5,   // as 4; at two levels the outer operand sums are staged in a workspace
-  kNumCfgs = 6
+  kCfgClassicalStaged = 6,   // ABC with one level: sums staged, products on the classical kernel
+  kNumCfgs = 7
 };
 inline int cfg_bm(int cfg) { return cfg == kCfg64 ? 64 : 128; }
 inline int cfg_bn(int cfg) { return cfg == kCfg64 ? 64 : 128; }

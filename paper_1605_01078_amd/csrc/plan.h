@@ -105,6 +105,13 @@ struct ClassicalArgs {
   int64_t m, n, k;
   double alpha, beta;
   int32_t tiles_m, tiles_n;     // 256 x 128 tiles of C
+  // A second destination (one-level ABC on this kernel): with extra = 1 the product is also
+  // added to C2 (same shape and ldc) with coefficient alpha2, after C.  Bit d of not_first:
+  // destination d is not receiving its first update (beta is not applied, C is read).
+  double* C2;
+  double alpha2;
+  int32_t extra;
+  int32_t not_first;
 };
 
 // C assembly for AB / Naive: C_s := beta*C_s at the first update, then C_s += alpha*gamma*M_r

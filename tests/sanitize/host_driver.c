@@ -124,8 +124,8 @@ int main(void) {
   }
 
   /* tuning controls */
-  for (int cfg = -1; cfg <= 5; ++cfg) EXPECT(strassen_set_tile_config(cfg) == 0);
-  EXPECT(strassen_set_tile_config(6) == -1);
+  for (int cfg = -1; cfg <= 6; ++cfg) EXPECT(strassen_set_tile_config(cfg) == 0);
+  EXPECT(strassen_set_tile_config(7) == -1);
   EXPECT(strassen_set_tile_config(-1) == 0);
   EXPECT(strassen_set_workspace_limit((size_t)1 << 20) == 0);
   EXPECT(strassen_set_workspace_limit(0) == 0);

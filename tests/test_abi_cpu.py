@@ -100,6 +100,9 @@ def test_workspace_sizes(m, n, k):
             want = 0
             if m % u or k % u:
                 want = 8 * (r32(mp * kp) + r32(kp * n) + (r32(mp * n) if m % u else 0))
+            elif levels == 1 and n % 2 == 0 and _cdiv(mq, 256) * _cdiv(nq, 128) >= 256:
+                # one level staged on the classical kernel: five A and five B quadrant sums
+                want = 8 * (5 * r32(mq * kq) + 5 * r32(kq * nq))
             assert sx.workspace_size(m, n, k, levels, "abc") == want
         ab = sx.workspace_size(m, n, k, levels, "ab")
         nprod = 7 ** levels
@@ -141,7 +144,10 @@ def test_two_level_abc_staging_workspace():
     for m, n, k in [(16384, 16384, 16384), (4096, 4096, 4096), (8192, 12288, 2048)]:
         want = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
         assert sx.workspace_size(m, n, k, 2, "abc") == want
-        assert sx.workspace_size(m, n, k, 1, "abc") == 0
+        # one level: its own staged sums where its products fill the GPU on the classical kernel
+        h = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
+        big = _cdiv(m // 2, 256) * _cdiv(n // 2, 128) >= 256
+        assert sx.workspace_size(m, n, k, 1, "abc") == (h if big else 0)
     for m, n, k in [(2048, 4096, 4096), (8192, 8192, 1024)]:
         assert sx.workspace_size(m, n, k, 2, "abc") == 0
     # n not a multiple of 4: B and C are copied with n rounded up to 4 columns, then staged

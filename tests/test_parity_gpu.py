@@ -271,6 +271,69 @@ def test_every_tile_config_bitwise_and_exact(cfg, levels):
         sx.set_tile_config(-1)
 
 
+@pytest.mark.parametrize("shape,beta", [((8192, 8192, 8192), 1.5), ((8196, 8194, 4100), 0.0)])
+def test_one_level_staged_on_the_classical_kernel(shape, beta):
+    """One-level ABC where its products fill the GPU on the classical kernel: the five sums of
+    each side staged (two passes), then seven classical launches adding each product to its C
+    quadrants; with a workspace cap that holds one product's two sums, seven sum passes; below
+    that, the all-products kernel (no workspace).  Every form and the all-products kernel
+    forced by configuration 4 give the same bits; sampled columns match the oracle (beta = 0:
+    C, filled with NaN, is not read)."""
+    m, n, k = shape
+    print(f"case one-level staged classical {shape} beta={beta}", flush=True)
+    A, B, C = W.problem(31, m, n, k, "uniform")
+    if beta == 0.0:
+        C[:] = np.nan
+    dA, dB = sx.to_device(A), sx.to_device(B)
+
+    def counted():
+        for kind in sx.KERNEL_KINDS:
+            sx.timing_collect(kind)
+        sx.timing_enable(True)
+        try:
+            dC = sx.to_device(C)
+            sx.dgemm(dA, dB, dC, -0.75, beta, 1, "abc")
+            torch.cuda.synchronize()
+        finally:
+            sx.timing_enable(False)
+        return (sx.to_host(dC), sx.timing_collect("outer_sums")[1],
+                sx.timing_collect("classical")[1], sx.timing_collect("all_products")[1])
+
+    staged, n_sums, n_cls, n_ap = counted()
+    assert (n_sums, n_cls, n_ap) == (2, 7, 0)
+    mq, nq, kq = m // 2, n // 2, k // 2
+    one = 8 * (-(-(mq * kq) // 32) * 32 + -(-(kq * nq) // 32) * 32)
+    outs = []
+    try:
+        for limit, want in ((one + 4096, (5 + 5, 7, 0)), (one // 2, (0, 0, 1))):
+            sx.set_workspace_limit(limit)
+            got, *counts = counted()
+            assert tuple(counts) == want, (limit, counts)
+            outs.append(got)
+        sx.set_workspace_limit(0)
+        sx.set_tile_config(4)
+        outs.append(counted()[0])
+    finally:
+        sx.set_workspace_limit(0)
+        sx.set_tile_config(-1)
+    for got in outs:
+        assert np.array_equal(got, staged)
+    cols = np.array([0, 1, n // 2 - 1, n // 2, n - 1])
+    Cc = np.asfortranarray(C[:, cols]) if beta != 0.0 else np.zeros((m, len(cols)), order="F")
+    ref = oracle_dgemm(A, np.asfortranarray(B[:, cols]), Cc, -0.75, beta)
+    assert rel_fro(staged[:, cols], ref) <= TOL[1]
+
+
+def test_one_level_staged_on_the_classical_kernel_exact_on_integers():
+    m, n, k = 8192, 8200, 2052
+    print(f"case one-level staged classical integers {m}x{n}x{k}", flush=True)
+    A, B, C = W.problem(32, m, n, k, "integer")
+    got = run(A, B, C, 1.0, 1.0, 1, "abc")
+    cols = np.array([0, 7, n // 2 - 1, n // 2, n - 1])
+    ref = oracle_dgemm(A, np.asfortranarray(B[:, cols]), np.asfortranarray(C[:, cols]), 1.0, 1.0)
+    assert np.array_equal(got[:, cols], ref)
+
+
 # Shapes on which ABC runs the all-products kernel (m and k multiples of 2^(L+1)): full tiles,
 # tile fringes inside the sub-blocks (m/4 = 194 = 3*64 + 2) and ragged n at both levels, and
 # sub-blocks of whole k steps with ragged m and n (1000 x 1096 x 1024).
