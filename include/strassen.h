@@ -50,7 +50,8 @@ extern "C" {
 /* Variants of Sec. 4.1 ("Variations on a theme"). */
 enum strassen_variant {
     STRASSEN_ABC = 0,   /* sums formed in the operand load, products added to every C
-                           destination in the kernel epilogue; no workspace            */
+                           destination in the kernel epilogue; runs without workspace
+                           (staging its sums where workspace is available is faster)   */
     STRASSEN_AB = 1,    /* sums formed in the operand load, products stored to explicit
                            temporaries M_r, C assembled from them by a second kernel    */
     STRASSEN_NAIVE = 2  /* explicit operand-sum temporaries, plain GEMM on them, then
@@ -108,7 +109,16 @@ enum strassen_precision { STRASSEN_PREC_F32 = 0, STRASSEN_PREC_F64 = 1 };
  * strassen_set_workspace_limit) too small for the ten sums but holding one m/2 x k/2 and one
  * k/2 x n/2 slot (a fifth of it) stages one outer product's sums at a time, just before its
  * launch (each sum still formed once; the same bits); smaller still, the sums are formed in
- * the load.
+ * the load.  At one level ABC likewise stages its five sums per side (m/2 x k/2 and k/2 x n/2
+ * slots, by the same streaming pass over the four quadrants) where m and k are multiples of 4,
+ * n is even, the operands fit the classical kernel's layout, k/2 >= 2048, the 256 x 128 tiles
+ * of a product fill whole rounds of the 256 CUs (at least 95% of the last one) and k/2 >= 4096
+ * or there are at least 1024 tiles: the seven products then run on the classical kernel, one
+ * launch each
+ * in product order, adding the product to its one or two C quadrants in the epilogue (beta at a
+ * quadrant's first update): bitwise the result of the all-products kernel.  A workspace that
+ * holds one slot per side but not ten stages one product's sums just before its launch; with
+ * less, the all-products kernel runs (no workspace).
  * ABC at levels >= 1 runs on block-padded copies of the operands that do not fit the fused
  * kernel's layout (m or k not a multiple of 2^(L+1), an operand not 16-byte aligned or with an
  * odd leading dimension; B and C also where staging needs n % 4 == 0): every sub-block of the
@@ -249,13 +259,14 @@ int strassen_dgemm_noalloc(int64_t m, int64_t n, int64_t k, double alpha,
  * m or k is not a multiple of 2^(L+1)) and at two levels the staging buffers of the (padded)
  * problem; NAIVE adds the operand-sum temporaries.  ABC, for 16-byte aligned operands with
  * even leading dimensions: where m, k are multiples of 2^(L+1) (and, for two levels, n of 4 or
- * no staging), 0 at one level and at two the staging buffers of its outer operand sums where
- * staging is the default (five m/2 x k/2 and five k/2 x n/2 slots, each rounded up to 32
- * doubles); otherwise the block-padded copies (A as mp x kp, B as kp x n', C as mp x n' where
+ * no staging), at one level the five m/2 x k/2 and five k/2 x n/2 sum slots where its
+ * products run on the classical kernel (see strassen_dgemm; else 0), and at two the staging
+ * buffers of its outer operand sums where staging is the default (five m/2 x k/2 and five
+ * k/2 x n/2 slots; every slot rounded up to 32 doubles); otherwise the block-padded copies (A as mp x kp, B as kp x n', C as mp x n' where
  * it is copied; mp = 2^L * (ceil(m/2^L) rounded up to even), kp likewise, n' = n rounded up to
  * 4 where staging needs it; each rounded up to 32 doubles) plus the staging buffers of the
- * padded problem.  A smaller caller workspace stages one outer product at a time (see above),
- * or turns staging or the copies off.
+ * padded problem.  A smaller caller workspace stages one (outer) product at a time (see
+ * above), or turns staging or the copies off.
  * Returns 0 or -i as strassen_dgemm does for the same argument (m=1 n=2 k=3 levels=4
  * variant=5 bytes=6).
  */
@@ -430,7 +441,7 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
 
 /*
  * strassen_set_tile_config — tuning control.  cfg = -1 (default) lets the library choose the
- * kernel and tile configuration per call; 0..5 forces one for every later call in the process:
+ * kernel and tile configuration per call; 0..6 forces one for every later call in the process:
  *   0: 128 x 128 tile, k step 16, two workgroups per CU;   1: 64 x 64, k step 16;
  *   2: 128 x 128, k step 8, two workgroups per CU;        3: 128 x 128, k step 16, one per CU;
  *   4: ABC and AB with levels >= 1 run the all-products kernel (the seven products of a level
@@ -439,7 +450,10 @@ int strassen_mlp_adam(float *params, const float *grad, float *m, float *v, int 
  *      leading dimensions), else on block-padded copies as by default; ABC forms the two-level
  *      outer sums in the load (two-level AB, which needs them staged, runs the tile kernel);
  *   5: as 4, with the two-level outer operand sums staged wherever n % 4 == 0 (the workspace,
- *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise).
+ *      library-owned or the caller's, must then hold them: STRASSEN_ERR_ALLOC otherwise);
+ *   6: the default, except that one-level ABC on the classical kernel (see strassen_dgemm) is
+ *      required where its layout and size conditions hold: STRASSEN_ERR_ALLOC when the
+ *      workspace cannot hold one product's two sum slots.
  * The default (-1) uses the all-products kernel wherever it applies and stages as described
  * at strassen_dgemm.  For strassen_gemm_ex, 0 / 1 force the BF16 product kernel's 128 x 128 /
  * 128 x 64 workgroup tiles (default: 128 x 64 where 128 x 128 tiles would number fewer than 512).

@@ -577,14 +577,25 @@ static int run_classical(int64_t m, int64_t n, int64_t k, double alpha, const do
 // workspace (the outer-sum kernel over the four quadrants), then one classical launch per
 // product in product order, each adding its product to its one or two C quadrants (beta at a
 // quadrant's first update).  Every C element receives the operations of the all-products
-// kernel (same sums, same MFMA k order, the same updates in product order): the same bits.  It
-// applies where the quadrants are exact halves the classical kernel takes as they are (m and k
-// multiples of 4, n even, its layout) and each product fills the GPU with its 256 x 128 tiles.
+// kernel (same sums, same MFMA k order, the same updates in product order): the same bits.
+// The shapes where it is faster (measured on MI355X): quadrants that are exact halves (m and
+// k multiples of 4, n even), k/2 >= 2048 (below, the staged sums and the second C quadrant of
+// five products cost more than the classical kernel's efficiency gains: at k = 2048 the
+// all-products kernel is 1.03x classical, this form 0.98x), each product's 256 x 128 tiles
+// filling whole rounds of the 256 CUs (at least 95% of the last round busy: 12288^3, with
+// 4.5 rounds, runs at 0.98x against 1.03x), and either k/2 >= 4096 or four rounds of tiles.
+bool one_level_staged_shape(int64_t m, int64_t n, int64_t k) {
+  if (m % 4 != 0 || k % 4 != 0 || n % 2 != 0) return false;
+  const int64_t kq = k / 2, tiles = cdiv(m / 2, 256) * cdiv(n / 2, 128);
+  const int64_t rounds = cdiv(tiles, 256);
+  return tiles >= 256 && kq >= 2048 && 20 * tiles >= 19 * 256 * rounds &&
+         (kq >= 4096 || tiles >= 1024);
+}
+
 static bool staged_classical_applies(int64_t m, int64_t n, int64_t k, const double* A,
                                      int64_t lda, const double* B, int64_t ldb, const double* C,
                                      int64_t ldc) {
-  return m % 4 == 0 && k % 4 == 0 && n % 2 == 0 && classical_size(m / 2, n / 2) &&
-         classical_layout(m / 2, k / 2, A, lda, B, ldb, C, ldc);
+  return one_level_staged_shape(m, n, k) && classical_layout(m / 2, k / 2, A, lda, B, ldb, C, ldc);
 }
 
 static int run_staged_classical(const Plan& p, const double* A, int64_t lda, const double* B,
@@ -1806,7 +1817,7 @@ size_t workspace_bytes(int64_t m, int64_t n, int64_t k, int levels, int variant)
       bytes = (size_t)pp.total * sizeof(double);
     else if (staging_applies(m, n, k, levels))
       bytes = (size_t)make_stage_plan(p).total * sizeof(double);
-    else if (levels == 1 && m % 4 == 0 && k % 4 == 0 && n % 2 == 0 && classical_size(m / 2, n / 2))
+    else if (levels == 1 && one_level_staged_shape(m, n, k))
       bytes = (size_t)make_stage_plan(p, false, 1).total * sizeof(double);   // staged sums
   }
   return bytes;

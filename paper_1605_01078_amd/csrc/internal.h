@@ -50,6 +50,10 @@ WsSource default_workspace();
 // recorded into a graph by stream capture must not carry them).
 void suspend_timing(bool on);
 
+// Whether one-level ABC stages its sums and runs its products on the classical kernel for
+// this shape (given aligned operands with even leading dimensions and the workspace).
+bool one_level_staged_shape(int64_t m, int64_t n, int64_t k);
+
 // C := alpha*A*B + beta*C (strassen_dgemm) with its workspace taken from `ws`.
 int dgemm(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
           const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,

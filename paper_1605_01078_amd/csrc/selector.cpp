@@ -163,6 +163,12 @@ double model_seconds(int64_t m, int64_t n, int64_t k, int dtype, int c) {
   };
   const double e_ap = whole_p ? K.e_full : K.e_masked;
   if (var == STRASSEN_ABC) {
+    if (L == 1 && one_level_staged_shape(m, n, k)) {
+      // the sums staged (per side four quadrants read, five sums written), the seven products
+      // on the classical kernel, five of them updating a second C quadrant
+      return 8.0 * 9.0 * (mq * kq + kq * nq) / K.bw + 2.0 * K.t_launch +
+             7.0 * classical(mq, nq, kq) + 5.0 * 16.0 * mq * nq / K.bw;
+    }
     double copies = 0.0;   // block-padded copies: A and B (or B only), C in and out
     if (pad_mk) copies = 8.0 * (2.0 * dm * dk + 2.0 * dk * dn + 4.0 * dm * dn) / K.bw + 4.0 * K.t_launch;
     else if (pad_n) copies = 8.0 * (2.0 * dk * dn + 4.0 * dm * dn) / K.bw + 3.0 * K.t_launch;

@@ -85,6 +85,29 @@ def _cdiv(a, b):
     return -(-a // b)
 
 
+def _one_level_staged(m, n, k):
+    """The shapes on which one-level ABC stages its sums and runs the classical kernel: exact
+    quadrants, k/2 >= 2048, whole rounds of 256 x 128 tiles (95% of the last one) and either
+    k/2 >= 4096 or at least 1024 tiles."""
+    if m % 4 or k % 4 or n % 2:
+        return False
+    tiles = _cdiv(m // 2, 256) * _cdiv(n // 2, 128)
+    rounds = _cdiv(tiles, 256)
+    return tiles >= 256 and k // 2 >= 2048 and 20 * tiles >= 19 * 256 * rounds and \
+        (k // 2 >= 4096 or tiles >= 1024)
+
+
+def test_one_level_staged_shapes():
+    assert _one_level_staged(16384, 16384, 16384) and _one_level_staged(8192, 8192, 8192)
+    assert not _one_level_staged(16384, 16384, 2048)    # rank-k: the all-products kernel
+    assert not _one_level_staged(12288, 12288, 12288)   # 4.5 rounds of tiles
+    r32 = lambda x: _cdiv(x, 32) * 32
+    for m, n, k in [(16384, 16384, 4096), (8192, 8192, 8192), (8188, 8190, 8196),
+                    (16384, 16384, 2048), (12288, 12288, 12288), (8192, 8192, 4096)]:
+        want = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
+        assert sx.workspace_size(m, n, k, 1, "abc") == (want if _one_level_staged(m, n, k) else 0)
+
+
 @pytest.mark.parametrize("m,n,k", [(512, 512, 512), (1000, 777, 333), (16384, 16384, 16384)])
 def test_workspace_sizes(m, n, k):
     assert sx.workspace_size(m, n, k, 0, "ab") == 0
@@ -100,7 +123,7 @@ def test_workspace_sizes(m, n, k):
             want = 0
             if m % u or k % u:
                 want = 8 * (r32(mp * kp) + r32(kp * n) + (r32(mp * n) if m % u else 0))
-            elif levels == 1 and n % 2 == 0 and _cdiv(mq, 256) * _cdiv(nq, 128) >= 256:
+            elif levels == 1 and _one_level_staged(m, n, k):
                 # one level staged on the classical kernel: five A and five B quadrant sums
                 want = 8 * (5 * r32(mq * kq) + 5 * r32(kq * nq))
             assert sx.workspace_size(m, n, k, levels, "abc") == want
@@ -146,8 +169,7 @@ def test_two_level_abc_staging_workspace():
         assert sx.workspace_size(m, n, k, 2, "abc") == want
         # one level: its own staged sums where its products fill the GPU on the classical kernel
         h = 8 * (5 * r32((m // 2) * (k // 2)) + 5 * r32((k // 2) * (n // 2)))
-        big = _cdiv(m // 2, 256) * _cdiv(n // 2, 128) >= 256
-        assert sx.workspace_size(m, n, k, 1, "abc") == (h if big else 0)
+        assert sx.workspace_size(m, n, k, 1, "abc") == (h if _one_level_staged(m, n, k) else 0)
     for m, n, k in [(2048, 4096, 4096), (8192, 8192, 1024)]:
         assert sx.workspace_size(m, n, k, 2, "abc") == 0
     # n not a multiple of 4: B and C are copied with n rounded up to 4 columns, then staged

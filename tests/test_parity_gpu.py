@@ -271,9 +271,10 @@ def test_every_tile_config_bitwise_and_exact(cfg, levels):
         sx.set_tile_config(-1)
 
 
-@pytest.mark.parametrize("shape,beta", [((8192, 8192, 8192), 1.5), ((8196, 8194, 4100), 0.0)])
+@pytest.mark.parametrize("shape,beta", [((8192, 8192, 8192), 1.5), ((8188, 8190, 8196), 0.0)])
 def test_one_level_staged_on_the_classical_kernel(shape, beta):
-    """One-level ABC where its products fill the GPU on the classical kernel: the five sums of
+    """One-level ABC where its products fill whole rounds of the GPU on the classical kernel
+    (k/2 >= 4096; the second shape has odd quadrant extents and tile fringes): the five sums of
     each side staged (two passes), then seven classical launches adding each product to its C
     quadrants; with a workspace cap that holds one product's two sums, seven sum passes; below
     that, the all-products kernel (no workspace).  Every form and the all-products kernel
@@ -325,7 +326,7 @@ def test_one_level_staged_on_the_classical_kernel(shape, beta):
 
 
 def test_one_level_staged_on_the_classical_kernel_exact_on_integers():
-    m, n, k = 8192, 8200, 2052
+    m, n, k = 8192, 8190, 8196
     print(f"case one-level staged classical integers {m}x{n}x{k}", flush=True)
     A, B, C = W.problem(32, m, n, k, "integer")
     got = run(A, B, C, 1.0, 1.0, 1, "abc")
