@@ -101,15 +101,29 @@ def copy_calibration():
     del x, y
 
 
-def dominant_kernel(L, variant):
+def one_level_staged(m, n, k):
+    """The library's rule for one-level ABC on the classical kernel (staged sums, one launch
+    per product): exact quadrants, k/2 >= 2048, whole rounds of 256 x 128 tiles (95% of the
+    last one) and k/2 >= 4096 or at least 1024 tiles."""
+    if m % 4 or k % 4 or n % 2:
+        return False
+    tiles = -(-(m // 2) // 256) * -(-(n // 2) // 128)
+    rounds = -(-tiles // 256)
+    return tiles >= 256 and k // 2 >= 2048 and 20 * tiles >= 19 * 256 * rounds and \
+        (k // 2 >= 4096 or tiles >= 1024)
+
+
+def dominant_kernel(L, variant, n=None):
     if L == 0:
+        return "classical_kernel"
+    if L == 1 and variant == "abc" and n is not None and one_level_staged(n, n, n):
         return "classical_kernel"
     return "all_products_kernel" if variant in ("abc", "ab") else "fp64_tile_kernel"
 
 
-def kernel_kind(L, variant):
+def kernel_kind(L, variant, n=None):
     return {"classical_kernel": "classical", "all_products_kernel": "all_products"}.get(
-        dominant_kernel(L, variant), "tile")
+        dominant_kernel(L, variant, n), "tile")
 
 
 def headline_key(L, variant, staged):
@@ -121,7 +135,7 @@ def headline_key(L, variant, staged):
 
 
 def traffic_path(L, variant, n):
-    return os.path.join(ROOT, "profiles", f"traffic_{dominant_kernel(L, variant)}_L{L}_{variant}_{n}.json")
+    return os.path.join(ROOT, "profiles", f"traffic_{dominant_kernel(L, variant, n)}_L{L}_{variant}_{n}.json")
 
 
 def traffic_summary(args):
@@ -130,7 +144,7 @@ def traffic_summary(args):
     calibration copy in the same run."""
     import csv
     import glob
-    kname = dominant_kernel(args.levels, args.variant)
+    kname = dominant_kernel(args.levels, args.variant, args.n)
 
     def read(d, counter):
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
@@ -833,7 +847,7 @@ def main():
     t0 = time.perf_counter()
     start_all = torch.cuda.Event(enable_timing=True)
     end_all = torch.cuda.Event(enable_timing=True)
-    kind = kernel_kind(L, variant)
+    kind = kernel_kind(L, variant, n)
     for k_ in sx.KERNEL_KINDS:   # drop what the warmup recorded
         sx.timing_collect(k_)
     sx.timing_enable(True)       # library-side event pairs around each kernel launch
@@ -975,6 +989,8 @@ def main():
     # launch of that kernel during the timed steps (the staged outer-sum passes of two-level ABC
     # and the assembly / sum passes are timed apart from it).
     launches = 7 ** (L - 1) if (variant in ("abc", "ab") and L >= 1) else 1
+    if L == 1 and variant == "abc" and one_level_staged(n, n, n):
+        launches = 7   # one classical launch per product
     if kern_launches != launches * args.steps:
         raise SystemExit(f"expected {launches * args.steps} launches of the {kind} kernel in the "
                          f"timed steps, recorded {kern_launches}")
@@ -990,7 +1006,7 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA, 4), "traffic": traffic,
-                "kernel": dominant_kernel(L, variant),
+                "kernel": dominant_kernel(L, variant, n),
                 "launches_per_step": launches,
                 "exec_flops_per_launch": exec_flops_launch, "avg_launch_ms": round(avg_launch_ms, 3),
                 "timing": "HIP event pair around each launch on the call's stream, timed steps"}
@@ -1048,7 +1064,9 @@ def main():
         "config": {"workload": f"strassen_dgemm L={L} {variant.upper()} m=n=k={n} FP64 "
                                f"C:=A*B+C, entries uniform[-1,1]",
                    "m": n, "n": n, "k": n, "levels": L, "variant": variant,
-                   "outer_sums": ("staged" if sums_launches else "in the tile load") if L == 2 else None,
+                   "outer_sums": (("staged" if sums_launches else "in the tile load") if L == 2 else
+                                  ("staged, products on the classical kernel" if L == 1 and sums_launches
+                                   else None)),
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
