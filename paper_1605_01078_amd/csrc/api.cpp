@@ -652,8 +652,8 @@ static int run_staged_classical(const Plan& p, const double* A, int64_t lda, con
     }
     c.C = dst[0];
     c.alpha = ag[0];
-    c.C2 = dst[1];
-    c.alpha2 = ag[1];
+    c.Cx[0] = dst[1];
+    c.ax[0] = ag[1];
     c.extra = P.nc - 1;
     c.beta = beta;
     c.ldc = ldc;
@@ -1261,6 +1261,80 @@ static int run_winograd(const WPlan& wp, double alpha, const double* A, int64_t 
   return 0;
 }
 
+// Winograd's variant at one level on the classical kernel (where one-level ABC takes that
+// route): the chain sums S1..S4 and T1..T4 over the four quadrants staged in workspace (four
+// m/2 x k/2 and four k/2 x n/2 slots), then one classical launch per product in product order,
+// each adding its product to every C quadrant it reaches (M1 all four): the all-products
+// kernel's C update, one product at a time, so the same bits.
+static size_t winograd_staged_bytes(int64_t m, int64_t n, int64_t k) {
+  const int64_t mq = m / 2, nq = n / 2, kq = k / 2;
+  return (size_t)(4 * round_up(mq * kq, 32) + 4 * round_up(kq * nq, 32)) * sizeof(double);
+}
+
+static int run_winograd_classical(int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                                  int64_t lda, const double* B, int64_t ldb, double beta,
+                                  double* C, int64_t ldc, double* ws, hipStream_t stream) {
+  const int64_t mq = m / 2, nq = n / 2, kq = k / 2;
+  const int64_t sa_stride = round_up(mq * kq, 32), sb_stride = round_up(kq * nq, 32);
+  double* SA = ws;
+  double* SB = ws + 4 * sa_stride;
+  ChainSumArgs ca;
+  std::memset(&ca, 0, sizeof ca);
+  ca.src = A;
+  ca.dst = SA;
+  ca.ld = lda;
+  ca.rows = mq;
+  ca.cols = kq;
+  ca.dst_stride = sa_stride;
+  ChainSumArgs cb = ca;
+  cb.src = B;
+  cb.dst = SB;
+  cb.ld = ldb;
+  cb.rows = kq;
+  cb.cols = nq;
+  cb.dst_stride = sb_stride;
+  for (int q = 0; q < 4; ++q) {
+    ca.blk[q] = (q >> 1) * mq + (q & 1) * kq * lda;
+    cb.blk[q] = (q >> 1) * kq + (q & 1) * nq * ldb;
+  }
+  SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_chain_sums(ca, 0, stream));
+  SMX_LAUNCH(STRASSEN_KERNEL_OUTER_SUMS, stream, launch_chain_sums(cb, 1, stream));
+  bool touched[4] = {false, false, false, false};
+  for (int r = 0; r < 7; ++r) {
+    const WProduct& P = kWinograd[r];
+    ClassicalArgs c;
+    std::memset(&c, 0, sizeof c);
+    c.A = P.a < 4 ? A + ca.blk[P.a] : SA + (P.a - 4) * sa_stride;
+    c.lda = P.a < 4 ? lda : mq;
+    c.B = P.b < 4 ? B + cb.blk[P.b] : SB + (P.b - 4) * sb_stride;
+    c.ldb = P.b < 4 ? ldb : kq;
+    for (int d = 0; d < P.nc; ++d) {
+      const int q = P.c[d].q;
+      double* dst = C + (q >> 1) * mq + (q & 1) * nq * ldc;
+      const double ag = P.c[d].sign > 0 ? alpha : -alpha;
+      if (d == 0) {
+        c.C = dst;
+        c.alpha = ag;
+      } else {
+        c.Cx[d - 1] = dst;
+        c.ax[d - 1] = ag;
+      }
+      if (touched[q]) c.not_first |= 1 << d;
+      touched[q] = true;
+    }
+    c.extra = P.nc - 1;
+    c.beta = beta;
+    c.ldc = ldc;
+    c.m = mq;
+    c.n = nq;
+    c.k = kq;
+    c.tiles_m = (int32_t)cdiv(mq, 256);
+    c.tiles_n = (int32_t)cdiv(nq, 128);
+    SMX_LAUNCH(STRASSEN_KERNEL_CLASSICAL, stream, launch_classical(c, stream));
+  }
+  return 0;
+}
+
 int dgemm_winograd(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int levels,
                    const WsSource& wsrc, hipStream_t stream) {
@@ -1273,6 +1347,19 @@ int dgemm_winograd(int64_t m, int64_t n, int64_t k, double alpha, const double* 
     int dev = 0;
     if (int rc = device_ready(&dev)) return rc;
     return run_scale(C, ldc, m, n, beta, stream);
+  }
+  if (levels == 1 && one_level_staged_shape(m, n, k) &&
+      classical_layout(m / 2, k / 2, A, lda, B, ldb, C, ldc) &&
+      wsrc.fits(winograd_staged_bytes(m, n, k))) {
+    int dev = 0;
+    if (int rc = device_ready(&dev)) return rc;
+    void* w = nullptr;
+    const int rc = get_workspace(wsrc, dev, winograd_staged_bytes(m, n, k), &w);
+    if (rc == 0)
+      return run_winograd_classical(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                    static_cast<double*>(w), stream);
+    if (wsrc.fixed) return rc;
+    g_last_error.clear();   // the library-owned allocation failed: the all-products kernel
   }
   const WPlan wp = make_w_plan(m, n, k, levels, A, lda, B, ldb, C, ldc);
   if (!wp.ok) return fail(STRASSEN_ERR_UNSUPPORTED, "sizes past the 32-bit tile offsets");
@@ -1995,6 +2082,8 @@ int strassen_workspace_size_winograd(int64_t m, int64_t n, int64_t k, int levels
                : (size_t)smx::make_w_plan(m, n, k, levels, nullptr, 2 * smx::cdiv(m, 2), nullptr,
                                           2 * smx::cdiv(k, 2), nullptr, 2 * smx::cdiv(m, 2))
                          .total * sizeof(double);
+  if (levels == 1 && m > 0 && n > 0 && k > 0 && smx::one_level_staged_shape(m, n, k))
+    *bytes = smx::winograd_staged_bytes(m, n, k);   // the staged chain sums
   return 0;
 }
 

@@ -19,10 +19,11 @@
 // row 64 wm + 32 fb + 2 (l % 16) + fm, column 64 wn + 16 fn + l / 16 + 4 e, and a C row pair is
 // one 16-byte access.  Every C element therefore receives exactly the FP64 operations of the
 // general tile kernel at levels = 0 (bitwise the same result), then one update
-// c = fma(alpha, acc, beta*c) (alpha*acc when beta = 0: C is not read).  One-level ABC runs its
-// seven products on this kernel with a second destination: the product is then added to each
-// of its (at most two) C quadrants, with the quadrant's coefficient, the first update of a
-// quadrant applying beta: the C update of the all-products kernel, one product per launch.
+// c = fma(alpha, acc, beta*c) (alpha*acc when beta = 0: C is not read).  One-level ABC (and
+// Winograd's variant) run their seven products on this kernel with further destinations: the
+// product is then added to each of its C quadrants (up to two, four for Winograd's M1), with
+// the quadrant's coefficient, the first update of a quadrant applying beta: the C update of
+// the all-products kernel, one product per launch.
 //
 // Requirements (checked by the host): m and k even, A, B, C 16-byte aligned, even leading
 // dimensions, 8 * 64 * ldc < 2^31 and 8 * 8 * ldb < 2^31.
@@ -207,10 +208,11 @@ struct Classical {
     const int64_t ldc = args.ldc;
     const double beta = args.beta;
     for (int d = 0; d <= args.extra; ++d) {
-    const double alpha = d == 0 ? args.alpha : args.alpha2;
+    const double alpha = d == 0 ? args.alpha : (d == 1 ? args.ax[0] : (d == 2 ? args.ax[1] : args.ax[2]));
+    double* const cd = d == 0 ? args.C : (d == 1 ? args.Cx[0] : (d == 2 ? args.Cx[1] : args.Cx[2]));
     const bool first = !((args.not_first >> d) & 1);
     const bool read_c = !(first && beta == 0.0);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc((d == 0 ? args.C : args.C2) + i0 + (j0 + 64 * wn) * ldc);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(cd + i0 + (j0 + 64 * wn) * ldc);
 #pragma unroll
     for (int fb = 0; fb < FMB; ++fb) {
       const int er = 64 * wm + 32 * fb + 2 * (lane & 15);

@@ -105,11 +105,12 @@ struct ClassicalArgs {
   int64_t m, n, k;
   double alpha, beta;
   int32_t tiles_m, tiles_n;     // 256 x 128 tiles of C
-  // A second destination (one-level ABC on this kernel): with extra = 1 the product is also
-  // added to C2 (same shape and ldc) with coefficient alpha2, after C.  Bit d of not_first:
-  // destination d is not receiving its first update (beta is not applied, C is read).
-  double* C2;
-  double alpha2;
+  // Further destinations (one-level ABC and Winograd's variant on this kernel): the product is
+  // also added to Cx[0 .. extra-1] (same shape and ldc) with coefficients ax[], after C, in
+  // that order.  Bit d of not_first: destination d (0 = C) is not receiving its first update
+  // (beta is not applied, C is read).
+  double* Cx[3];
+  double ax[3];
   int32_t extra;
   int32_t not_first;
 };

@@ -331,6 +331,9 @@ def test_winograd_entry_point_checks_and_workspace():
                                      None) == -6
     r32 = lambda x: _cdiv(x, 32) * 32
     assert sx.workspace_size_winograd(4096, 4096, 4096, 1) == 0
+    # one level where its products run on the classical kernel: the eight staged chain sums
+    assert sx.workspace_size_winograd(16384, 16384, 16384, 1) == 8 * 8 * r32(8192 * 8192)
+    assert sx.workspace_size_winograd(16384, 16384, 2048, 1) == 0
     assert sx.workspace_size_winograd(4096, 4096, 4096, 2) == 8 * 8 * r32(2048 * 2048)
     m, n, k = 1001, 998, 777
     mp, kp = 2 * 2 * _cdiv(_cdiv(m, 2), 2), 2 * 2 * _cdiv(_cdiv(k, 2), 2)

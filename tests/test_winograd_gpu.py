@@ -84,3 +84,52 @@ def test_full_size_two_levels_sampled_columns():
     ref = oracle_dgemm(sx.to_host(A), np.asfortranarray(B[:, idx].cpu().numpy()),
                        np.asfortranarray(C0[:, idx].cpu().numpy()), 1.0, 1.0)
     assert rel_fro(C[:, idx].cpu().numpy(), ref) <= TOL[2]
+
+
+@pytest.mark.parametrize("shape,beta", [((8192, 8192, 8192), 1.0), ((8188, 8190, 8196), 0.0)])
+def test_one_level_on_the_classical_kernel(shape, beta):
+    """Where one-level ABC runs on the classical kernel, so does Winograd's variant: its chain
+    sums S1..S4 / T1..T4 staged (two passes), seven classical launches adding each product to
+    every C quadrant it reaches (M1 all four).  A workspace cap below the eight slots gives the
+    all-products kernel: the same bits.  Sampled columns against the oracle (beta = 0: C, full
+    of NaN, is not read); integers exact."""
+    m, n, k = shape
+    print(f"case winograd one level classical {shape} beta={beta}", flush=True)
+    r32 = lambda x: -(-x // 32) * 32
+    slots = 8 * (4 * r32((m // 2) * (k // 2)) + 4 * r32((k // 2) * (n // 2)))
+    assert sx.workspace_size_winograd(m, n, k, 1) == slots
+    cols = np.array([0, 5, n // 2 - 1, n // 2, n - 1])
+    for kind in ("uniform", "integer"):
+        A, B, C = W.problem(41, m, n, k, kind)
+        if beta == 0.0:
+            C[:] = np.nan
+        dA, dB = sx.to_device(A), sx.to_device(B)
+
+        def counted():
+            for kk in sx.KERNEL_KINDS:
+                sx.timing_collect(kk)
+            sx.timing_enable(True)
+            try:
+                dC = sx.to_device(C)
+                sx.dgemm_winograd(dA, dB, dC, 1.0, beta, 1)
+                torch.cuda.synchronize()
+            finally:
+                sx.timing_enable(False)
+            return (sx.to_host(dC), sx.timing_collect("outer_sums")[1],
+                    sx.timing_collect("classical")[1], sx.timing_collect("all_products")[1])
+
+        staged, *counts = counted()
+        assert tuple(counts) == (2, 7, 0)
+        try:
+            sx.set_workspace_limit(slots // 2)
+            fused, *counts = counted()
+            assert tuple(counts) == (0, 0, 1)
+        finally:
+            sx.set_workspace_limit(0)
+        assert np.array_equal(staged, fused)
+        Cc = np.asfortranarray(C[:, cols]) if beta != 0.0 else np.zeros((m, len(cols)), order="F")
+        ref = oracle_dgemm(A, np.asfortranarray(B[:, cols]), Cc, 1.0, beta)
+        if kind == "integer":
+            assert np.array_equal(staged[:, cols], ref)
+        else:
+            assert rel_fro(staged[:, cols], ref) <= TOL[1]
