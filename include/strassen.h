@@ -153,7 +153,11 @@ int strassen_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
  * epilogue to each C block it reaches (C00 = M1 + M2, C01 = M1 + M3 + M5 + M6,
  * C10 = M1 - M4 + M6 + M7, C11 = M1 + M5 + M6 + M7), in product order.  Two levels stage the
  * outer chain sums in workspace (four m/2 x k/2 and four k/2 x n/2 slots) and run one launch
- * per outer product.  Sizes, layouts and conventions as strassen_dgemm; block-padded copies
+ * per outer product.  One level, where one-level ABC runs its products on the classical kernel
+ * (see strassen_dgemm) and the workspace holds the eight chain-sum slots, stages the chain sums
+ * over the quadrants and runs the seven products on the classical kernel, each added to every
+ * C quadrant it reaches (the same bits; without that workspace, the fused kernel as above).
+ * Sizes, layouts and conventions as strassen_dgemm; block-padded copies
  * where m or k is not a multiple of 2^(L+1), n (two levels) not a multiple of 4, an operand is
  * not 16-byte aligned or a leading dimension odd.  Workspace (copies, staging:
  * strassen_workspace_size_winograd) is required: STRASSEN_ERR_ALLOC when it cannot be had.
