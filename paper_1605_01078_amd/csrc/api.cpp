@@ -602,6 +602,8 @@ static int run_staged_classical(const Plan& p, const double* A, int64_t lda, con
                                 int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
                                 double* stage, bool one_at_a_time, hipStream_t stream) {
   const int64_t om = p.mq, on = p.nq, okk = p.kq;   // the quadrants
+  if (cdiv(om, 256) * cdiv(on, 128) >= (int64_t(1) << 30))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
   const StagePlan sp = make_stage_plan(p, one_at_a_time, 1);
   OuterSumArgs oa, ob;
   std::memset(&oa, 0, sizeof oa);
@@ -1275,6 +1277,8 @@ static int run_winograd_classical(int64_t m, int64_t n, int64_t k, double alpha,
                                   int64_t lda, const double* B, int64_t ldb, double beta,
                                   double* C, int64_t ldc, double* ws, hipStream_t stream) {
   const int64_t mq = m / 2, nq = n / 2, kq = k / 2;
+  if (cdiv(mq, 256) * cdiv(nq, 128) >= (int64_t(1) << 30))
+    return fail(STRASSEN_ERR_UNSUPPORTED, "too many tiles");
   const int64_t sa_stride = round_up(mq * kq, 32), sb_stride = round_up(kq * nq, 32);
   double* SA = ws;
   double* SB = ws + 4 * sa_stride;
