@@ -457,10 +457,12 @@ def sweep_suite(args):
     """Every member (classical; one- and two-level ABC, AB, Naive) on the square sizes
     m = n = k = 2048, 4096, ..., 16384 and the rank-k shapes m = n = 16384, k = 256 ... 8192,
     entries uniform[-1, 1]: median of three event-timed calls each, effective TFLOPS and the
-    ratio to classical at the same shape."""
+    ratio to classical at the same shape; the fastest member's result on four sampled columns
+    against the oracle (relative Frobenius error within 1e-13 / 1e-12 / 1e-11 by level)."""
     import torch
     import paper_1605_01078_amd as sx
     import workloads as W
+    from oracle import oracle_dgemm, rel_fro
 
     stream = torch.cuda.current_stream()
     shapes = [(s_, s_, s_) for s_ in range(2048, 16384 + 1, 2048)]
@@ -482,9 +484,25 @@ def sweep_suite(args):
                           if key.startswith("L") and key != "L0_abc"}
         best = min((key for key in row if key.startswith("L")), key=lambda key: row[key])
         row["best"] = best
-        log(f"  {m}x{n}x{k}: classical {base:.3f} ms, best {best} {row[best]:.3f} ms")
+        # sampled parity of the fastest member: four columns of C against the oracle
+        lv, v = int(best[1]), best.split("_", 1)[1]
+        cols = np.sort(np.random.default_rng(m + 3 * k).choice(n, size=4, replace=False))
+        idx = torch.as_tensor(cols, device="cuda")
+        C0 = W.device_uniform(3, m, n)
+        Cc = C0[:, idx].cpu().numpy()
+        sx.dgemm(A, B, C0, 1.0, 1.0, lv, v, stream)
+        torch.cuda.synchronize()
+        ref = oracle_dgemm(sx.to_host(A), np.asfortranarray(B[:, idx].cpu().numpy()),
+                           np.asfortranarray(Cc), 1.0, 1.0)
+        err = float(rel_fro(C0[:, idx].cpu().numpy(), ref))
+        tol = {0: 1e-13, 1: 1e-12, 2: 1e-11}[lv]
+        row["parity"] = {"member": best, "rel_err": err, "tolerance": tol, "pass": err <= tol}
+        if err > tol:
+            raise SystemExit(f"sweep parity failed at {m}x{n}x{k} ({best}): {err:.3e} > {tol:.0e}")
+        log(f"  {m}x{n}x{k}: classical {base:.3f} ms, best {best} {row[best]:.3f} ms, "
+            f"sampled rel err {err:.2e}")
         rows.append(row)
-        del A, B, C
+        del A, B, C, C0
         sx.release_workspace()
         torch.cuda.empty_cache()
     sq = [r for r in rows if r["m"] == r["k"]]
