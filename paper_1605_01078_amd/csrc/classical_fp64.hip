@@ -29,6 +29,8 @@
 // dimensions, 8 * 64 * ldc < 2^31 and 8 * 8 * ldb < 2^31.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.h"
 #include "plan.h"
 #include "tile_fp64.h"
@@ -204,34 +206,53 @@ struct Classical {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
     // ---- epilogue: C row pairs of each destination, read once (unless its first update has
-    // beta == 0), updated, written once ----
+    // beta == 0), updated, written once.  The update's case is chosen once per destination and
+    // each 32-row block's sixteen loads are issued before its first store: the vector memory
+    // counter counts loads and stores in one queue, so a store between two loads would make
+    // the wait for the second load cover the store too (one round trip per row pair). ----
     const int64_t ldc = args.ldc;
     const double beta = args.beta;
     for (int d = 0; d <= args.extra; ++d) {
-    const double alpha = d == 0 ? args.alpha : (d == 1 ? args.ax[0] : (d == 2 ? args.ax[1] : args.ax[2]));
-    double* const cd = d == 0 ? args.C : (d == 1 ? args.Cx[0] : (d == 2 ? args.Cx[1] : args.Cx[2]));
-    const bool first = !((args.not_first >> d) & 1);
-    const bool read_c = !(first && beta == 0.0);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(cd + i0 + (j0 + 64 * wn) * ldc);
+      const double alpha = d == 0 ? args.alpha : (d == 1 ? args.ax[0] : (d == 2 ? args.ax[1] : args.ax[2]));
+      double* const cd = d == 0 ? args.C : (d == 1 ? args.Cx[0] : (d == 2 ? args.Cx[1] : args.Cx[2]));
+      const bool first = !((args.not_first >> d) & 1);
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(cd + i0 + (j0 + 64 * wn) * ldc);
+      auto update = [&](auto case_tag) {
+        constexpr int CASE = decltype(case_tag)::value;
 #pragma unroll
-    for (int fb = 0; fb < FMB; ++fb) {
-      const int er = 64 * wm + 32 * fb + 2 * (lane & 15);
-      const bool row_ok = FULL || i0 + er < m;
+        for (int fb = 0; fb < FMB; ++fb) {
+          const int er = 64 * wm + 32 * fb + 2 * (lane & 15);
+          const bool row_ok = FULL || i0 + er < m;
+          uint32_t off[FN][4];
+          d2_t c[FN][4];
 #pragma unroll
-      for (int fn = 0; fn < FN; ++fn)
+          for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int ec = 16 * fn + (lane >> 4) + 4 * e;   // column inside the wave's block
-          const bool ok = row_ok && (FULL || j0 + 64 * wn + ec < n);
-          const uint32_t off = (uint32_t)(8 * (er + (int64_t)ec * ldc));
-          d2_t c = __builtin_bit_cast(
-              d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (ok && read_c) ? off : kOOB, 0, 0));
-          c.x = c_update(c.x, acc[fb][0][fn][e], alpha, beta, first);
-          c.y = c_update(c.y, acc[fb][1][fn][e], alpha, beta, first);
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, c), rs, ok ? off : kOOB,
-                                                 0, 0);
+            for (int e = 0; e < 4; ++e) {
+              const int ec = 16 * fn + (lane >> 4) + 4 * e;   // column inside the wave's block
+              const bool ok = row_ok && (FULL || j0 + 64 * wn + ec < n);
+              off[fn][e] = ok ? (uint32_t)(8 * (er + (int64_t)ec * ldc)) : kOOB;
+              if constexpr (CASE == 1)
+                c[fn][e] = (d2_t){0.0, 0.0};
+              else
+                c[fn][e] = __builtin_bit_cast(
+                    d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off[fn][e], 0, 0));
+            }
+#pragma unroll
+          for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              d2_t v;
+              v.x = c_update_case<CASE>(c[fn][e].x, acc[fb][0][fn][e], alpha, beta);
+              v.y = c_update_case<CASE>(c[fn][e].y, acc[fb][1][fn][e], alpha, beta);
+              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v), rs, off[fn][e],
+                                                     0, 0);
+            }
         }
-    }
+      };
+      if (!first) update(std::integral_constant<int, 0>{});
+      else if (beta == 0.0) update(std::integral_constant<int, 1>{});
+      else update(std::integral_constant<int, 2>{});
     }
   }
 };

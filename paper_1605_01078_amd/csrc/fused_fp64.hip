@@ -39,6 +39,8 @@
 // leading dimensions.  n is arbitrary.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.h"
 #include "plan.h"
 #include "tile_fp64.h"
@@ -378,44 +380,74 @@ struct AllProducts {
       return;
     }
 
-    // ---- epilogue: every C quadrant of every outer destination, read once, written once ----
+    // ---- epilogue: every C quadrant of every outer destination, read once, written once.
+    // The case of each element's first update is chosen once per destination, and the sixteen
+    // loads of a destination (four quadrants x four row pairs) are issued before its first
+    // store: the vector memory counter counts loads and stores in one queue, so a store between
+    // two loads would make the wait for the second load cover the store too.  Every access
+    // carries its whole offset in the lane offset (scalar offset 0; below 2^31 bytes as
+    // 8 * 64 * ldc < 2^31): the compiler inserts the wait state that a 16-byte store needs
+    // before its data registers are rewritten only for stores without a scalar offset
+    // register, and with the stores issued back to back the registers are rewritten at once. ----
     const int64_t ldc = args.ldc;
     const uint32_t e_off = (uint32_t)(8 * (er + (int64_t)ec * ldc));
     for (int d = 0; d < args.nc; ++d) {
       const double ag_outer = args.c_sg[d] * args.alpha;
       const bool first_outer = (args.c_first >> d) & 1;
+      auto update = [&](auto case_tag) {
+        constexpr int CASE = decltype(case_tag)::value;   // case of each element's first update
+        __amdgpu_buffer_rsrc_t rs[4];
+        uint32_t off[4][4];
+        d2_t c[4][4];
 #pragma unroll
-      for (int cq = 0; cq < 4; ++cq) {
-        const int64_t cb = args.c_cb[d] + (cq & 1);   // column block in units of nq
-        const __amdgpu_buffer_rsrc_t rs =
-            make_rsrc(args.C + args.c_off[d] + (cq >> 1) * mq + (cq & 1) * nq * ldc + i0 + j0 * ldc);
+        for (int cq = 0; cq < 4; ++cq) {
+          const int64_t cb = args.c_cb[d] + (cq & 1);   // column block in units of nq
+          rs[cq] = make_rsrc(args.C + args.c_off[d] + (cq >> 1) * mq + (cq & 1) * nq * ldc + i0 +
+                             j0 * ldc);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t col = j0 + ec + 4 * e;
-          const bool ok = e_row_ok && col < nq && cb * nq + col < args.n;
-          const uint32_t so = (uint32_t)(8 * 4 * e * ldc);
-          const bool read_c = !(first_outer && args.beta == 0.0);
-          d2_t c = __builtin_bit_cast(
-              d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (ok && read_c) ? e_off : kOOB, so, 0));
-          bool first = first_outer;
+          for (int e = 0; e < 4; ++e) {
+            const int64_t col = j0 + ec + 4 * e;
+            const bool ok = e_row_ok && col < nq && cb * nq + col < args.n;
+            off[cq][e] = ok ? e_off + (uint32_t)(8 * 4 * e * ldc) : kOOB;
+            if constexpr (CASE == 1)
+              c[cq][e] = (d2_t){0.0, 0.0};
+            else
+              c[cq][e] = __builtin_bit_cast(
+                  d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs[cq], off[cq][e], 0, 0));
+          }
+        }
 #pragma unroll
-          for (int r = 0; r < 7; ++r) {
-            const int nc = SCHEME == 1 ? kWinograd[r].nc : kOneLevel[r].nc;
+        for (int cq = 0; cq < 4; ++cq)
 #pragma unroll
-            for (int dd = 0; dd < 4; ++dd) {
-              const QTerm t = SCHEME == 1 ? kWinograd[r].c[dd] : kOneLevel[r].c[dd < 2 ? dd : 0];
-              if (dd < nc && t.q == cq) {
-                const double ag = t.sign > 0 ? ag_outer : -ag_outer;
-                c.x = c_update(c.x, acc[r][0][e], ag, args.beta, first);
-                c.y = c_update(c.y, acc[r][1][e], ag, args.beta, first);
-                first = false;
+          for (int e = 0; e < 4; ++e) {
+            d2_t v = c[cq][e];
+            bool first = true;
+#pragma unroll
+            for (int r = 0; r < 7; ++r) {
+              const int nc = SCHEME == 1 ? kWinograd[r].nc : kOneLevel[r].nc;
+#pragma unroll
+              for (int dd = 0; dd < 4; ++dd) {
+                const QTerm t = SCHEME == 1 ? kWinograd[r].c[dd] : kOneLevel[r].c[dd < 2 ? dd : 0];
+                if (dd < nc && t.q == cq) {
+                  const double ag = t.sign > 0 ? ag_outer : -ag_outer;
+                  if (first) {
+                    v.x = c_update_case<CASE>(v.x, acc[r][0][e], ag, args.beta);
+                    v.y = c_update_case<CASE>(v.y, acc[r][1][e], ag, args.beta);
+                  } else {
+                    v.x = c_update_case<0>(v.x, acc[r][0][e], ag, args.beta);
+                    v.y = c_update_case<0>(v.y, acc[r][1][e], ag, args.beta);
+                  }
+                  first = false;
+                }
               }
             }
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v), rs[cq],
+                                                   off[cq][e], 0, 0);
           }
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, c), rs, ok ? e_off : kOOB,
-                                                 so, 0);
-        }
-      }
+      };
+      if (!first_outer) update(std::integral_constant<int, 0>{});
+      else if (args.beta == 0.0) update(std::integral_constant<int, 1>{});
+      else update(std::integral_constant<int, 2>{});
     }
   }
 };

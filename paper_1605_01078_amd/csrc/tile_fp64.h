@@ -33,13 +33,24 @@ __device__ __forceinline__ int code_row(uint8_t c) { return c & 7; }
 __device__ __forceinline__ int code_col(uint8_t c) { return (c >> 3) & 7; }
 __device__ __forceinline__ bool code_neg(uint8_t c) { return (c & 0x80) != 0; }
 
-// One C update.  Every variant goes through this function in the same product order, so
-// ABC, AB and Naive give bitwise identical results for the same table.
+// One C update, its case fixed at compile time: 0, a later update of the element
+// (c + ag*mv); 1, its first update with beta == 0 (C is not read); 2, its first update with
+// beta != 0.  Epilogues that know the case for a whole destination pick it once, outside their
+// loops.
+template <int CASE>
+__device__ __forceinline__ double c_update_case(double c, double mv, double ag, double beta) {
+  if constexpr (CASE == 0) return __builtin_fma(ag, mv, c);
+  else if constexpr (CASE == 1) return ag * mv;
+  else return __builtin_fma(ag, mv, beta * c);
+}
+
+// One C update.  Every variant goes through this function (or its cases above) in the same
+// product order, so ABC, AB and Naive give bitwise identical results for the same table.
 __device__ __forceinline__ double c_update(double c, double mv, double ag, double beta,
                                            bool first) {
-  if (!first) return __builtin_fma(ag, mv, c);
-  if (beta == 0.0) return ag * mv;
-  return __builtin_fma(ag, mv, beta * c);
+  if (!first) return c_update_case<0>(c, mv, ag, beta);
+  if (beta == 0.0) return c_update_case<1>(c, mv, ag, beta);
+  return c_update_case<2>(c, mv, ag, beta);
 }
 
 // Signed operand sums.  A pair of terms c0*x0 + c1*x1 (c = +-1) is rounded once as
