@@ -324,11 +324,15 @@ struct Bf16Gemm {
     };
     // Epilogue of product r: lane l, element e of block (fm, fn) is tile row
     // WTM wm + 16 fm + 4 (l / 16) + e, column WTN wn + 16 fn + l % 16.  Its byte offset is the
-    // lane's base (row WTM wm + 4 (l / 16), column WTN wn + l % 16) plus 8 (16 fm + e), an
-    // instruction immediate, plus 128 fn ldc, a scalar, so no per-element offset stays live.
-    // Where the workgroup's block of this destination lies wholly inside C and its row pairs
-    // are 16-byte aligned (vec_c), rows e = 0, 1 and 2, 3 move as 16-byte pairs; else element
-    // by element, masked.
+    // lane's base (row WTM wm + 4 (l / 16), column WTN wn + l % 16) plus 8 (16 fm + e) plus
+    // 128 fn ldc, all in the lane offset (below 2^31 bytes as 8 * 128 * ldc < 2^31).  Where the
+    // workgroup's block of this destination lies wholly inside C and its row pairs are 16-byte
+    // aligned (vec_c), rows e = 0, 1 and 2, 3 move as 16-byte pairs; else element by element,
+    // masked.  Each 16-row block's loads are issued before its first store: the vector memory
+    // counter counts loads and stores in one queue, so a store between two loads would make
+    // the wait for the second load cover the store too.  No access carries a scalar offset
+    // register: the compiler inserts the wait state that a 16-byte store needs before its data
+    // registers are rewritten only for stores without one.
     const uint32_t e_base = (uint32_t)(8 * (wm * WTM + 4 * g + (int64_t)(wn * WTN + li) * args.ldc));
     auto epilogue = [&](int r) {
       const ProdDesc& pd = tab.prod[r];
@@ -346,41 +350,52 @@ struct Bf16Gemm {
         if (args.vec_c && rlim >= BM && clim >= BN) {
 #pragma unroll
           for (int fm = 0; fm < NFM; ++fm) {
+            uint32_t off[NFN][2];
+            d2_t c[NFN][2];
 #pragma unroll
-            for (int fn = 0; fn < NFN; ++fn) {
-              const uint32_t so = (uint32_t)(128 * fn * ldc);
+            for (int fn = 0; fn < NFN; ++fn)
 #pragma unroll
-              for (int e = 0; e < 4; e += 2) {
-                const uint32_t off = e_base + 8 * (16 * fm + e);
-                d2_t c = {0.0, 0.0};
-                if (read_c)
-                  c = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, so, 0));
-                c.x = update(c.x, acc[fm][fn][e], ag, first);
-                c.y = update(c.y, acc[fm][fn][e + 1], ag, first);
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, c), rs, off, so, 0);
+              for (int h = 0; h < 2; ++h) {
+                off[fn][h] = e_base + 8 * (16 * fm + 2 * h) + (uint32_t)(128 * fn * ldc);
+                c[fn][h] = __builtin_bit_cast(
+                    d2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, read_c ? off[fn][h] : kOOB, 0, 0));
               }
-            }
+#pragma unroll
+            for (int fn = 0; fn < NFN; ++fn)
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                d2_t v;
+                v.x = update(c[fn][h].x, acc[fm][fn][2 * h], ag, first);
+                v.y = update(c[fn][h].y, acc[fm][fn][2 * h + 1], ag, first);
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v), rs, off[fn][h], 0, 0);
+              }
             __builtin_amdgcn_sched_barrier(0);   // keep the C traffic of one row block together
           }
           continue;
         }
 #pragma unroll
         for (int fm = 0; fm < NFM; ++fm) {
+          uint32_t off[NFN][4];
+          double c[NFN][4];
 #pragma unroll
           for (int fn = 0; fn < NFN; ++fn) {
-            const uint32_t so = (uint32_t)(128 * fn * ldc);
             const bool col_ok = wn * WTN + 16 * fn + li < clim;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const bool ok = col_ok && wm * WTM + 16 * fm + 4 * g + e < rlim;
-              const uint32_t off = e_base + 8 * (16 * fm + e);
-              const double c = __builtin_bit_cast(
-                  double, __builtin_amdgcn_raw_buffer_load_b64(rs, (ok && read_c) ? off : kOOB, so, 0));
-              const double out = update(c, acc[fm][fn][e], ag, first);
-              __builtin_amdgcn_raw_buffer_store_b64(as_u2(out), rs, ok ? off : kOOB, so, 0);
+              off[fn][e] = ok ? e_base + 8 * (16 * fm + e) + (uint32_t)(128 * fn * ldc) : kOOB;
+              c[fn][e] = __builtin_bit_cast(
+                  double, __builtin_amdgcn_raw_buffer_load_b64(rs, read_c ? off[fn][e] : kOOB, 0, 0));
             }
-            __builtin_amdgcn_sched_barrier(0);
           }
+#pragma unroll
+          for (int fn = 0; fn < NFN; ++fn)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const double out = update(c[fn][e], acc[fm][fn][e], ag, first);
+              __builtin_amdgcn_raw_buffer_store_b64(as_u2(out), rs, off[fn][e], 0, 0);
+            }
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     };
