@@ -39,6 +39,19 @@ def test_integer_bit_exact(shape):
     assert np.array_equal(run(A, B, C, 1.0, 1.0), oracle_dgemm(A, B, C.copy(order="F"), 1.0, 1.0))
 
 
+@pytest.mark.parametrize("shape", [(2048, 2048, 2048), (1024, 1000, 1040)])
+def test_integer_bit_exact_beta_zero(shape):
+    """beta = 0: each C block's first update (in the launch that first reaches it) writes
+    alpha*M without reading C, while the same launch adds to other blocks that earlier launches
+    wrote, and later launches add to it."""
+    m, n, k = shape
+    print(f"case L=3 integer beta0 {shape}", flush=True)
+    A, B, C = W.problem(113, m, n, k, "integer")
+    C[:] = np.nan
+    got = run(A, B, C, -1.0, 0.0)
+    assert np.array_equal(got, oracle_dgemm(A, B, np.zeros_like(C, order="F"), -1.0, 0.0))
+
+
 @pytest.mark.parametrize("case", [(512, 512, 512, 1, 3, 1, 0), (640, 640, 640, 0, 0, 0, 1)])
 def test_integer_odd_ld_and_misaligned(case):
     m, n, k, ea, eb, ec, off = case
