@@ -124,9 +124,13 @@ __global__ __launch_bounds__(256) void lu_base_kernel(double* P, int64_t ld, int
 }
 
 // X (rows x w) := X U^{-1} with U upper triangular w x w (w <= 64; unit: ones on the diagonal,
-// not read).  Each row of X is solved right-looking: for p = 0, 1, ...: x_p := x_p / u_pp, then
-// every later x_j is reduced by x_p u_pj.  Each x_j thus receives its products in increasing p
-// and is divided last, the order of x_j = (b_j - sum_{p<j} x_p u_pj) / u_jj summed term by term.
+// not read).  Each row of X is solved right-looking: for p = 0, 1, ...: x_p := x_p * (1 / u_pp),
+// then every later x_j is reduced by x_p u_pj.  Each x_j thus receives its products in increasing
+// p and is scaled last, the order of x_j = (b_j - sum_{p<j} x_p u_pj) / u_jj summed term by term,
+// with the division done as LAPACK's unblocked factorizations do it: by the rounded reciprocal
+// of the diagonal (the same value as the quotient where u_jj is a power of two).  The 64
+// reciprocals are formed once, in parallel, before the solve, so the chain of dependent
+// operations from one step to the next holds a multiplication where a division would stand.
 // Element (r, j) of X is at B + r * xr + j * xc and u_pj at U + p * ur + j * uc, so the same
 // kernel solves B := B U^{-1} (xr = 1, xc = ldb), B := B L^{-T} (U = L^T: ur = ldl, uc = 1) and,
 // on the transposed view, B := L^{-1} B for a unit lower L (U = L^T; X = B^T: xr = ldb, xc = 1).
@@ -146,6 +150,7 @@ __global__ __launch_bounds__(256) void trsm_rows_upper_kernel(const double* U, i
   constexpr int kPer = kLuB / 4;  // columns per lane
   __shared__ double u[kLuB * kS];
   __shared__ double xs[kLuB * kX];
+  __shared__ double uinv[kLuB];   // 1 / u_pp
   const int tid = threadIdx.x;
   const bool col_major_u = ur == 1;
   const bool rows_contiguous = xc == 1 && xr != 1;   // X^T is column-major
@@ -175,14 +180,16 @@ __global__ __launch_bounds__(256) void trsm_rows_upper_kernel(const double* U, i
     }
   }
   __syncthreads();
+  if (tid < kLuB) uinv[tid] = 1.0 / u[tid * kS + tid];
+  __syncthreads();
   const int row = tid >> 2, q = tid & 3;
   const double* uq = u + q;   // lane q reads columns 4k + q of U
   double x[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) x[k] = xs[row * kX + 4 * k + q];
-  // U entries of one step: the pivot u_pp, then u_{p, 4k+q} for k = p / 4 .. 15
+  // U entries of one step: 1 / u_pp, then u_{p, 4k+q} for k = p / 4 .. 15
   double cur[kPer + 1];
-  cur[0] = u[0];
+  cur[0] = uinv[0];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) cur[1 + k] = uq[4 * k];
   static_for<0, kLuB>([&](auto step) {
@@ -191,11 +198,11 @@ __global__ __launch_bounds__(256) void trsm_rows_upper_kernel(const double* U, i
     __builtin_amdgcn_sched_barrier(0);
     if (p + 1 < kLuB) {
       constexpr int pn = p + 1, kn = pn / 4;
-      nxt[0] = u[pn * kS + pn];
+      nxt[0] = uinv[pn];
 #pragma unroll
       for (int k = kn; k < kPer; ++k) nxt[1 + k - kn] = uq[pn * kS + 4 * k];
     }
-    const double piv = x[k0] / cur[0];        // meaningful on lane q0 of each group
+    const double piv = x[k0] * cur[0];        // meaningful on lane q0 of each group
     const double xp = quad_bcast<q0>(piv);    // x_p, final
     if (q == q0) x[k0] = xp;
     if (q > q0) {
