@@ -361,8 +361,9 @@ struct AllProducts {
     const int ec = 16 * wn + (lane >> 4);       // tile column of element 0
     const bool e_row_ok = i0 + er < mq;
     if (STORE_M) {
-      // ---- epilogue (AB): the seven products to their temporaries (8-byte stores through
-      // as_u2: a 16-byte store of a pair built from accumulator elements stored wrong values) ----
+      // ---- epilogue (AB): the seven products to their temporaries, a row pair per 16-byte
+      // store with the whole offset in the lane offset (scalar offset 0: the compiler inserts
+      // the wait state before the pair's registers are rewritten only for such stores) ----
       const int64_t ldm = args.ldm;
       const uint32_t m_off = (uint32_t)(8 * (er + (int64_t)ec * ldm));
 #pragma unroll
@@ -372,9 +373,12 @@ struct AllProducts {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const bool ok = e_row_ok && j0 + ec + 4 * e < nq;
-          const uint32_t so = (uint32_t)(8 * 4 * e * ldm);
-          __builtin_amdgcn_raw_buffer_store_b64(as_u2(acc[r][0][e]), rs, ok ? m_off : kOOB, so, 0);
-          __builtin_amdgcn_raw_buffer_store_b64(as_u2(acc[r][1][e]), rs, ok ? m_off + 8 : kOOB, so, 0);
+          d2_t v;
+          v.x = acc[r][0][e];
+          v.y = acc[r][1][e];
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, v), rs,
+                                                 ok ? m_off + (uint32_t)(8 * 4 * e * ldm) : kOOB,
+                                                 0, 0);
         }
       }
       return;
